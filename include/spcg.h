@@ -1,0 +1,161 @@
+/*
+ * spcg.h -- C ABI of the MI355X (gfx950) CSR SpMV / conjugate-gradient library.
+ *
+ * The operations follow the data-parallel kernels of Weinberg, "Data-parallel
+ * programming with Intel Array Building Blocks" (arXiv 1211.1581):
+ *   - CSR storage in three arrays and the row-wise product y = A x (Sec. 3.2);
+ *   - the conjugate-gradient solver for SPD systems (Sec. 3.4, Fig. 6 and the
+ *     loop that follows it: one SpMV, two inner products, three vector updates
+ *     per pass).
+ * Beyond the paper: Jacobi and learned (M^-1 = G G^T) preconditioning, and an
+ * FP32-inner / FP64-outer mixed-precision solver.
+ *
+ * Conventions for every call:
+ *   - Pointers prefixed d_ are device pointers (HBM of the current device),
+ *     h_ are host pointers.  The caller owns all of them; the library never
+ *     frees caller memory and never calls hipMalloc on a solve path (the
+ *     matrix handle allocates its analysis arrays once, in spcg_csr_create).
+ *   - Indices are int32, CSR column indices are 0-based, rows ascend.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Calls
+ *     marked "asynchronous" only enqueue work on it.
+ *   - Return value: an SPCG_* status code.  No exception crosses the ABI.
+ *   - A handle may be used from one stream at a time.
+ */
+#ifndef SPCG_H
+#define SPCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ----------------------------------------------------------- status codes */
+#define SPCG_OK 0
+#define SPCG_NOT_CONVERGED 1 /* x valid, maxit reached */
+#define SPCG_FELL_BACK 2     /* learned form missed its budget or broke down; Jacobi-PCG finished */
+#define SPCG_INVALID_ARG (-1)
+#define SPCG_INVALID_CSR (-2)
+#define SPCG_HIP_ERROR (-3)
+#define SPCG_NOT_SPD (-4)     /* p.Ap <= 0, r.z <= 0 or a non-positive diagonal */
+#define SPCG_NON_FINITE (-5)  /* NaN/Inf in the input or in a residual */
+
+/* value types */
+#define SPCG_F64 0
+#define SPCG_F32 1
+
+/* preconditioners and precisions of cg_solve */
+#define SPCG_PRECOND_NONE 0
+#define SPCG_PRECOND_JACOBI 1
+#define SPCG_PRECOND_LEARNED 2
+#define SPCG_PREC_F64 0
+#define SPCG_PREC_MIXED 1
+
+typedef struct spcg_csr *spcg_csr_t;
+
+/* Human-readable name of a status code (static string). */
+const char *spcg_status_str(int status);
+
+/* Text of the last HIP error seen by the library on this thread ("" if none). */
+const char *spcg_last_error(void);
+
+/*
+ * Create a matrix handle (Sec. 3.2: values, column of each value, position of
+ * each row's first value; here with n_rows + 1 entries so the last row's end
+ * is explicit).
+ *   n_rows, n_cols  >= 0;   nnz = d_row_ptr[n_rows] < 2^31
+ *   d_row_ptr int32[n_rows+1], d_col int32[nnz], d_vals (F64: double[nnz],
+ *   F32: float[nnz]); all borrowed: they must stay alive and unchanged until
+ *   spcg_csr_destroy.  Columns need not be sorted; duplicates are summed.
+ * The structure is validated on the device (row_ptr[0] = 0, non-decreasing,
+ * row_ptr[n] = nnz, 0 <= col < n_cols) -> SPCG_INVALID_CSR.  Then the row
+ * analysis runs: a partition of the rows into blocks of bounded work and the
+ * position of each row's diagonal.  Synchronous: returns after `stream` has
+ * finished the analysis.  The handle owns its analysis arrays (device memory).
+ */
+int spcg_csr_create(spcg_csr_t *out, int32_t n_rows, int32_t n_cols, int64_t nnz,
+                    const int32_t *d_row_ptr, const int32_t *d_col, const void *d_vals,
+                    int32_t dtype, hipStream_t stream);
+
+/* Release a handle's analysis arrays (synchronises the device first). */
+int spcg_csr_destroy(spcg_csr_t A);
+
+/* Analysis summary: row blocks, blocks ending in a long row, longest row. */
+int spcg_csr_info(spcg_csr_t A, int64_t *n_blocks, int64_t *n_long_rows, int64_t *max_row_len);
+
+/*
+ * y = A x (Sec. 3.2): y_i = sum over the entries k of row i of vals[k] * x[col[k]],
+ * for all n_rows rows, overwriting y (an empty row gives 0).  x: n_cols
+ * elements, y: n_rows elements, both of the handle's dtype; FP32 matrices
+ * accumulate in FP32.  x and y must not overlap.  Asynchronous.  The sum
+ * order inside a row is fixed by the analysis, so repeated calls give
+ * bitwise-identical y.
+ */
+int spmv_csr(spcg_csr_t A, const void *d_x, void *d_y, hipStream_t stream);
+
+/*
+ * Deterministic inner product *d_out = sum_i a_i b_i (FP64), the reduction
+ * the CG loop uses (Sec. 3.4: two reductions per pass).  Fixed-order blocked
+ * summation; d_work: spcg_dot_workspace_bytes(n) bytes.  Asynchronous.
+ */
+size_t spcg_dot_workspace_bytes(int64_t n);
+int spcg_dot(int64_t n, const double *d_a, const double *d_b, double *d_out, void *d_work,
+             hipStream_t stream);
+
+typedef struct {
+    double tol;          /* stop when ||r_k||_2 <= tol ||b||_2 (default 1e-10) */
+    int32_t maxit;       /* cap on passes (products A p), >= 0 */
+    int32_t precond;     /* SPCG_PRECOND_* */
+    int32_t precision;   /* SPCG_PREC_F64 or SPCG_PREC_MIXED (Jacobi inner) */
+    int32_t check_every; /* passes enqueued between host checks of the device flag; 0 = adaptive */
+    double delta;        /* mixed: FP64 residual replacement when ||r32|| < delta * ||r at last replacement|| */
+    spcg_csr_t G;        /* learned: lower-triangular factor (pattern of tril(A)), F32 values */
+    spcg_csr_t GT;       /* learned: its transpose (pattern of triu(A)), F32 values */
+    int32_t budget;      /* learned: passes allowed before the Jacobi fallback */
+    int32_t small_path;  /* 1 = allow the single-workgroup solver for small n, 0 = never */
+} spcg_cg_opts;
+
+typedef struct {
+    int32_t iters;          /* passes of the (first) solver: products A p */
+    int32_t iters_fallback; /* passes of the Jacobi fallback (learned form) */
+    int32_t n_updates;      /* mixed: FP64 residual replacements */
+    int32_t n_restarts;     /* true-residual restarts */
+    double true_relres;     /* ||b - A x||_2 / ||b||_2 recomputed in FP64 at exit */
+} spcg_cg_result;
+
+/* Fill opts with defaults: tol 1e-10, maxit 20000, Jacobi, FP64, adaptive checks, delta 0.1. */
+void spcg_cg_default_opts(spcg_cg_opts *opts);
+
+/* Bytes of device workspace cg_solve needs for A and opts (256-byte aligned pointer). */
+size_t spcg_cg_workspace_bytes(spcg_csr_t A, const spcg_cg_opts *opts);
+
+/*
+ * Solve A x = b for SPD A by preconditioned conjugate gradients (Sec. 3.4):
+ *   r0 = b - A x0, z = M^-1 r, p = z;  per pass: q = A p, alpha = (r.z)/(p.q),
+ *   x += alpha p, r -= alpha q, z = M^-1 r, beta = (r'.z')/(r.z), p = z + beta p;
+ *   stop when ||r|| <= tol ||b|| or after maxit passes.  On exit the residual
+ *   is recomputed in FP64; a gap above tol restarts from it (within maxit).
+ * A: F64 handle.  d_b double[n], d_x double[n] (in: x0, out: x).
+ * d_work: spcg_cg_workspace_bytes(A, opts) bytes, 256-byte aligned.
+ * h_hist: NULL or host double[maxit + 1] receiving ||r_k|| / ||b|| for
+ *   k = 0..iters (FP32 estimates between replacements for the mixed form).
+ * res: filled on every return that is not INVALID_ARG.
+ * ||b|| = 0 gives x = 0 and zero passes.  Synchronous (returns after the
+ * final check); the loop itself keeps its scalars on the device and the host
+ * reads one status word every check_every passes.
+ * Mixed precision: FP32 values, vectors and reductions inside, FP64 only for
+ * r = b - A x, x += d and the final check.  Learned: M^-1 = G G^T for at most
+ * `budget` passes, then (or on breakdown) Jacobi-PCG from the current x and
+ * status SPCG_FELL_BACK.
+ */
+int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *opts,
+             void *d_work, size_t work_bytes, spcg_cg_result *res, double *h_hist,
+             hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPCG_H */

@@ -1,0 +1,963 @@
+// cg.hip -- preconditioned conjugate gradients on the device (arXiv 1211.1581,
+// Sec. 3.4: per pass one SpMV, two inner products and three vector updates).
+//
+// Schedule of one pass (FP64 Jacobi-PCG; the scalars never leave the device):
+//   K1  q = A p            SpMV with p.q folded into the row epilogue;
+//                          the last workgroup forms sigma and alpha = rho/sigma
+//   K2  x += alpha p, r -= alpha q, z = D^-1 r   (z not stored)
+//                          partials r.z and r.r; the last workgroup forms
+//                          beta, the history entry and the stop decision
+//   K3  p = D^-1 r + beta p
+// Every kernel carries the pass number it belongs to and does nothing unless
+// the device state is at that pass and running, so the host can enqueue a
+// batch of passes and read one status word per batch.
+//
+// Mixed precision: the same kernels in FP32 on fl32(A) with FP32 vectors and
+// reductions; when ||r32|| falls below delta * ||r at the last replacement||
+// (or below tol ||b||, or at maxit) the state halts with "replace": x64 += x32,
+// r64 = b - A x64 in FP64, r32 = fl32(r64), rho recomputed, p kept.
+//
+// Learned: M^-1 = G G^T with G lower-triangular (FP32 values, FP64 vectors):
+// t = G^T r and z = G t are two SpMV-shaped launches on the handles of G^T
+// and G, with r.z folded into the second one.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+
+namespace spcg {
+
+enum Halt : int {
+    RUN = 0,
+    H_CONV = 1,     // recursive residual below tol ||b||
+    H_MAXIT = 2,
+    H_BREAK = 3,    // breakdown; status holds NOT_SPD / NON_FINITE
+    H_REPLACE = 4,  // mixed: FP64 residual replacement due
+    H_BUDGET = 5,   // learned: pass budget used up
+    H_ZERO = 6,     // ||b|| = 0
+};
+
+struct CgState {
+    double rho, alpha, beta, rr, nb, thresh, rlast, delta, true_rr, r2_64;
+    float rho32, alpha32, beta32, rr32;
+    int k, maxit, halt, status, budget, n_updates, bad_diag, pad;
+};
+
+constexpr int kVecPer = 4;
+constexpr int kVecBlock = kBlock * kVecPer;
+constexpr int kSmallThreads = 1024;
+
+inline int64_t vec_blocks(int64_t n) { return (n + kVecBlock - 1) / kVecBlock; }
+
+template <typename T> __device__ __forceinline__ T st_alpha(const CgState *s);
+template <> __device__ __forceinline__ double st_alpha<double>(const CgState *s) { return s->alpha; }
+template <> __device__ __forceinline__ float st_alpha<float>(const CgState *s) { return s->alpha32; }
+template <typename T> __device__ __forceinline__ T st_beta(const CgState *s);
+template <> __device__ __forceinline__ double st_beta<double>(const CgState *s) { return s->beta; }
+template <> __device__ __forceinline__ float st_beta<float>(const CgState *s) { return s->beta32; }
+
+__device__ __forceinline__ bool finite_d(double v) { return isfinite(v); }
+
+__device__ __forceinline__ void set_break(CgState *s, double v) {
+    s->status = finite_d(v) ? SPCG_NOT_SPD : SPCG_NON_FINITE;
+    s->halt = H_BREAK;
+}
+
+// ------------------------------------------------------------- set-up --
+
+__global__ void k_init_state(CgState *st, unsigned *cnt_d, int ncnt_d, unsigned *cnt_f, int ncnt_f,
+                             int maxit, double delta, int budget) {
+    for (int i = threadIdx.x; i < ncnt_d; i += blockDim.x) cnt_d[i] = 0u;
+    for (int i = threadIdx.x; i < ncnt_f; i += blockDim.x) cnt_f[i] = 0u;
+    if (threadIdx.x == 0) {
+        CgState s;
+        memset(&s, 0, sizeof s);
+        s.maxit = maxit;
+        s.delta = delta;
+        s.budget = budget;
+        *st = s;
+    }
+}
+
+// state fields for a new phase (restart / fallback): keep nb, thresh, k
+__global__ void k_phase_state(CgState *st, int maxit, int budget) {
+    if (threadIdx.x == 0) {
+        st->maxit = maxit;
+        st->budget = budget;
+        st->halt = RUN;
+        st->status = SPCG_OK;
+    }
+}
+
+// dinv_i = 1 / (sum of row i's diagonal entries); dinv32 = fl32(dinv)
+__global__ void __launch_bounds__(kBlock)
+k_diag_inv(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+           const double *__restrict__ vals, double *__restrict__ dinv, float *__restrict__ dinv32,
+           CgState *st) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double d = 0.0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k)
+        if (col[k] == i) d += vals[k];
+    if (!(d > 0.0)) atomicOr(&st->bad_diag, isfinite(d) ? 1 : 2);
+    const double v = 1.0 / d;
+    dinv[i] = v;
+    if (dinv32) dinv32[i] = (float)v;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_to_f32(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = (float)a[i];
+}
+
+template <typename T>
+__global__ void k_fill(int64_t n, T *p, T v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_copy(int64_t n, const double *__restrict__ a, double *__restrict__ b) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = a[i];
+}
+
+// ------------------------------------------- residual r = b - A x (FP64) --
+
+enum ResidMode : int { R_INIT = 0, R_TRUE = 1, R_REPLACE = 2 };
+
+struct EpiResid {
+    const double *__restrict__ b;
+    double *__restrict__ r;
+    float *__restrict__ r32;
+    double bb, rr;
+    __device__ __forceinline__ void row(int i, double s) {
+        const double bi = b[i];
+        const double ri = bi - s;
+        r[i] = ri;
+        if (r32) r32[i] = (float)ri;
+        bb += bi * bi;
+        rr += ri * ri;
+    }
+};
+
+// Every row belongs to exactly one row block, so r is fully written.
+__global__ void __launch_bounds__(kBlock)
+k_resid(CsrDev A, const double *__restrict__ vals, const double *__restrict__ x,
+        const double *__restrict__ b, double *__restrict__ r, float *__restrict__ r32, CgState *st,
+        Reduce<double> R, double *hist, int mode, double tol) {
+    __shared__ SpmvSmem<double> sm;
+    if (mode == R_REPLACE && st->halt != H_REPLACE) return;
+    const int blk = xcd_remap(blockIdx.x, A.n_blocks);
+    EpiResid epi{b, r, r32, 0.0, 0.0};
+    spmv_block<double, double, double>(A, vals, x, blk, sm, epi);
+    const double v[2] = {block_sum(epi.bb, sm.red), block_sum(epi.rr, sm.red)};
+    auto fin = [&](double(&t)[2]) {
+        if (mode == R_INIT) {
+            st->nb = sqrt(t[0]);
+            st->thresh = tol * st->nb;
+            st->rr = t[1];
+            st->rlast = sqrt(t[1]);
+            if (!(t[0] > 0.0)) {
+                if (finite_d(t[0])) st->halt = H_ZERO;
+                else set_break(st, t[0]);
+            } else if (!finite_d(t[1])) {
+                set_break(st, t[1]);
+            }
+        } else if (mode == R_TRUE) {
+            st->true_rr = t[1];
+        } else {
+            st->rlast = sqrt(t[1]);
+            st->r2_64 = t[1];
+            st->n_updates += 1;
+            hist[st->k] = st->rlast / st->nb;
+        }
+    };
+    reduce_arrive<2>(v, blk, A.n_blocks, R, fin);
+}
+
+// z = M^-1 r, p = z, rho = r.z  (start of a phase; r and rr are set)
+template <int PRE>
+__global__ void __launch_bounds__(kBlock)
+k_start(int n, const double *__restrict__ r, const double *__restrict__ dinv,
+        const double *__restrict__ zin, double *__restrict__ p, CgState *st, Reduce<double> R,
+        double *hist) {
+    __shared__ double red[4];
+    if (st->halt != RUN) return;
+    double rz = 0.0, rr = 0.0;
+    const int base = blockIdx.x * kVecBlock + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < kVecPer; ++u) {
+        const int i = base + u * kBlock;
+        if (i < n) {
+            const double ri = r[i];
+            const double zi = PRE == SPCG_PRECOND_JACOBI ? dinv[i] * ri
+                              : PRE == SPCG_PRECOND_NONE ? ri
+                                                         : zin[i];
+            p[i] = zi;
+            rz += ri * zi;
+            rr += ri * ri;
+        }
+    }
+    const double v[2] = {block_sum(rz, red), block_sum(rr, red)};
+    auto fin = [&](double(&t)[2]) {
+        st->rho = t[0];
+        st->rr = t[1];
+        hist[st->k] = sqrt(t[1]) / st->nb;
+        if (!finite_d(t[0]) || !finite_d(t[1])) set_break(st, NAN);
+        else if (sqrt(t[1]) <= st->thresh) st->halt = H_CONV;
+        else if (!(t[0] > 0.0)) set_break(st, t[0]);
+        else if (st->k >= st->maxit) st->halt = H_MAXIT;
+    };
+    reduce_arrive<2>(v, blockIdx.x, gridDim.x, R, fin);
+}
+
+// ------------------------------------------------------ one CG pass --
+
+template <typename T>
+struct EpiPQ {
+    T *__restrict__ q;
+    const T *__restrict__ p;
+    T acc;
+    __device__ __forceinline__ void row(int i, T s) {
+        q[i] = s;
+        acc += p[i] * s;
+    }
+};
+
+// K1: q = A p, sigma = p.q, alpha = rho / sigma
+template <typename TV, typename T>
+__global__ void __launch_bounds__(kBlock)
+k_cg_q(CsrDev A, const TV *__restrict__ vals, const T *__restrict__ p, T *__restrict__ q,
+       CgState *st, Reduce<T> R, int expect) {
+    __shared__ SpmvSmem<T> sm;
+    if (st->halt != RUN || st->k != expect) return;
+    const int blk = xcd_remap(blockIdx.x, A.n_blocks);
+    EpiPQ<T> epi{q, p, T(0)};
+    spmv_block<TV, T, T>(A, vals, p, blk, sm, epi);
+    const T v[1] = {block_sum(epi.acc, sm.red)};
+    auto fin = [&](T(&t)[1]) {
+        const T sigma = t[0];
+        if (!(sigma > T(0)) || !finite_d((double)sigma)) {
+            set_break(st, (double)sigma);
+        } else if constexpr (sizeof(T) == 8) {
+            st->alpha = st->rho / sigma;
+        } else {
+            st->alpha32 = st->rho32 / sigma;
+        }
+    };
+    reduce_arrive<1>(v, blk, A.n_blocks, R, fin);
+}
+
+// K2: x += alpha p, r -= alpha q, z = M^-1 r; partials (r.z, r.r).
+// PRE = LEARNED: only r.r here (z comes from two SpMVs).  MIXED = FP32 inner.
+template <typename T, int PRE, bool MIXED>
+__global__ void __launch_bounds__(kBlock)
+k_cg_xr(int n, int expect, T *__restrict__ x, T *__restrict__ r, const T *__restrict__ p,
+        const T *__restrict__ q, const T *__restrict__ dinv, CgState *st, Reduce<T> R,
+        double *hist) {
+    __shared__ T red[4];
+    if (st->halt != RUN || st->k != expect) return;
+    const T alpha = st_alpha<T>(st);
+    T rz = T(0), rr = T(0);
+    const int base = blockIdx.x * kVecBlock + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < kVecPer; ++u) {
+        const int i = base + u * kBlock;
+        if (i < n) {
+            x[i] += alpha * p[i];
+            const T ri = r[i] - alpha * q[i];
+            r[i] = ri;
+            if constexpr (PRE == SPCG_PRECOND_JACOBI) rz += ri * (dinv[i] * ri);
+            rr += ri * ri;
+        }
+    }
+    if constexpr (PRE == SPCG_PRECOND_NONE) rz = rr;
+    const T v[2] = {block_sum(rz, red), block_sum(rr, red)};
+    auto fin = [&](T(&t)[2]) {
+        const int k = expect + 1;
+        st->k = k;
+        const double rrd = (double)t[1];
+        const double est = sqrt(rrd);
+        hist[k] = est / st->nb;
+        if (!finite_d((double)t[0]) || !finite_d(rrd)) {
+            set_break(st, NAN);
+            return;
+        }
+        if constexpr (PRE != SPCG_PRECOND_LEARNED) {
+            if (rrd > 0.0 && !(t[0] > T(0))) {
+                set_break(st, (double)t[0]);
+                return;
+            }
+        }
+        if constexpr (MIXED) {
+            st->beta32 = t[0] / st->rho32;
+            st->rho32 = t[0];
+            st->rr32 = t[1];
+            if (est < st->delta * st->rlast || est <= st->thresh || k >= st->maxit)
+                st->halt = H_REPLACE;
+        } else {
+            st->rr = rrd;
+            if constexpr (PRE != SPCG_PRECOND_LEARNED) {
+                st->beta = (double)t[0] / st->rho;
+                st->rho = (double)t[0];
+            }
+            if (est <= st->thresh) st->halt = H_CONV;
+            else if (k >= st->maxit) st->halt = H_MAXIT;
+            else if (PRE == SPCG_PRECOND_LEARNED && k >= st->budget) st->halt = H_BUDGET;
+        }
+    };
+    reduce_arrive<2>(v, blockIdx.x, gridDim.x, R, fin);
+}
+
+// K3: p = z + beta p  (z = D^-1 r, r, or the stored z)
+template <typename T, int PRE>
+__global__ void __launch_bounds__(kBlock)
+k_cg_p(int n, int expect, const T *__restrict__ r, const T *__restrict__ dinv,
+       const T *__restrict__ z, T *__restrict__ p, const CgState *st) {
+    const int h = st->halt;
+    if (st->k != expect + 1 || (h != RUN && h != H_REPLACE)) return;
+    const T beta = st_beta<T>(st);
+    const int base = blockIdx.x * kVecBlock + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < kVecPer; ++u) {
+        const int i = base + u * kBlock;
+        if (i < n) {
+            const T zi = PRE == SPCG_PRECOND_JACOBI ? dinv[i] * r[i]
+                         : PRE == SPCG_PRECOND_NONE ? r[i]
+                                                    : z[i];
+            p[i] = zi + beta * p[i];
+        }
+    }
+}
+
+// ------------------------------------------- learned: z = G (G^T r) --
+
+template <typename TV, typename T>
+struct EpiStoreT {
+    T *__restrict__ y;
+    __device__ __forceinline__ void row(int i, T s) { y[i] = s; }
+};
+
+// t = G^T r  (runs in a pass after K2, or at a phase start when expect < 0)
+__global__ void __launch_bounds__(kBlock)
+k_gt_apply(CsrDev GT, const float *__restrict__ vals, const double *__restrict__ r,
+           double *__restrict__ t, const CgState *st, int expect) {
+    __shared__ SpmvSmem<double> sm;
+    if (st->halt != RUN || (expect >= 0 && st->k != expect + 1)) return;
+    const int blk = xcd_remap(blockIdx.x, GT.n_blocks);
+    EpiStoreT<float, double> epi{t};
+    spmv_block<float, double, double>(GT, vals, r, blk, sm, epi);
+}
+
+struct EpiZ {
+    double *__restrict__ z;
+    const double *__restrict__ r;
+    double acc;
+    __device__ __forceinline__ void row(int i, double s) {
+        z[i] = s;
+        acc += r[i] * s;
+    }
+};
+
+// z = G t, rho' = r.z, beta = rho'/rho  (expect < 0: phase start, only z)
+__global__ void __launch_bounds__(kBlock)
+k_g_apply_rz(CsrDev G, const float *__restrict__ vals, const double *__restrict__ t,
+             const double *__restrict__ r, double *__restrict__ z, CgState *st, Reduce<double> R,
+             int expect) {
+    __shared__ SpmvSmem<double> sm;
+    if (st->halt != RUN || (expect >= 0 && st->k != expect + 1)) return;
+    const int blk = xcd_remap(blockIdx.x, G.n_blocks);
+    EpiZ epi{z, r, 0.0};
+    spmv_block<float, double, double>(G, vals, t, blk, sm, epi);
+    if (expect < 0) return;
+    const double v[1] = {block_sum(epi.acc, sm.red)};
+    auto fin = [&](double(&s)[1]) {
+        const double rho = s[0];
+        if (!finite_d(rho)) set_break(st, NAN);
+        else if (st->rr > 0.0 && !(rho > 0.0)) set_break(st, rho);
+        else {
+            st->beta = rho / st->rho;
+            st->rho = rho;
+        }
+    };
+    reduce_arrive<1>(v, blk, G.n_blocks, R, fin);
+}
+
+// ------------------------------------------------------------ mixed --
+
+// x64 += x32, x32 = 0  (replacement or final fold)
+__global__ void __launch_bounds__(kBlock)
+k_mp_fold(int n, double *__restrict__ x, float *__restrict__ x32, const CgState *st, int always) {
+    if (!always && st->halt != H_REPLACE) return;
+    const int base = blockIdx.x * kVecBlock + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < kVecPer; ++u) {
+        const int i = base + u * kBlock;
+        if (i < n) {
+            x[i] += (double)x32[i];
+            x32[i] = 0.0f;
+        }
+    }
+}
+
+// z32 = dinv32 r32, rho32 = r32.z32 (FP32); init: p32 = z32 as well.
+// Ends the replacement: converged, out of passes, or running again.
+__global__ void __launch_bounds__(kBlock)
+k_mp_rz(int n, const float *__restrict__ r32, const float *__restrict__ dinv32,
+        float *__restrict__ p32, CgState *st, Reduce<float> R, double *hist, int init) {
+    __shared__ float red[4];
+    if (init ? st->halt != RUN : st->halt != H_REPLACE) return;
+    float rz = 0.0f;
+    const int base = blockIdx.x * kVecBlock + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < kVecPer; ++u) {
+        const int i = base + u * kBlock;
+        if (i < n) {
+            const float ri = r32[i];
+            const float zi = dinv32[i] * ri;
+            if (init) p32[i] = zi;
+            rz += ri * zi;
+        }
+    }
+    const float v[1] = {block_sum(rz, red)};
+    auto fin = [&](float(&t)[1]) {
+        st->rho32 = t[0];
+        if (init) hist[st->k] = st->rlast / st->nb;
+        if (!finite_d((double)t[0]) || !finite_d(st->rlast)) set_break(st, NAN);
+        else if (st->rlast <= st->thresh) st->halt = H_CONV;
+        else if (!(t[0] > 0.0f)) set_break(st, (double)t[0]);
+        else if (st->k >= st->maxit) st->halt = H_MAXIT;
+        else st->halt = RUN;
+    };
+    reduce_arrive<1>(v, blockIdx.x, gridDim.x, R, fin);
+}
+
+// ------------------------------------- single-workgroup solver (small n) --
+
+template <typename T>
+__device__ __forceinline__ T wg_sum(T v, T *sh16) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh16[w] = v;
+    __syncthreads();
+    T s = T(0);
+#pragma unroll
+    for (int i = 0; i < kSmallThreads / 64; ++i) s += sh16[i];
+    __syncthreads();
+    return s;
+}
+
+// The whole loop in one 1024-thread workgroup (vectors stay in L2); the
+// state was prepared by k_resid / k_start.  Exits at convergence, maxit or
+// breakdown: every thread evaluates the same stop test on the same sums.
+template <int PRE>
+__global__ void __launch_bounds__(kSmallThreads)
+k_cg_small(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+           const double *__restrict__ vals, double *__restrict__ x, double *__restrict__ r,
+           double *__restrict__ p, double *__restrict__ q, const double *__restrict__ dinv,
+           CgState *st, double *hist) {
+    __shared__ double sh[kSmallThreads / 64];
+    if (st->halt != RUN) return;
+    double rho = st->rho;
+    const double thresh = st->thresh, nb = st->nb;
+    const int maxit = st->maxit;
+    int k = st->k;
+    int halt = RUN, status = SPCG_OK;
+    double rr = st->rr, alpha = 0.0, beta = 0.0;
+    while (true) {
+        double pq = 0.0;
+        for (int i = threadIdx.x; i < n; i += kSmallThreads) {
+            double s = 0.0;
+            for (int e = rp[i]; e < rp[i + 1]; ++e) s += vals[e] * p[col[e]];
+            q[i] = s;
+            pq += p[i] * s;
+        }
+        const double sigma = wg_sum(pq, sh);
+        if (!(sigma > 0.0) || !isfinite(sigma)) {
+            halt = H_BREAK;
+            status = isfinite(sigma) ? SPCG_NOT_SPD : SPCG_NON_FINITE;
+            break;
+        }
+        alpha = rho / sigma;
+        double rz = 0.0, rl = 0.0;
+        for (int i = threadIdx.x; i < n; i += kSmallThreads) {
+            x[i] += alpha * p[i];
+            const double ri = r[i] - alpha * q[i];
+            r[i] = ri;
+            const double zi = PRE == SPCG_PRECOND_JACOBI ? dinv[i] * ri : ri;
+            rz += ri * zi;
+            rl += ri * ri;
+        }
+        const double rzs = wg_sum(rz, sh);
+        rr = wg_sum(rl, sh);
+        ++k;
+        const double est = sqrt(rr);
+        if (threadIdx.x == 0) hist[k] = est / nb;
+        if (!isfinite(rzs) || !isfinite(rr)) {
+            halt = H_BREAK;
+            status = SPCG_NON_FINITE;
+            break;
+        }
+        if (rr > 0.0 && !(rzs > 0.0)) {
+            halt = H_BREAK;
+            status = SPCG_NOT_SPD;
+            break;
+        }
+        beta = rzs / rho;
+        rho = rzs;
+        if (est <= thresh) { halt = H_CONV; break; }
+        if (k >= maxit) { halt = H_MAXIT; break; }
+        for (int i = threadIdx.x; i < n; i += kSmallThreads) {
+            const double zi = PRE == SPCG_PRECOND_JACOBI ? dinv[i] * r[i] : r[i];
+            p[i] = zi + beta * p[i];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        st->k = k;
+        st->rho = rho;
+        st->rr = rr;
+        st->halt = halt;
+        st->status = status;
+    }
+}
+
+// ----------------------------------------------------------- workspace --
+
+struct Work {
+    CgState *st;
+    double *hist;
+    double *r, *p, *q, *dinv, *z, *t, *x0;
+    float *r32, *p32, *q32, *x32, *dinv32, *vals32;
+    Reduce<double> Rd;
+    Reduce<float> Rf;
+    int64_t nslots;
+};
+
+static int64_t n_slots(const spcg_csr *A, const spcg_cg_opts *o) {
+    int64_t s = std::max<int64_t>(A->n_blocks, vec_blocks(A->n_rows));
+    if (o->precond == SPCG_PRECOND_LEARNED) {
+        if (o->G) s = std::max<int64_t>(s, o->G->n_blocks);
+        if (o->GT) s = std::max<int64_t>(s, o->GT->n_blocks);
+    }
+    return std::max<int64_t>(s, 1);
+}
+
+static size_t carve(const spcg_csr *A, const spcg_cg_opts *o, char *base, Work *w) {
+    const int64_t n = A->n_rows;
+    const bool mixed = o->precision == SPCG_PREC_MIXED;
+    const bool learned = o->precond == SPCG_PRECOND_LEARNED;
+    char *p = base;
+    auto take = [&](size_t bytes) {
+        char *q = p;
+        p += align256(bytes);
+        return q;
+    };
+    const int64_t ns = n_slots(A, o);
+    Work W;
+    memset(&W, 0, sizeof W);
+    W.nslots = ns;
+    W.st = (CgState *)take(sizeof(CgState));
+    W.hist = (double *)take(sizeof(double) * ((size_t)std::max(o->maxit, 0) + 1));
+    W.r = (double *)take(sizeof(double) * n);
+    W.dinv = (double *)take(sizeof(double) * n);
+    if (!mixed) {
+        W.p = (double *)take(sizeof(double) * n);
+        W.q = (double *)take(sizeof(double) * n);
+    }
+    if (learned) {
+        W.z = (double *)take(sizeof(double) * n);
+        W.t = (double *)take(sizeof(double) * n);
+        W.x0 = (double *)take(sizeof(double) * n);
+    }
+    if (mixed) {
+        W.r32 = (float *)take(sizeof(float) * n);
+        W.p32 = (float *)take(sizeof(float) * n);
+        W.q32 = (float *)take(sizeof(float) * n);
+        W.x32 = (float *)take(sizeof(float) * n);
+        W.dinv32 = (float *)take(sizeof(float) * n);
+        W.vals32 = (float *)take(sizeof(float) * (size_t)A->nnz);
+    }
+    // reductions (carved without the take() rounding, which they do themselves)
+    if (base) {
+        W.Rd = reduce_carve<double>(p, ns, 2);
+        W.Rf = reduce_carve<float>(p, ns, 2);
+    } else {
+        p += reduce_bytes<double>(ns, 2) + reduce_bytes<float>(ns, 2);
+    }
+    if (w) *w = W;
+    return (size_t)(p - base);
+}
+
+static unsigned grid_of(int64_t n, int per) { return (unsigned)std::max<int64_t>((n + per - 1) / per, 1); }
+
+struct Solver {
+    spcg_csr *A;
+    const spcg_cg_opts *o;
+    Work w;
+    hipStream_t s;
+    CgState *h;  // pinned host copy
+    double *x;
+    const double *b;
+
+    int read_state() {
+        SPCG_TRY(hipMemcpyAsync(h, w.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+        SPCG_TRY(hipStreamSynchronize(s));
+        return SPCG_OK;
+    }
+    int64_t ncnt(int64_t ns) const { return (ns + kGroup - 1) / kGroup + 1; }
+
+    int resid(int mode, float *r32) {
+        if (A->n_rows == 0) return SPCG_OK;
+        hipLaunchKernelGGL(k_resid, dim3((unsigned)A->n_blocks), dim3(kBlock), 0, s, dev_view(A),
+                           (const double *)A->vals, x, b, w.r, r32, w.st, w.Rd, w.hist, mode,
+                           o->tol);
+        SPCG_LAUNCH_CHECK("k_resid");
+        return SPCG_OK;
+    }
+
+    // z = M^-1 r, p = z, rho; the phase's first history entry
+    int start(int pre) {
+        const int n = A->n_rows;
+        const unsigned gv = grid_of(n, kVecBlock);
+        if (pre == SPCG_PRECOND_LEARNED) {
+            hipLaunchKernelGGL(k_gt_apply, dim3((unsigned)o->GT->n_blocks), dim3(kBlock), 0, s,
+                               dev_view(o->GT), (const float *)o->GT->vals, (const double *)w.r,
+                               w.t, w.st, -1);
+            SPCG_LAUNCH_CHECK("k_gt_apply");
+            hipLaunchKernelGGL(k_g_apply_rz, dim3((unsigned)o->G->n_blocks), dim3(kBlock), 0, s,
+                               dev_view(o->G), (const float *)o->G->vals, (const double *)w.t,
+                               (const double *)w.r, w.z, w.st, w.Rd, -1);
+            SPCG_LAUNCH_CHECK("k_g_apply_rz");
+            hipLaunchKernelGGL(k_start<SPCG_PRECOND_LEARNED>, dim3(gv), dim3(kBlock), 0, s, n,
+                               w.r, w.dinv, w.z, w.p, w.st, w.Rd, w.hist);
+        } else if (pre == SPCG_PRECOND_JACOBI) {
+            hipLaunchKernelGGL(k_start<SPCG_PRECOND_JACOBI>, dim3(gv), dim3(kBlock), 0, s, n, w.r,
+                               w.dinv, w.z, w.p, w.st, w.Rd, w.hist);
+        } else {
+            hipLaunchKernelGGL(k_start<SPCG_PRECOND_NONE>, dim3(gv), dim3(kBlock), 0, s, n, w.r,
+                               w.dinv, w.z, w.p, w.st, w.Rd, w.hist);
+        }
+        SPCG_LAUNCH_CHECK("k_start");
+        return SPCG_OK;
+    }
+
+    int pass64(int pre, int expect) {
+        const int n = A->n_rows;
+        const unsigned gv = grid_of(n, kVecBlock);
+        hipLaunchKernelGGL((k_cg_q<double, double>), dim3((unsigned)A->n_blocks), dim3(kBlock), 0,
+                           s, dev_view(A), (const double *)A->vals, (const double *)w.p, w.q, w.st,
+                           w.Rd, expect);
+        if (pre == SPCG_PRECOND_JACOBI) {
+            hipLaunchKernelGGL((k_cg_xr<double, SPCG_PRECOND_JACOBI, false>), dim3(gv),
+                               dim3(kBlock), 0, s, n, expect, x, w.r, w.p, w.q, w.dinv, w.st, w.Rd,
+                               w.hist);
+            hipLaunchKernelGGL((k_cg_p<double, SPCG_PRECOND_JACOBI>), dim3(gv), dim3(kBlock), 0, s,
+                               n, expect, w.r, w.dinv, w.z, w.p, w.st);
+        } else if (pre == SPCG_PRECOND_NONE) {
+            hipLaunchKernelGGL((k_cg_xr<double, SPCG_PRECOND_NONE, false>), dim3(gv), dim3(kBlock),
+                               0, s, n, expect, x, w.r, w.p, w.q, w.dinv, w.st, w.Rd, w.hist);
+            hipLaunchKernelGGL((k_cg_p<double, SPCG_PRECOND_NONE>), dim3(gv), dim3(kBlock), 0, s,
+                               n, expect, w.r, w.dinv, w.z, w.p, w.st);
+        } else {
+            hipLaunchKernelGGL((k_cg_xr<double, SPCG_PRECOND_LEARNED, false>), dim3(gv),
+                               dim3(kBlock), 0, s, n, expect, x, w.r, w.p, w.q, w.dinv, w.st, w.Rd,
+                               w.hist);
+            hipLaunchKernelGGL(k_gt_apply, dim3((unsigned)o->GT->n_blocks), dim3(kBlock), 0, s,
+                               dev_view(o->GT), (const float *)o->GT->vals, (const double *)w.r,
+                               w.t, w.st, expect);
+            hipLaunchKernelGGL(k_g_apply_rz, dim3((unsigned)o->G->n_blocks), dim3(kBlock), 0, s,
+                               dev_view(o->G), (const float *)o->G->vals, (const double *)w.t,
+                               (const double *)w.r, w.z, w.st, w.Rd, expect);
+            hipLaunchKernelGGL((k_cg_p<double, SPCG_PRECOND_LEARNED>), dim3(gv), dim3(kBlock), 0,
+                               s, n, expect, w.r, w.dinv, w.z, w.p, w.st);
+        }
+        SPCG_LAUNCH_CHECK("cg pass");
+        return SPCG_OK;
+    }
+
+    int pass32(int expect) {
+        const int n = A->n_rows;
+        const unsigned gv = grid_of(n, kVecBlock);
+        hipLaunchKernelGGL((k_cg_q<float, float>), dim3((unsigned)A->n_blocks), dim3(kBlock), 0, s,
+                           dev_view(A), (const float *)w.vals32, (const float *)w.p32, w.q32, w.st,
+                           w.Rf, expect);
+        hipLaunchKernelGGL((k_cg_xr<float, SPCG_PRECOND_JACOBI, true>), dim3(gv), dim3(kBlock), 0,
+                           s, n, expect, w.x32, w.r32, w.p32, w.q32, w.dinv32, w.st, w.Rf, w.hist);
+        hipLaunchKernelGGL((k_cg_p<float, SPCG_PRECOND_JACOBI>), dim3(gv), dim3(kBlock), 0, s, n,
+                           expect, w.r32, w.dinv32, (const float *)nullptr, w.p32, w.st);
+        SPCG_LAUNCH_CHECK("mixed pass");
+        return SPCG_OK;
+    }
+
+    int replace() {
+        const int n = A->n_rows;
+        const unsigned gv = grid_of(n, kVecBlock);
+        hipLaunchKernelGGL(k_mp_fold, dim3(gv), dim3(kBlock), 0, s, n, x, w.x32, w.st, 0);
+        SPCG_LAUNCH_CHECK("k_mp_fold");
+        int rc = resid(R_REPLACE, w.r32);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_mp_rz, dim3(gv), dim3(kBlock), 0, s, n, (const float *)w.r32,
+                           (const float *)w.dinv32, w.p32, w.st, w.Rf, w.hist, 0);
+        SPCG_LAUNCH_CHECK("k_mp_rz");
+        return SPCG_OK;
+    }
+
+    // Run passes until the device state halts.  Batches are sized from the
+    // observed residual decay so that few empty passes are enqueued.
+    int loop(bool mixed, int pre) {
+        int rc;
+        double prev_rr = mixed ? (double)h->rlast * h->rlast : h->rr;
+        int prev_k = h->k;
+        int batch = o->check_every > 0 ? o->check_every : 8;
+        while (h->halt == RUN) {
+            const int k0 = h->k;
+            const int nb = std::min(batch, std::max(h->maxit - k0, 1));
+            for (int j = 0; j < nb; ++j) {
+                rc = mixed ? pass32(k0 + j) : pass64(pre, k0 + j);
+                if (rc) return rc;
+            }
+            if ((rc = read_state())) return rc;
+            if (mixed && h->halt == H_REPLACE) {
+                if ((rc = replace())) return rc;
+                if ((rc = read_state())) return rc;
+            }
+            if (o->check_every > 0) continue;
+            // adaptive batch: passes predicted to reach the next stop test
+            const double cur_rr = mixed ? (double)h->rr32 : h->rr;
+            const int dk = h->k - prev_k;
+            int next = 16;
+            if (dk > 0 && cur_rr > 0.0 && prev_rr > cur_rr) {
+                const double rate = std::log(prev_rr / cur_rr) / dk;  // per pass, in log(rr)
+                double target = h->thresh * h->thresh;
+                if (mixed) target = std::max(target, h->delta * h->delta * h->rlast * h->rlast);
+                const double need = std::log(cur_rr / target) / rate;
+                next = (int)std::ceil(std::max(need, 1.0));
+            }
+            batch = std::min(std::max(next, 2), 64);
+            prev_rr = cur_rr;
+            prev_k = h->k;
+        }
+        return SPCG_OK;
+    }
+};
+
+static int small_ok(const spcg_csr *A, const spcg_cg_opts *o) {
+    return o->small_path && o->precision == SPCG_PREC_F64 && o->precond != SPCG_PRECOND_LEARNED &&
+           A->n_rows <= 16384 && A->nnz <= (int64_t)1 << 18;
+}
+
+}  // namespace spcg
+
+using namespace spcg;
+
+extern "C" {
+
+void spcg_cg_default_opts(spcg_cg_opts *o) {
+    if (!o) return;
+    memset(o, 0, sizeof *o);
+    o->tol = 1e-10;
+    o->maxit = 20000;
+    o->precond = SPCG_PRECOND_JACOBI;
+    o->precision = SPCG_PREC_F64;
+    o->check_every = 0;
+    o->delta = 0.1;
+    o->budget = 1 << 30;
+    o->small_path = 1;
+}
+
+size_t spcg_cg_workspace_bytes(spcg_csr_t A, const spcg_cg_opts *o) {
+    if (!A || !o) return 0;
+    return carve(A, o, nullptr, nullptr) + 256;
+}
+
+int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o, void *d_work,
+             size_t work_bytes, spcg_cg_result *res, double *h_hist, hipStream_t s) {
+    if (!A || !o || !res) return SPCG_INVALID_ARG;
+    memset(res, 0, sizeof *res);
+    if (A->dtype != SPCG_F64 || A->n_rows != A->n_cols) return SPCG_INVALID_ARG;
+    if (o->maxit < 0 || !(o->tol >= 0.0)) return SPCG_INVALID_ARG;
+    if (o->precond < SPCG_PRECOND_NONE || o->precond > SPCG_PRECOND_LEARNED) return SPCG_INVALID_ARG;
+    if (o->precision != SPCG_PREC_F64 && o->precision != SPCG_PREC_MIXED) return SPCG_INVALID_ARG;
+    const bool mixed = o->precision == SPCG_PREC_MIXED;
+    const bool learned = o->precond == SPCG_PRECOND_LEARNED;
+    if (mixed && (o->precond != SPCG_PRECOND_JACOBI || !(o->delta > 0.0 && o->delta < 1.0)))
+        return SPCG_INVALID_ARG;
+    if (learned) {
+        if (!o->G || !o->GT || o->G->dtype != SPCG_F32 || o->GT->dtype != SPCG_F32 ||
+            o->G->n_rows != A->n_rows || o->GT->n_rows != A->n_rows ||
+            o->G->n_cols != A->n_rows || o->GT->n_cols != A->n_rows || o->budget < 0)
+            return SPCG_INVALID_ARG;
+    }
+    const int n = A->n_rows;
+    if (n > 0 && (!d_b || !d_x)) return SPCG_INVALID_ARG;
+    if (!d_work || ((uintptr_t)d_work & 255) != 0 ||
+        work_bytes < spcg_cg_workspace_bytes(A, o) - 256)
+        return SPCG_INVALID_ARG;
+    if (n == 0) {
+        if (h_hist) h_hist[0] = 0.0;
+        return SPCG_OK;
+    }
+
+    Solver S;
+    S.A = A;
+    S.o = o;
+    S.s = s;
+    S.x = d_x;
+    S.b = d_b;
+    S.h = (CgState *)A->h_pinned;
+    static_assert(sizeof(CgState) <= 256, "pinned status buffer");
+    carve(A, o, (char *)d_work, &S.w);
+    Work &w = S.w;
+    int rc;
+    const int64_t ns = w.nslots;
+    const int budget = learned ? std::min(o->budget, o->maxit) : o->maxit;
+    hipLaunchKernelGGL(k_init_state, dim3(1), dim3(256), 0, s, w.st, w.Rd.counters,
+                       (int)S.ncnt(ns), w.Rf.counters, (int)S.ncnt(ns), learned ? budget : o->maxit,
+                       o->delta, budget);
+    SPCG_LAUNCH_CHECK("k_init_state");
+    if (o->precond == SPCG_PRECOND_JACOBI || learned) {
+        hipLaunchKernelGGL(k_diag_inv, dim3(grid_of(n, kBlock)), dim3(kBlock), 0, s, n,
+                           A->row_ptr, A->col, (const double *)A->vals, w.dinv, w.dinv32, w.st);
+        SPCG_LAUNCH_CHECK("k_diag_inv");
+    }
+    if (mixed) {
+        hipLaunchKernelGGL(k_to_f32, dim3(grid_of(A->nnz, kBlock * 8)), dim3(kBlock), 0, s,
+                           A->nnz, (const double *)A->vals, w.vals32);
+        hipLaunchKernelGGL(k_fill<float>, dim3(grid_of(n, kBlock * 8)), dim3(kBlock), 0, s,
+                           (int64_t)n, w.x32, 0.0f);
+        SPCG_LAUNCH_CHECK("mixed set-up");
+    }
+    if (learned) {
+        hipLaunchKernelGGL(k_copy, dim3(grid_of(n, kBlock * 8)), dim3(kBlock), 0, s, (int64_t)n,
+                           (const double *)d_x, w.x0);
+        SPCG_LAUNCH_CHECK("k_copy");
+    }
+    if ((rc = S.resid(R_INIT, mixed ? w.r32 : nullptr))) return rc;
+    if ((rc = S.read_state())) return rc;
+    CgState *h = S.h;
+    if (h->bad_diag) {
+        rc = (h->bad_diag & 2) ? SPCG_NON_FINITE : SPCG_NOT_SPD;
+        return rc;
+    }
+    if (h->halt == H_ZERO) {
+        hipLaunchKernelGGL(k_fill<double>, dim3(grid_of(n, kBlock * 8)), dim3(kBlock), 0, s,
+                           (int64_t)n, d_x, 0.0);
+        SPCG_LAUNCH_CHECK("k_fill");
+        SPCG_TRY(hipStreamSynchronize(s));
+        if (h_hist) h_hist[0] = 0.0;
+        return SPCG_OK;
+    }
+    if (h->halt == H_BREAK) return h->status;
+
+    const int pre0 = o->precond;
+    int status = SPCG_OK;
+    int restarts = 0;
+    bool fell_back = false;
+    int learned_iters = 0;
+    int pre = pre0;
+    if (mixed) {
+        hipLaunchKernelGGL(k_mp_rz, dim3(grid_of(n, kVecBlock)), dim3(kBlock), 0, s, n,
+                           (const float *)w.r32, (const float *)w.dinv32, w.p32, w.st, w.Rf,
+                           w.hist, 1);
+        SPCG_LAUNCH_CHECK("k_mp_rz");
+    } else if ((rc = S.start(pre))) {
+        return rc;
+    }
+    if ((rc = S.read_state())) return rc;
+
+    for (;;) {
+        if (h->halt == RUN) {
+            if (!mixed && !learned && small_ok(A, o) && pre != SPCG_PRECOND_LEARNED) {
+                if (pre == SPCG_PRECOND_JACOBI)
+                    hipLaunchKernelGGL(k_cg_small<SPCG_PRECOND_JACOBI>, dim3(1),
+                                       dim3(kSmallThreads), 0, s, n, A->row_ptr, A->col,
+                                       (const double *)A->vals, d_x, w.r, w.p, w.q, w.dinv, w.st,
+                                       w.hist);
+                else
+                    hipLaunchKernelGGL(k_cg_small<SPCG_PRECOND_NONE>, dim3(1), dim3(kSmallThreads),
+                                       0, s, n, A->row_ptr, A->col, (const double *)A->vals, d_x,
+                                       w.r, w.p, w.q, w.dinv, w.st, w.hist);
+                SPCG_LAUNCH_CHECK("k_cg_small");
+                if ((rc = S.read_state())) return rc;
+            } else if ((rc = S.loop(mixed, pre))) {
+                return rc;
+            }
+        }
+        const int halt = h->halt;
+        if (pre == SPCG_PRECOND_LEARNED && (halt == H_BUDGET || halt == H_BREAK ||
+                                            (halt == H_MAXIT))) {
+            // fall back to Jacobi-PCG: from x0 after a breakdown, else from x
+            learned_iters = h->k;
+            fell_back = true;
+            pre = SPCG_PRECOND_JACOBI;
+            if (halt == H_BREAK) {
+                hipLaunchKernelGGL(k_copy, dim3(grid_of(n, kBlock * 8)), dim3(kBlock), 0, s,
+                                   (int64_t)n, (const double *)w.x0, d_x);
+                SPCG_LAUNCH_CHECK("k_copy");
+            }
+            hipLaunchKernelGGL(k_init_state, dim3(1), dim3(256), 0, s, w.st, w.Rd.counters,
+                               (int)S.ncnt(ns), w.Rf.counters, (int)S.ncnt(ns),
+                               o->maxit - (halt == H_BREAK ? 0 : learned_iters), o->delta,
+                               o->maxit);
+            SPCG_LAUNCH_CHECK("k_init_state");
+            if ((rc = S.resid(R_INIT, nullptr))) return rc;
+            if ((rc = S.start(pre))) return rc;
+            if ((rc = S.read_state())) return rc;
+            if (h->halt == H_BREAK) return h->status;
+            continue;
+        }
+        if (halt == H_BREAK) {
+            status = h->status;
+            break;
+        }
+        // exit check: fold the FP32 correction, recompute b - A x in FP64
+        if (mixed) {
+            hipLaunchKernelGGL(k_mp_fold, dim3(grid_of(n, kVecBlock)), dim3(kBlock), 0, s, n, d_x,
+                               w.x32, w.st, 1);
+            SPCG_LAUNCH_CHECK("k_mp_fold");
+        }
+        if ((rc = S.resid(R_TRUE, nullptr))) return rc;
+        if ((rc = S.read_state())) return rc;
+        const double tr = std::sqrt(h->true_rr) / h->nb;
+        res->true_relres = tr;
+        if (tr <= o->tol) {
+            status = SPCG_OK;
+            break;
+        }
+        if (h->k >= h->maxit || restarts >= 4 || mixed) {
+            status = SPCG_NOT_CONVERGED;
+            break;
+        }
+        // residual gap: restart from the true residual (r holds b - A x)
+        ++restarts;
+        hipLaunchKernelGGL(k_phase_state, dim3(1), dim3(64), 0, s, w.st, h->maxit, h->budget);
+        SPCG_LAUNCH_CHECK("k_phase_state");
+        if ((rc = S.start(pre))) return rc;
+        if ((rc = S.read_state())) return rc;
+    }
+    if (fell_back) {
+        res->iters = learned_iters;
+        res->iters_fallback = h->k;
+        if (status == SPCG_OK) status = SPCG_FELL_BACK;
+    } else {
+        res->iters = h->k;
+    }
+    res->n_updates = h->n_updates;
+    res->n_restarts = restarts;
+    if (h_hist) {
+        const int kk = h->k;
+        SPCG_TRY(hipMemcpyAsync(h_hist, w.hist, sizeof(double) * (kk + 1), hipMemcpyDeviceToHost, s));
+        SPCG_TRY(hipStreamSynchronize(s));
+    }
+    return status;
+}
+
+}  // extern "C"

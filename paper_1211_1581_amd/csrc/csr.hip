@@ -1,0 +1,280 @@
+// csr.hip -- matrix handle (validation + row analysis), y = A x, and the
+// deterministic inner product.  CSR in three arrays and the row-wise product
+// follow Sec. 3.2 of arXiv 1211.1581.
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "internal.h"
+
+namespace spcg {
+
+static thread_local char g_err[512] = "";
+
+void set_error(hipError_t e, const char *what) {
+    snprintf(g_err, sizeof g_err, "%s: %s", what, hipGetErrorString(e));
+}
+
+int hip_status(hipError_t e, const char *what) {
+    set_error(e, what);
+    return SPCG_HIP_ERROR;
+}
+
+// ------------------------------------------------------------- analysis --
+
+// flags[0]: error bits (1 row_ptr[0] != 0, 2 decreasing row_ptr, 4 row_ptr[n] != nnz,
+// 8 column out of range); flags[1]: longest row; flags[2]: blocks whose
+// last row does not fit the LDS slab.
+__global__ void k_fill_i32(int32_t *p, int n, int32_t v) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_validate(int n, int ncols, int64_t nnz, const int32_t *__restrict__ rp,
+           const int32_t *__restrict__ col, int32_t *flags) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int err = 0, mx = 0;
+    for (int64_t i = t0; i <= n; i += stride) {
+        const int a = rp[i];
+        if (i == 0 && a != 0) err |= 1;
+        if (i < n) {
+            const int len = rp[i + 1] - a;
+            if (len < 0) err |= 2;
+            mx = max(mx, len);
+        } else if ((int64_t)a != nnz) {
+            err |= 4;
+        }
+    }
+    for (int64_t k = t0; k < nnz; k += stride) {
+        const int c = col[k];
+        if (c < 0 || c >= ncols) err |= 8;
+    }
+    if (err) atomicOr(&flags[0], err);
+    if (mx) atomicMax(&flags[1], mx);
+}
+
+// block_row[b] = first row i with row_ptr[i] + i >= b * kChunk (b < nb), block_row[nb] = n
+__global__ void __launch_bounds__(kBlock)
+k_partition(int n, const int32_t *__restrict__ rp, int64_t nb, int32_t *block_row) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > nb) return;
+    if (b == nb) {
+        block_row[b] = n;
+        return;
+    }
+    const int64_t target = b * kChunk;
+    int lo = 0, hi = n;  // answer in [lo, hi]
+    while (lo < hi) {
+        const int mid = lo + ((hi - lo) >> 1);
+        if ((int64_t)rp[mid] + mid >= target) hi = mid;
+        else lo = mid + 1;
+    }
+    block_row[b] = lo;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_count_long(const int32_t *__restrict__ rp, const int32_t *__restrict__ block_row, int64_t nb,
+             int32_t *flags) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const int r0 = block_row[b], r1 = block_row[b + 1];
+    if (r0 < r1 && rp[r1] - rp[r0] > kSlab) atomicAdd(&flags[2], 1);
+}
+
+// ------------------------------------------------------------------ SpMV --
+
+template <typename T>
+struct EpiStore {
+    T *__restrict__ y;
+    __device__ __forceinline__ void row(int i, T s) { y[i] = s; }
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_spmv(CsrDev A, const T *__restrict__ vals, const T *__restrict__ x, T *__restrict__ y) {
+    __shared__ SpmvSmem<T> sm;
+    const int blk = xcd_remap(blockIdx.x, A.n_blocks);
+    EpiStore<T> epi{y};
+    spmv_block<T, T, T>(A, vals, x, blk, sm, epi);
+}
+
+template <typename T>
+int launch_spmv(const spcg_csr *A, const T *x, T *y, hipStream_t s) {
+    if (A->n_rows == 0) return SPCG_OK;
+    hipLaunchKernelGGL(k_spmv<T>, dim3((unsigned)A->n_blocks), dim3(kBlock), 0, s, dev_view(A),
+                       (const T *)A->vals, x, y);
+    SPCG_LAUNCH_CHECK("k_spmv");
+    return SPCG_OK;
+}
+
+// ------------------------------------------------------------------- dot --
+
+constexpr int kDotPerBlock = kBlock * 16;
+
+__global__ void __launch_bounds__(kBlock)
+k_dot_partials(int64_t n, const double *__restrict__ a, const double *__restrict__ b,
+               double *__restrict__ part) {
+    __shared__ double red[4];
+    const int64_t base = (int64_t)blockIdx.x * kDotPerBlock;
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < kDotPerBlock / kBlock; ++u) {
+        const int64_t i = base + threadIdx.x + (int64_t)u * kBlock;
+        if (i < n) s += a[i] * b[i];
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_dot_final(int64_t nparts, const double *__restrict__ part, double *out) {
+    __shared__ double red[4];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < nparts; i += kBlock) s += part[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) *out = s;
+}
+
+}  // namespace spcg
+
+using namespace spcg;
+
+extern "C" {
+
+const char *spcg_status_str(int status) {
+    switch (status) {
+        case SPCG_OK: return "OK";
+        case SPCG_NOT_CONVERGED: return "NOT_CONVERGED";
+        case SPCG_FELL_BACK: return "FELL_BACK";
+        case SPCG_INVALID_ARG: return "INVALID_ARG";
+        case SPCG_INVALID_CSR: return "INVALID_CSR";
+        case SPCG_HIP_ERROR: return "HIP_ERROR";
+        case SPCG_NOT_SPD: return "NOT_SPD";
+        case SPCG_NON_FINITE: return "NON_FINITE";
+        default: return "UNKNOWN";
+    }
+}
+
+const char *spcg_last_error(void) { return g_err; }
+
+static void release(spcg_csr *h) {
+    if (!h) return;
+    if (h->block_row) (void)hipFree(h->block_row);
+    if (h->flags) (void)hipFree(h->flags);
+    if (h->h_pinned) (void)hipHostFree(h->h_pinned);
+    delete h;
+}
+
+int spcg_csr_create(spcg_csr_t *out, int32_t n_rows, int32_t n_cols, int64_t nnz,
+                    const int32_t *d_row_ptr, const int32_t *d_col, const void *d_vals,
+                    int32_t dtype, hipStream_t stream) {
+    if (!out) return SPCG_INVALID_ARG;
+    *out = nullptr;
+    if (n_rows < 0 || n_cols < 0 || nnz < 0 || nnz >= (int64_t(1) << 31)) return SPCG_INVALID_ARG;
+    if (dtype != SPCG_F64 && dtype != SPCG_F32) return SPCG_INVALID_ARG;
+    if (!d_row_ptr || (nnz > 0 && (!d_col || !d_vals))) return SPCG_INVALID_ARG;
+    spcg_csr *h = new (std::nothrow) spcg_csr;
+    if (!h) return SPCG_INVALID_ARG;
+    h->n_rows = n_rows;
+    h->n_cols = n_cols;
+    h->nnz = nnz;
+    h->row_ptr = d_row_ptr;
+    h->col = d_col;
+    h->vals = d_vals;
+    h->dtype = dtype;
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) { release(h); return hip_status(e, "hipGetDevice"); }
+#define CREATE_TRY(expr)                                            \
+    do {                                                            \
+        hipError_t e_ = (expr);                                     \
+        if (e_ != hipSuccess) { release(h); return hip_status(e_, #expr); } \
+    } while (0)
+    CREATE_TRY(hipMalloc(&h->flags, 256));
+    CREATE_TRY(hipHostMalloc(&h->h_pinned, 256, hipHostMallocDefault));
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, stream, h->flags, 64, 0);
+    CREATE_TRY(hipGetLastError());
+    {
+        const int64_t work = (int64_t)n_rows + 1 > nnz ? (int64_t)n_rows + 1 : nnz;
+        const unsigned grid = (unsigned)std::min<int64_t>((work + kBlock - 1) / kBlock, 8192);
+        hipLaunchKernelGGL(k_validate, dim3(grid > 0 ? grid : 1), dim3(kBlock), 0, stream, n_rows,
+                           n_cols, nnz, d_row_ptr, d_col, h->flags);
+        CREATE_TRY(hipGetLastError());
+    }
+    int32_t *hf = (int32_t *)h->h_pinned;
+    CREATE_TRY(hipMemcpyAsync(hf, h->flags, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    CREATE_TRY(hipStreamSynchronize(stream));
+    if (hf[0] != 0) {
+        release(h);
+        return SPCG_INVALID_CSR;
+    }
+    h->max_len = hf[1];
+    h->n_blocks = n_row_blocks(n_rows, nnz);
+    if (h->n_blocks > INT32_MAX / 2) { release(h); return SPCG_INVALID_ARG; }
+    CREATE_TRY(hipMalloc(&h->block_row, sizeof(int32_t) * (h->n_blocks + 1)));
+    {
+        const unsigned grid = (unsigned)((h->n_blocks + 1 + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(k_partition, dim3(grid), dim3(kBlock), 0, stream, n_rows, d_row_ptr,
+                           h->n_blocks, h->block_row);
+        CREATE_TRY(hipGetLastError());
+        if (h->n_blocks > 0) {
+            const unsigned g2 = (unsigned)((h->n_blocks + kBlock - 1) / kBlock);
+            hipLaunchKernelGGL(k_count_long, dim3(g2), dim3(kBlock), 0, stream, d_row_ptr,
+                               h->block_row, h->n_blocks, h->flags);
+            CREATE_TRY(hipGetLastError());
+        }
+    }
+    CREATE_TRY(hipMemcpyAsync(hf, h->flags, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    CREATE_TRY(hipStreamSynchronize(stream));
+    h->n_long = hf[2];
+#undef CREATE_TRY
+    *out = h;
+    return SPCG_OK;
+}
+
+int spcg_csr_destroy(spcg_csr_t A) {
+    if (!A) return SPCG_INVALID_ARG;
+    hipError_t e = hipDeviceSynchronize();
+    release(A);
+    return e == hipSuccess ? SPCG_OK : hip_status(e, "hipDeviceSynchronize");
+}
+
+int spcg_csr_info(spcg_csr_t A, int64_t *n_blocks, int64_t *n_long_rows, int64_t *max_row_len) {
+    if (!A) return SPCG_INVALID_ARG;
+    if (n_blocks) *n_blocks = A->n_blocks;
+    if (n_long_rows) *n_long_rows = A->n_long;
+    if (max_row_len) *max_row_len = A->max_len;
+    return SPCG_OK;
+}
+
+int spmv_csr(spcg_csr_t A, const void *d_x, void *d_y, hipStream_t stream) {
+    if (!A) return SPCG_INVALID_ARG;
+    if (A->n_rows > 0 && !d_y) return SPCG_INVALID_ARG;
+    if (A->nnz > 0 && !d_x) return SPCG_INVALID_ARG;
+    if (A->dtype == SPCG_F64)
+        return launch_spmv<double>(A, (const double *)d_x, (double *)d_y, stream);
+    return launch_spmv<float>(A, (const float *)d_x, (float *)d_y, stream);
+}
+
+size_t spcg_dot_workspace_bytes(int64_t n) {
+    const int64_t parts = n > 0 ? (n + kDotPerBlock - 1) / kDotPerBlock : 1;
+    return align256(sizeof(double) * parts);
+}
+
+int spcg_dot(int64_t n, const double *d_a, const double *d_b, double *d_out, void *d_work,
+             hipStream_t stream) {
+    if (n < 0 || !d_out || !d_work || (n > 0 && (!d_a || !d_b))) return SPCG_INVALID_ARG;
+    const int64_t parts = n > 0 ? (n + kDotPerBlock - 1) / kDotPerBlock : 0;
+    double *part = (double *)d_work;
+    if (parts > 0) {
+        hipLaunchKernelGGL(k_dot_partials, dim3((unsigned)parts), dim3(kBlock), 0, stream, n, d_a,
+                           d_b, part);
+        SPCG_LAUNCH_CHECK("k_dot_partials");
+    }
+    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kBlock), 0, stream, parts, part, d_out);
+    SPCG_LAUNCH_CHECK("k_dot_final");
+    return SPCG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,230 @@
+"""Thin ctypes binding of libspcg.so (include/spcg.h).
+
+Argument marshalling only: torch tensors provide device memory and the
+current HIP stream; every step of SpMV and CG runs in the library's kernels.
+Importing works without a GPU; calls need the built library and a device and
+raise if either is missing (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspcg.so")
+
+OK, NOT_CONVERGED, FELL_BACK = 0, 1, 2
+INVALID_ARG, INVALID_CSR, HIP_ERROR, NOT_SPD, NON_FINITE = -1, -2, -3, -4, -5
+F64, F32 = 0, 1
+PRECOND = {"none": 0, "jacobi": 1, "learned": 2}
+PRECISION = {"f64": 0, "mixed": 1}
+
+
+class SpcgError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        super().__init__(f"{what}: {status_str(status)} {last_error()}".strip())
+
+
+class CgOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32),
+                ("precond", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("delta", ctypes.c_double),
+                ("G", ctypes.c_void_p), ("GT", ctypes.c_void_p),
+                ("budget", ctypes.c_int32), ("small_path", ctypes.c_int32)]
+
+
+class CgResult(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("iters_fallback", ctypes.c_int32),
+                ("n_updates", ctypes.c_int32), ("n_restarts", ctypes.c_int32),
+                ("true_relres", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libspcg.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1211_1581_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        L.spcg_status_str.argtypes = [ctypes.c_int]
+        L.spcg_status_str.restype = ctypes.c_char_p
+        L.spcg_last_error.argtypes = []
+        L.spcg_last_error.restype = ctypes.c_char_p
+        L.spcg_csr_create.argtypes = [ctypes.POINTER(P), i32, i32, i64, P, P, P, i32, P]
+        L.spcg_csr_destroy.argtypes = [P]
+        L.spcg_csr_info.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                    ctypes.POINTER(i64)]
+        L.spmv_csr.argtypes = [P, P, P, P]
+        L.spcg_dot_workspace_bytes.argtypes = [i64]
+        L.spcg_dot_workspace_bytes.restype = sz
+        L.spcg_dot.argtypes = [i64, P, P, P, P, P]
+        L.spcg_cg_default_opts.argtypes = [ctypes.POINTER(CgOpts)]
+        L.spcg_cg_default_opts.restype = None
+        L.spcg_cg_workspace_bytes.argtypes = [P, ctypes.POINTER(CgOpts)]
+        L.spcg_cg_workspace_bytes.restype = sz
+        L.cg_solve.argtypes = [P, P, P, ctypes.POINTER(CgOpts), P, sz,
+                               ctypes.POINTER(CgResult), P, P]
+        _lib = L
+    return _lib
+
+
+def status_str(st: int) -> str:
+    return lib().spcg_status_str(st).decode()
+
+
+def last_error() -> str:
+    return lib().spcg_last_error().decode()
+
+
+def _check(st, what):
+    if st < 0 and st != NOT_SPD and st != NON_FINITE:
+        raise SpcgError(st, what)
+    return st
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    """Device buffer of nbytes whose start is 256-byte aligned."""
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + nbytes]
+
+
+class CsrMatrix:
+    """A CSR matrix resident on the device and its library handle.
+
+    row_ptr int32[n+1], col int32[nnz], vals float64 or float32[nnz], all
+    device tensors that this object keeps alive for the handle's lifetime."""
+
+    def __init__(self, row_ptr, col, vals, n_cols=None):
+        self.row_ptr = row_ptr.contiguous()
+        self.col = col.contiguous()
+        self.vals = vals.contiguous()
+        self.n_rows = self.row_ptr.numel() - 1
+        self.n_cols = self.n_rows if n_cols is None else int(n_cols)
+        self.nnz = self.col.numel()
+        self.dtype = {torch.float64: F64, torch.float32: F32}[self.vals.dtype]
+        self._h = ctypes.c_void_p(0)
+        st = lib().spcg_csr_create(ctypes.byref(self._h), self.n_rows, self.n_cols, self.nnz,
+                                   _ptr(self.row_ptr), _ptr(self.col), _ptr(self.vals),
+                                   self.dtype, _stream())
+        if st != OK:
+            self._h = ctypes.c_void_p(0)
+            raise SpcgError(st, "spcg_csr_create")
+
+    @classmethod
+    def from_host(cls, A, device="cuda", dtype=torch.float64):
+        """From an object with n_rows, n_cols, row_ptr, col, vals (numpy)."""
+        rp = torch.as_tensor(A.row_ptr, dtype=torch.int32).to(device)
+        c = torch.as_tensor(A.col, dtype=torch.int32).to(device)
+        v = torch.as_tensor(A.vals).to(dtype).to(device)
+        return cls(rp, c, v, n_cols=A.n_cols)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().spcg_csr_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+               "spcg_csr_info")
+        return dict(n_blocks=a.value, n_long=b.value, max_row_len=c.value)
+
+    def close(self):
+        if self._h and self._h.value:
+            lib().spcg_csr_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def spmv_csr(A: CsrMatrix, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
+    """y = A x on the current stream (asynchronous)."""
+    if y is None:
+        y = torch.empty(A.n_rows, dtype=A.vals.dtype, device=A.vals.device)
+    assert x.dtype == A.vals.dtype and y.dtype == A.vals.dtype
+    assert x.numel() == A.n_cols and y.numel() == A.n_rows and x.is_contiguous()
+    _check(lib().spmv_csr(A.handle, _ptr(x), _ptr(y), _stream()), "spmv_csr")
+    return y
+
+
+def dot(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+    """Deterministic FP64 inner product, result as a 1-element device tensor."""
+    assert a.dtype == torch.float64 and b.dtype == torch.float64 and a.numel() == b.numel()
+    n = a.numel()
+    out = torch.empty(1, dtype=torch.float64, device=a.device)
+    work = _workspace(lib().spcg_dot_workspace_bytes(n), a.device)
+    _check(lib().spcg_dot(n, _ptr(a), _ptr(b), _ptr(out), _ptr(work), _stream()), "spcg_dot")
+    return out
+
+
+def cg_opts(tol=1e-10, maxit=20000, precond="jacobi", precision="f64", check_every=0,
+            delta=0.1, G=None, GT=None, budget=None, small_path=True) -> CgOpts:
+    o = CgOpts()
+    lib().spcg_cg_default_opts(ctypes.byref(o))
+    o.tol = tol
+    o.maxit = maxit
+    o.precond = PRECOND[precond]
+    o.precision = PRECISION[precision]
+    o.check_every = check_every
+    o.delta = delta
+    o.G = G.handle.value if G is not None else None
+    o.GT = GT.handle.value if GT is not None else None
+    if budget is not None:
+        o.budget = budget
+    o.small_path = 1 if small_path else 0
+    return o
+
+
+class CgWorkspace:
+    """Reusable device workspace for cg_solve with fixed options."""
+
+    def __init__(self, A: CsrMatrix, opts: CgOpts):
+        self.nbytes = lib().spcg_cg_workspace_bytes(A.handle, ctypes.byref(opts))
+        self.buf = _workspace(self.nbytes, A.vals.device)
+
+
+def cg_solve(A: CsrMatrix, b: torch.Tensor, x: torch.Tensor | None = None, *, opts=None,
+             work: CgWorkspace | None = None, want_hist=True, **kw):
+    """Solve A x = b (x: in x0, out solution; zero if None).  Returns a dict with
+    status, x, iters, iters_fallback, n_updates, n_restarts, true_relres, hist."""
+    if opts is None:
+        opts = cg_opts(**kw)
+    if x is None:
+        x = torch.zeros_like(b)
+    assert b.dtype == torch.float64 and x.dtype == torch.float64 and x.is_contiguous()
+    if work is None:
+        work = CgWorkspace(A, opts)
+    res = CgResult()
+    hist = (ctypes.c_double * (opts.maxit + 1))() if want_hist else None
+    hp = ctypes.cast(hist, ctypes.c_void_p) if want_hist else ctypes.c_void_p(0)
+    st = lib().cg_solve(A.handle, _ptr(b), _ptr(x), ctypes.byref(opts), _ptr(work.buf),
+                        work.nbytes, ctypes.byref(res), hp, _stream())
+    _check(st, "cg_solve")
+    k = res.iters_fallback if res.iters_fallback > 0 or st == FELL_BACK else res.iters
+    out = dict(status=st, x=x, iters=res.iters, iters_fallback=res.iters_fallback,
+               n_updates=res.n_updates, n_restarts=res.n_restarts,
+               true_relres=res.true_relres)
+    if want_hist:
+        import numpy as np
+        out["hist"] = np.ctypeslib.as_array(hist)[:k + 1].copy()
+    return out

@@ -1,0 +1,66 @@
+"""Host-side checks of the C ABI: the library loads without a GPU and exports
+every function that include/spcg.h declares; struct layouts of the binding
+match the header; the oracle library builds.  No compute call is made."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "spcg.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([a-z_][a-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for required in ["spcg_csr_create", "spcg_csr_destroy", "spmv_csr", "cg_solve",
+                     "spcg_cg_workspace_bytes", "spcg_dot", "spcg_status_str"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1211_1581_amd import spcg
+    if not os.path.exists(spcg.LIB_PATH):
+        from paper_1211_1581_amd import build
+        build.build()
+    L = ctypes.CDLL(spcg.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_status_strings_and_struct_sizes():
+    from paper_1211_1581_amd import spcg
+    assert spcg.status_str(spcg.OK) == "OK"
+    assert spcg.status_str(spcg.NOT_SPD) == "NOT_SPD"
+    # spcg_cg_opts: double, 4 x int32, double, 2 pointers, 2 x int32
+    assert ctypes.sizeof(spcg.CgOpts) == 8 + 16 + 8 + 16 + 8
+    assert ctypes.sizeof(spcg.CgResult) == 16 + 8
+    o = spcg.CgOpts()
+    spcg.lib().spcg_cg_default_opts(ctypes.byref(o))
+    assert o.tol == 1e-10 and o.maxit == 20000 and o.precond == 1 and o.delta == 0.1
+
+
+def test_invalid_args_rejected_on_host():
+    from paper_1211_1581_amd import spcg
+    L = spcg.lib()
+    h = ctypes.c_void_p(0)
+    # negative sizes and bad dtype are rejected before any device work
+    assert L.spcg_csr_create(ctypes.byref(h), -1, 3, 0, None, None, None, 0, None) == spcg.INVALID_ARG
+    assert L.spcg_csr_create(ctypes.byref(h), 3, 3, 0, None, None, None, 7, None) == spcg.INVALID_ARG
+    assert L.spmv_csr(None, None, None, None) == spcg.INVALID_ARG
+    res = spcg.CgResult()
+    assert L.cg_solve(None, None, None, None, None, 0, ctypes.byref(res), None, None) == spcg.INVALID_ARG
+
+
+def test_oracle_builds():
+    import oracle
+    path = oracle.build(force=False)
+    assert os.path.exists(path)
