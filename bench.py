@@ -1,0 +1,248 @@
+"""Benchmark of the CSR SpMV / conjugate-gradient hot path on one MI355X.
+
+One step = one Jacobi-preconditioned CG solve (FP64) of the 3-D 7-point
+Poisson matrix on a 128^3 grid to a 1e-10 relative residual: the SpMV with
+p.q folded in, the reductions, the fused vector updates, the Jacobi step, the
+device-side stop test and the final FP64 residual check.  Inputs (matrix, b,
+x0 = 0) are resident in HBM before the timed region.
+
+Prints ONE JSON line.  `value` is the hot path's algorithmic HBM throughput
+(passes x algorithmic bytes per pass / wall time of the solves); the roofline
+object reports the dominant kernel (SpMV + p.q) from HIP events recorded
+around each of its launches on the solve's stream; `cpu_baseline` times the
+FP64 oracle on the host cores on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--cpu-seconds 15] [--forms]
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "SpMV GB/s (% HBM peak); CG time to 1e-10 rel. residual, learned vs plain"
+
+
+def spmv_bytes(n, nnz, sv=8, sx=8):
+    """Algorithmic bytes of y = A x: values + int32 columns + int32 row pointers,
+    x read once, y written once."""
+    return nnz * (sv + 4) + 4 * (n + 1) + n * sx + n * sx
+
+
+def jpcg_pass_bytes(n, nnz):
+    """FP64 Jacobi-PCG pass: SpMV + 88 n (x, p, r, q, dinv read and x, r
+    written by the update; r, dinv, p read and p written by the direction)."""
+    return spmv_bytes(n, nnz) + 88 * n
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1211_1581_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if they
+    were taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(A, b, seconds):
+    """The oracle (plain FP64 C, OpenMP rows) on a bounded sample: as many
+    Jacobi-PCG passes of the same system as fit in about `seconds`."""
+    import oracle
+    n, nnz = A.n_rows, A.nnz
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    # calibrate with a short run, then size the sample
+    t = time.perf_counter()
+    r = oracle.pcg(A, b, tol=0.0, maxit=3, precond="jacobi")
+    dt = time.perf_counter() - t
+    per = dt / max(r["iters"], 1)
+    passes = int(max(5, min(425, seconds / max(per, 1e-6))))
+    t = time.perf_counter()
+    r = oracle.pcg(A, b, tol=0.0, maxit=passes, precond="jacobi")
+    dt = time.perf_counter() - t
+    gbs = r["iters"] * jpcg_pass_bytes(n, nnz) / dt / 1e9
+    return {"value": round(gbs, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": f"{r['iters']} Jacobi-PCG passes (with set-up) of the 128^3 Poisson "
+                      f"system in {dt:.1f} s; a full solve takes 425 passes",
+            "est_time_to_tol_s": round(dt / r["iters"] * 425, 2)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib", action="store_true",
+                    help="first copy 256 MiB device-to-device once (reference dispatch for "
+                         "hardware byte counters)")
+    ap.add_argument("--forms", action="store_true",
+                    help="also time the mixed-precision and learned forms (160^3 / 128^3 FV)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(how it would shard is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1211_1581_amd import inputs as I
+    from paper_1211_1581_amd import spcg
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.calib:
+        src = torch.ones(2 ** 25, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    A = I.poisson3d(128)
+    xs = I.uniform_vector(A.n_rows, 1)
+    b = I.rhs_from_solution(A, xs)
+    n, nnz = A.n_rows, A.nnz
+
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    M = spcg.CsrMatrix.from_host(A, device=dev)
+    torch.cuda.synchronize()
+    analysis_ms = (time.perf_counter() - t) * 1e3  # includes the host->device copy
+
+    bt = torch.as_tensor(b, device=dev)
+    x = torch.zeros(n, dtype=torch.float64, device=dev)
+    opts = spcg.cg_opts(tol=1e-10, maxit=20000, precond="jacobi", timing=True)
+    work = spcg.CgWorkspace(M, opts)
+
+    def step():
+        x.zero_()
+        return spcg.cg_solve(M, bt, x, opts=opts, work=work, want_hist=False)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    iters = outs[-1]["iters"]
+    assert all(o["status"] == 0 for o in outs), [o["status"] for o in outs]
+    passes = sum(o["iters"] for o in outs)
+    value = passes * jpcg_pass_bytes(n, nnz) / (t1 - t0) / 1e9
+
+    spmv_ms = sum(o["spmv_ms"] for o in outs)
+    spmv_calls = sum(o["spmv_calls"] for o in outs)
+    b_spmv = spmv_bytes(n, nnz)
+    avg_us = spmv_ms * 1e3 / max(spmv_calls, 1)
+    achieved = b_spmv / (avg_us * 1e-6) / 1e9
+    traffic = measured_traffic("k_cg_q", "poisson128")
+
+    # standalone SpMV, cold: rotate over 3 copies (651 MB > the 256 MB MALL)
+    copies = [M] + [spcg.CsrMatrix.from_host(A, device=dev) for _ in range(2)]
+    xt = torch.as_tensor(xs, device=dev)
+    y = torch.empty(n, dtype=torch.float64, device=dev)
+    for i in range(6):
+        spcg.spmv_csr(copies[i % 3], xt, y)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(30)]
+    for i, (e0, e1) in enumerate(evs):
+        e0.record()
+        spcg.spmv_csr(copies[i % 3], xt, y)
+        e1.record()
+    torch.cuda.synchronize()
+    cold_us = float(np.median([e0.elapsed_time(e1) * 1e3 for e0, e1 in evs]))
+    del copies
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "3-D 7-point Poisson 128^3 (n=2097152, nnz=14581760, int32 CSR), "
+                               "b = A x*, x* ~ U[-1,1] seed 1, x0 = 0, FP64 Jacobi-PCG to 1e-10",
+                   "parallelism": "single GPU"},
+        "time_to_tol_ms": round(ms_per_step, 3),
+        "iters": iters,
+        "true_relres": outs[-1]["true_relres"],
+        "analysis_ms": round(analysis_ms, 2),
+        "spmv_in_cg_gbs": round(achieved, 1),
+        "spmv_in_cg_pct_peak": round(100 * achieved / PEAK_HBM_GBS, 1),
+        "spmv_cold_gbs": round(b_spmv / (cold_us * 1e-6) / 1e9, 1),
+        "spmv_cold_us": round(cold_us, 2),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": traffic, "kernel": "k_cg_q (SpMV q = A p with p.q partials)",
+                     "bytes_per_launch": b_spmv, "avg_launch_us": round(avg_us, 2),
+                     "launches": spmv_calls},
+    }
+    if args.forms:
+        line["forms"] = forms(args)
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(A, b, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+def forms(args):
+    """Time-to-tolerance of FP64 Jacobi-PCG vs the mixed-precision form on the
+    160^3 finite-volume diffusion matrix (seed 3)."""
+    import torch
+
+    from paper_1211_1581_amd import inputs as I
+    from paper_1211_1581_amd import spcg
+    dev = torch.device("cuda:0")
+    A, _, xs = I.fv_diffusion(160, 3)
+    b = I.rhs_from_solution(A, xs)
+    M = spcg.CsrMatrix.from_host(A, device=dev)
+    bt = torch.as_tensor(b, device=dev)
+    out = {}
+    for prec in ("f64", "mixed"):
+        opts = spcg.cg_opts(tol=1e-10, maxit=20000, precond="jacobi", precision=prec)
+        work = spcg.CgWorkspace(M, opts)
+        x = torch.zeros_like(bt)
+        spcg.cg_solve(M, bt, x, opts=opts, work=work, want_hist=False)
+        ts = []
+        for _ in range(3):
+            x.zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = spcg.cg_solve(M, bt, x, opts=opts, work=work, want_hist=False)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        out[prec] = {"ms": round(1e3 * min(ts), 2), "iters": r["iters"],
+                     "n_updates": r["n_updates"], "true_relres": r["true_relres"],
+                     "status": r["status"]}
+    out["workload"] = "FV diffusion 160^3, GRF seed 3, Jacobi-PCG vs FP32-inner reliable-update"
+    return out
+
+
+if __name__ == "__main__":
+    main()

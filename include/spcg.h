@@ -116,6 +116,9 @@ typedef struct {
     spcg_csr_t GT;       /* learned: its transpose (pattern of triu(A)), F32 values */
     int32_t budget;      /* learned: passes allowed before the Jacobi fallback */
     int32_t small_path;  /* 1 = allow the single-workgroup solver for small n, 0 = never */
+    int32_t timing;      /* 1 = bracket every SpMV launch of the pass loop with HIP events on
+                            `stream` and report their summed duration (events are created on the
+                            handle the first time; adds an event record per launch) */
 } spcg_cg_opts;
 
 typedef struct {
@@ -124,6 +127,9 @@ typedef struct {
     int32_t n_updates;      /* mixed: FP64 residual replacements */
     int32_t n_restarts;     /* true-residual restarts */
     double true_relres;     /* ||b - A x||_2 / ||b||_2 recomputed in FP64 at exit */
+    double spmv_ms;         /* timing = 1: summed duration of the timed SpMV launches */
+    int32_t spmv_calls;     /* timing = 1: number of SpMV launches that ran and were timed */
+    int32_t reserved;
 } spcg_cg_result;
 
 /* Fill opts with defaults: tol 1e-10, maxit 20000, Jacobi, FP64, adaptive checks, delta 0.1. */

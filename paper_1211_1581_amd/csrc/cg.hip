@@ -2,11 +2,10 @@
 // Sec. 3.4: per pass one SpMV, two inner products and three vector updates).
 //
 // Schedule of one pass (FP64 Jacobi-PCG; the scalars never leave the device):
-//   K1  q = A p            SpMV with p.q folded into the row epilogue;
-//                          the last workgroup forms sigma and alpha = rho/sigma
-//   K2  x += alpha p, r -= alpha q, z = D^-1 r   (z not stored)
-//                          partials r.z and r.r; the last workgroup forms
-//                          beta, the history entry and the stop decision
+//   K1  q = A p            SpMV with p.q folded into the row epilogue
+//   F1  sigma = sum of K1's partials, alpha = rho / sigma   (one workgroup)
+//   K2  x += alpha p, r -= alpha q, z = D^-1 r   (z not stored); partials r.z, r.r
+//   F2  rho', ||r||^2 -> beta, history entry, stop decision  (one workgroup)
 //   K3  p = D^-1 r + beta p
 // Every kernel carries the pass number it belongs to and does nothing unless
 // the device state is at that pass and running, so the host can enqueue a
@@ -25,6 +24,8 @@
 
 #include <algorithm>
 #include <cmath>
+
+#include <hip/hip_ext.h>
 
 #include "internal.h"
 
@@ -67,11 +68,9 @@ __device__ __forceinline__ void set_break(CgState *s, double v) {
 }
 
 // ------------------------------------------------------------- set-up --
+// ------------------------------------------------------------- set-up --
 
-__global__ void k_init_state(CgState *st, unsigned *cnt_d, int ncnt_d, unsigned *cnt_f, int ncnt_f,
-                             int maxit, double delta, int budget) {
-    for (int i = threadIdx.x; i < ncnt_d; i += blockDim.x) cnt_d[i] = 0u;
-    for (int i = threadIdx.x; i < ncnt_f; i += blockDim.x) cnt_f[i] = 0u;
+__global__ void k_init_state(CgState *st, int maxit, double delta, int budget) {
     if (threadIdx.x == 0) {
         CgState s;
         memset(&s, 0, sizeof s);
@@ -82,11 +81,9 @@ __global__ void k_init_state(CgState *st, unsigned *cnt_d, int ncnt_d, unsigned 
     }
 }
 
-// state fields for a new phase (restart / fallback): keep nb, thresh, k
-__global__ void k_phase_state(CgState *st, int maxit, int budget) {
+// state fields for a restart from the true residual: keep nb, thresh, k
+__global__ void k_phase_state(CgState *st) {
     if (threadIdx.x == 0) {
-        st->maxit = maxit;
-        st->budget = budget;
         st->halt = RUN;
         st->status = SPCG_OK;
     }
@@ -147,47 +144,54 @@ struct EpiResid {
     }
 };
 
-// Every row belongs to exactly one row block, so r is fully written.
-__global__ void __launch_bounds__(kBlock)
+// r = b - A x (and r32 = fl32(r)); partials (b.b, r.r).  Every row belongs to
+// exactly one row block, so r is fully written.
+SPCG_ROWBLOCK_KERNEL
 k_resid(CsrDev A, const double *__restrict__ vals, const double *__restrict__ x,
-        const double *__restrict__ b, double *__restrict__ r, float *__restrict__ r32, CgState *st,
-        Reduce<double> R, double *hist, int mode, double tol) {
+        const double *__restrict__ b, double *__restrict__ r, float *__restrict__ r32,
+        const CgState *st, double *part, int mode) {
     __shared__ SpmvSmem<double> sm;
     if (mode == R_REPLACE && st->halt != H_REPLACE) return;
-    const int blk = xcd_remap(blockIdx.x, A.n_blocks);
+    int bs, be;
+    const int slot = block_range(A.n_blocks, bs, be);
     EpiResid epi{b, r, r32, 0.0, 0.0};
-    spmv_block<double, double, double>(A, vals, x, blk, sm, epi);
+    for (int k = bs; k < be; ++k) spmv_block<double, double, double>(A, vals, x, k, sm, epi);
     const double v[2] = {block_sum(epi.bb, sm.red), block_sum(epi.rr, sm.red)};
-    auto fin = [&](double(&t)[2]) {
-        if (mode == R_INIT) {
-            st->nb = sqrt(t[0]);
-            st->thresh = tol * st->nb;
-            st->rr = t[1];
-            st->rlast = sqrt(t[1]);
-            if (!(t[0] > 0.0)) {
-                if (finite_d(t[0])) st->halt = H_ZERO;
-                else set_break(st, t[0]);
-            } else if (!finite_d(t[1])) {
-                set_break(st, t[1]);
-            }
-        } else if (mode == R_TRUE) {
-            st->true_rr = t[1];
-        } else {
-            st->rlast = sqrt(t[1]);
-            st->r2_64 = t[1];
-            st->n_updates += 1;
-            hist[st->k] = st->rlast / st->nb;
-        }
-    };
-    reduce_arrive<2>(v, blk, A.n_blocks, R, fin);
+    store_partials(part, slot, v);
 }
 
-// z = M^-1 r, p = z, rho = r.z  (start of a phase; r and rr are set)
+__global__ void __launch_bounds__(kFinThreads)
+k_fin_resid(CgState *st, const double *part, int nslots, double *hist, int mode, double tol) {
+    if (mode == R_REPLACE && st->halt != H_REPLACE) return;
+    double t[2];
+    finalize_sum(part, nslots, t);
+    if (threadIdx.x != 0) return;
+    if (mode == R_INIT) {
+        st->nb = sqrt(t[0]);
+        st->thresh = tol * st->nb;
+        st->rr = t[1];
+        st->rlast = sqrt(t[1]);
+        if (!(t[0] > 0.0)) {
+            if (finite_d(t[0])) st->halt = H_ZERO;
+            else set_break(st, t[0]);
+        } else if (!finite_d(t[1])) {
+            set_break(st, t[1]);
+        }
+    } else if (mode == R_TRUE) {
+        st->true_rr = t[1];
+    } else {
+        st->rlast = sqrt(t[1]);
+        st->r2_64 = t[1];
+        st->n_updates += 1;
+        hist[st->k] = st->rlast / st->nb;
+    }
+}
+
+// z = M^-1 r, p = z; partials (r.z, r.r)  (start of a phase; r is set)
 template <int PRE>
 __global__ void __launch_bounds__(kBlock)
 k_start(int n, const double *__restrict__ r, const double *__restrict__ dinv,
-        const double *__restrict__ zin, double *__restrict__ p, CgState *st, Reduce<double> R,
-        double *hist) {
+        const double *__restrict__ zin, double *__restrict__ p, const CgState *st, double *part) {
     __shared__ double red[4];
     if (st->halt != RUN) return;
     double rz = 0.0, rr = 0.0;
@@ -206,16 +210,22 @@ k_start(int n, const double *__restrict__ r, const double *__restrict__ dinv,
         }
     }
     const double v[2] = {block_sum(rz, red), block_sum(rr, red)};
-    auto fin = [&](double(&t)[2]) {
-        st->rho = t[0];
-        st->rr = t[1];
-        hist[st->k] = sqrt(t[1]) / st->nb;
-        if (!finite_d(t[0]) || !finite_d(t[1])) set_break(st, NAN);
-        else if (sqrt(t[1]) <= st->thresh) st->halt = H_CONV;
-        else if (!(t[0] > 0.0)) set_break(st, t[0]);
-        else if (st->k >= st->maxit) st->halt = H_MAXIT;
-    };
-    reduce_arrive<2>(v, blockIdx.x, gridDim.x, R, fin);
+    store_partials(part, blockIdx.x, v);
+}
+
+__global__ void __launch_bounds__(kFinThreads)
+k_fin_start(CgState *st, const double *part, int nslots, double *hist) {
+    if (st->halt != RUN) return;
+    double t[2];
+    finalize_sum(part, nslots, t);
+    if (threadIdx.x != 0) return;
+    st->rho = t[0];
+    st->rr = t[1];
+    hist[st->k] = sqrt(t[1]) / st->nb;
+    if (!finite_d(t[0]) || !finite_d(t[1])) set_break(st, NAN);
+    else if (sqrt(t[1]) <= st->thresh) st->halt = H_CONV;
+    else if (!(t[0] > 0.0)) set_break(st, t[0]);
+    else if (st->k >= st->maxit) st->halt = H_MAXIT;
 }
 
 // ------------------------------------------------------ one CG pass --
@@ -231,37 +241,45 @@ struct EpiPQ {
     }
 };
 
-// K1: q = A p, sigma = p.q, alpha = rho / sigma
+// K1: q = A p; partial p.q
 template <typename TV, typename T>
-__global__ void __launch_bounds__(kBlock)
+SPCG_ROWBLOCK_KERNEL
 k_cg_q(CsrDev A, const TV *__restrict__ vals, const T *__restrict__ p, T *__restrict__ q,
-       CgState *st, Reduce<T> R, int expect) {
+       const CgState *st, T *part, int expect) {
     __shared__ SpmvSmem<T> sm;
     if (st->halt != RUN || st->k != expect) return;
-    const int blk = xcd_remap(blockIdx.x, A.n_blocks);
+    int bs, be;
+    const int slot = block_range(A.n_blocks, bs, be);
     EpiPQ<T> epi{q, p, T(0)};
-    spmv_block<TV, T, T>(A, vals, p, blk, sm, epi);
+    for (int k = bs; k < be; ++k) spmv_block<TV, T, T>(A, vals, p, k, sm, epi);
     const T v[1] = {block_sum(epi.acc, sm.red)};
-    auto fin = [&](T(&t)[1]) {
-        const T sigma = t[0];
-        if (!(sigma > T(0)) || !finite_d((double)sigma)) {
-            set_break(st, (double)sigma);
-        } else if constexpr (sizeof(T) == 8) {
-            st->alpha = st->rho / sigma;
-        } else {
-            st->alpha32 = st->rho32 / sigma;
-        }
-    };
-    reduce_arrive<1>(v, blk, A.n_blocks, R, fin);
+    store_partials(part, slot, v);
+}
+
+// F1: sigma = p.q, alpha = rho / sigma
+template <typename T>
+__global__ void __launch_bounds__(kFinThreads)
+k_fin_q(CgState *st, const T *part, int nslots, int expect) {
+    if (st->halt != RUN || st->k != expect) return;
+    T t[1];
+    finalize_sum(part, nslots, t);
+    if (threadIdx.x != 0) return;
+    const T sigma = t[0];
+    if (!(sigma > T(0)) || !finite_d((double)sigma)) {
+        set_break(st, (double)sigma);
+    } else if constexpr (sizeof(T) == 8) {
+        st->alpha = st->rho / sigma;
+    } else {
+        st->alpha32 = st->rho32 / sigma;
+    }
 }
 
 // K2: x += alpha p, r -= alpha q, z = M^-1 r; partials (r.z, r.r).
-// PRE = LEARNED: only r.r here (z comes from two SpMVs).  MIXED = FP32 inner.
-template <typename T, int PRE, bool MIXED>
+// PRE = LEARNED: r.r only (z comes from two SpMVs).  T = float: mixed inner.
+template <typename T, int PRE>
 __global__ void __launch_bounds__(kBlock)
 k_cg_xr(int n, int expect, T *__restrict__ x, T *__restrict__ r, const T *__restrict__ p,
-        const T *__restrict__ q, const T *__restrict__ dinv, CgState *st, Reduce<T> R,
-        double *hist) {
+        const T *__restrict__ q, const T *__restrict__ dinv, const CgState *st, T *part) {
     __shared__ T red[4];
     if (st->halt != RUN || st->k != expect) return;
     const T alpha = st_alpha<T>(st);
@@ -280,40 +298,48 @@ k_cg_xr(int n, int expect, T *__restrict__ x, T *__restrict__ r, const T *__rest
     }
     if constexpr (PRE == SPCG_PRECOND_NONE) rz = rr;
     const T v[2] = {block_sum(rz, red), block_sum(rr, red)};
-    auto fin = [&](T(&t)[2]) {
-        const int k = expect + 1;
-        st->k = k;
-        const double rrd = (double)t[1];
-        const double est = sqrt(rrd);
-        hist[k] = est / st->nb;
-        if (!finite_d((double)t[0]) || !finite_d(rrd)) {
-            set_break(st, NAN);
+    store_partials(part, blockIdx.x, v);
+}
+
+// F2: pass count, history, stop decision, beta and rho
+template <typename T, int PRE, bool MIXED>
+__global__ void __launch_bounds__(kFinThreads)
+k_fin_xr(CgState *st, const T *part, int nslots, double *hist, int expect) {
+    if (st->halt != RUN || st->k != expect) return;
+    T t[2];
+    finalize_sum(part, nslots, t);
+    if (threadIdx.x != 0) return;
+    const int k = expect + 1;
+    st->k = k;
+    const double rrd = (double)t[1];
+    const double est = sqrt(rrd);
+    hist[k] = est / st->nb;
+    if (!finite_d((double)t[0]) || !finite_d(rrd)) {
+        set_break(st, NAN);
+        return;
+    }
+    if constexpr (PRE != SPCG_PRECOND_LEARNED) {
+        if (rrd > 0.0 && !(t[0] > T(0))) {
+            set_break(st, (double)t[0]);
             return;
         }
+    }
+    if constexpr (MIXED) {
+        st->beta32 = t[0] / st->rho32;
+        st->rho32 = t[0];
+        st->rr32 = t[1];
+        if (est < st->delta * st->rlast || est <= st->thresh || k >= st->maxit)
+            st->halt = H_REPLACE;
+    } else {
+        st->rr = rrd;
         if constexpr (PRE != SPCG_PRECOND_LEARNED) {
-            if (rrd > 0.0 && !(t[0] > T(0))) {
-                set_break(st, (double)t[0]);
-                return;
-            }
+            st->beta = (double)t[0] / st->rho;
+            st->rho = (double)t[0];
         }
-        if constexpr (MIXED) {
-            st->beta32 = t[0] / st->rho32;
-            st->rho32 = t[0];
-            st->rr32 = t[1];
-            if (est < st->delta * st->rlast || est <= st->thresh || k >= st->maxit)
-                st->halt = H_REPLACE;
-        } else {
-            st->rr = rrd;
-            if constexpr (PRE != SPCG_PRECOND_LEARNED) {
-                st->beta = (double)t[0] / st->rho;
-                st->rho = (double)t[0];
-            }
-            if (est <= st->thresh) st->halt = H_CONV;
-            else if (k >= st->maxit) st->halt = H_MAXIT;
-            else if (PRE == SPCG_PRECOND_LEARNED && k >= st->budget) st->halt = H_BUDGET;
-        }
-    };
-    reduce_arrive<2>(v, blockIdx.x, gridDim.x, R, fin);
+        if (est <= st->thresh) st->halt = H_CONV;
+        else if (k >= st->maxit) st->halt = H_MAXIT;
+        else if (PRE == SPCG_PRECOND_LEARNED && k >= st->budget) st->halt = H_BUDGET;
+    }
 }
 
 // K3: p = z + beta p  (z = D^-1 r, r, or the stored z)
@@ -339,21 +365,21 @@ k_cg_p(int n, int expect, const T *__restrict__ r, const T *__restrict__ dinv,
 
 // ------------------------------------------- learned: z = G (G^T r) --
 
-template <typename TV, typename T>
-struct EpiStoreT {
-    T *__restrict__ y;
-    __device__ __forceinline__ void row(int i, T s) { y[i] = s; }
+struct EpiStore64 {
+    double *__restrict__ y;
+    __device__ __forceinline__ void row(int i, double s) { y[i] = s; }
 };
 
-// t = G^T r  (runs in a pass after K2, or at a phase start when expect < 0)
-__global__ void __launch_bounds__(kBlock)
+// t = G^T r  (in a pass after K2, or at a phase start when expect < 0)
+SPCG_ROWBLOCK_KERNEL
 k_gt_apply(CsrDev GT, const float *__restrict__ vals, const double *__restrict__ r,
            double *__restrict__ t, const CgState *st, int expect) {
     __shared__ SpmvSmem<double> sm;
     if (st->halt != RUN || (expect >= 0 && st->k != expect + 1)) return;
-    const int blk = xcd_remap(blockIdx.x, GT.n_blocks);
-    EpiStoreT<float, double> epi{t};
-    spmv_block<float, double, double>(GT, vals, r, blk, sm, epi);
+    int bs, be;
+    block_range(GT.n_blocks, bs, be);
+    EpiStore64 epi{t};
+    for (int k = bs; k < be; ++k) spmv_block<float, double, double>(GT, vals, r, k, sm, epi);
 }
 
 struct EpiZ {
@@ -366,28 +392,35 @@ struct EpiZ {
     }
 };
 
-// z = G t, rho' = r.z, beta = rho'/rho  (expect < 0: phase start, only z)
-__global__ void __launch_bounds__(kBlock)
-k_g_apply_rz(CsrDev G, const float *__restrict__ vals, const double *__restrict__ t,
-             const double *__restrict__ r, double *__restrict__ z, CgState *st, Reduce<double> R,
-             int expect) {
+// z = G t; partial r.z
+SPCG_ROWBLOCK_KERNEL
+k_g_apply(CsrDev G, const float *__restrict__ vals, const double *__restrict__ t,
+          const double *__restrict__ r, double *__restrict__ z, const CgState *st, double *part,
+          int expect) {
     __shared__ SpmvSmem<double> sm;
     if (st->halt != RUN || (expect >= 0 && st->k != expect + 1)) return;
-    const int blk = xcd_remap(blockIdx.x, G.n_blocks);
+    int bs, be;
+    const int slot = block_range(G.n_blocks, bs, be);
     EpiZ epi{z, r, 0.0};
-    spmv_block<float, double, double>(G, vals, t, blk, sm, epi);
-    if (expect < 0) return;
+    for (int k = bs; k < be; ++k) spmv_block<float, double, double>(G, vals, t, k, sm, epi);
     const double v[1] = {block_sum(epi.acc, sm.red)};
-    auto fin = [&](double(&s)[1]) {
-        const double rho = s[0];
-        if (!finite_d(rho)) set_break(st, NAN);
-        else if (st->rr > 0.0 && !(rho > 0.0)) set_break(st, rho);
-        else {
-            st->beta = rho / st->rho;
-            st->rho = rho;
-        }
-    };
-    reduce_arrive<1>(v, blk, G.n_blocks, R, fin);
+    store_partials(part, slot, v);
+}
+
+// rho' = r.z, beta = rho' / rho
+__global__ void __launch_bounds__(kFinThreads)
+k_fin_grz(CgState *st, const double *part, int nslots, int expect) {
+    if (st->halt != RUN || st->k != expect + 1) return;
+    double s[1];
+    finalize_sum(part, nslots, s);
+    if (threadIdx.x != 0) return;
+    const double rho = s[0];
+    if (!finite_d(rho)) set_break(st, NAN);
+    else if (st->rr > 0.0 && !(rho > 0.0)) set_break(st, rho);
+    else {
+        st->beta = rho / st->rho;
+        st->rho = rho;
+    }
 }
 
 // ------------------------------------------------------------ mixed --
@@ -407,11 +440,10 @@ k_mp_fold(int n, double *__restrict__ x, float *__restrict__ x32, const CgState 
     }
 }
 
-// z32 = dinv32 r32, rho32 = r32.z32 (FP32); init: p32 = z32 as well.
-// Ends the replacement: converged, out of passes, or running again.
+// z32 = dinv32 r32; partial r32.z32 (FP32); init: p32 = z32 as well
 __global__ void __launch_bounds__(kBlock)
 k_mp_rz(int n, const float *__restrict__ r32, const float *__restrict__ dinv32,
-        float *__restrict__ p32, CgState *st, Reduce<float> R, double *hist, int init) {
+        float *__restrict__ p32, const CgState *st, float *part, int init) {
     __shared__ float red[4];
     if (init ? st->halt != RUN : st->halt != H_REPLACE) return;
     float rz = 0.0f;
@@ -427,16 +459,23 @@ k_mp_rz(int n, const float *__restrict__ r32, const float *__restrict__ dinv32,
         }
     }
     const float v[1] = {block_sum(rz, red)};
-    auto fin = [&](float(&t)[1]) {
-        st->rho32 = t[0];
-        if (init) hist[st->k] = st->rlast / st->nb;
-        if (!finite_d((double)t[0]) || !finite_d(st->rlast)) set_break(st, NAN);
-        else if (st->rlast <= st->thresh) st->halt = H_CONV;
-        else if (!(t[0] > 0.0f)) set_break(st, (double)t[0]);
-        else if (st->k >= st->maxit) st->halt = H_MAXIT;
-        else st->halt = RUN;
-    };
-    reduce_arrive<1>(v, blockIdx.x, gridDim.x, R, fin);
+    store_partials(part, blockIdx.x, v);
+}
+
+// Ends a replacement (or the start): converged, out of passes, or running.
+__global__ void __launch_bounds__(kFinThreads)
+k_fin_mprz(CgState *st, const float *part, int nslots, double *hist, int init) {
+    if (init ? st->halt != RUN : st->halt != H_REPLACE) return;
+    float t[1];
+    finalize_sum(part, nslots, t);
+    if (threadIdx.x != 0) return;
+    st->rho32 = t[0];
+    if (init) hist[st->k] = st->rlast / st->nb;
+    if (!finite_d((double)t[0]) || !finite_d(st->rlast)) set_break(st, NAN);
+    else if (st->rlast <= st->thresh) st->halt = H_CONV;
+    else if (!(t[0] > 0.0f)) set_break(st, (double)t[0]);
+    else if (st->k >= st->maxit) st->halt = H_MAXIT;
+    else st->halt = RUN;
 }
 
 // ------------------------------------- single-workgroup solver (small n) --
@@ -536,16 +575,16 @@ struct Work {
     double *hist;
     double *r, *p, *q, *dinv, *z, *t, *x0;
     float *r32, *p32, *q32, *x32, *dinv32, *vals32;
-    Reduce<double> Rd;
-    Reduce<float> Rf;
+    double *partd;  // [nslots * 2]
+    float *partf;   // [nslots * 2]
     int64_t nslots;
 };
 
 static int64_t n_slots(const spcg_csr *A, const spcg_cg_opts *o) {
-    int64_t s = std::max<int64_t>(A->n_blocks, vec_blocks(A->n_rows));
+    int64_t s = std::max<int64_t>(spmv_grid(A->n_blocks), vec_blocks(A->n_rows));
     if (o->precond == SPCG_PRECOND_LEARNED) {
-        if (o->G) s = std::max<int64_t>(s, o->G->n_blocks);
-        if (o->GT) s = std::max<int64_t>(s, o->GT->n_blocks);
+        if (o->G) s = std::max<int64_t>(s, spmv_grid(o->G->n_blocks));
+        if (o->GT) s = std::max<int64_t>(s, spmv_grid(o->GT->n_blocks));
     }
     return std::max<int64_t>(s, 1);
 }
@@ -554,16 +593,15 @@ static size_t carve(const spcg_csr *A, const spcg_cg_opts *o, char *base, Work *
     const int64_t n = A->n_rows;
     const bool mixed = o->precision == SPCG_PREC_MIXED;
     const bool learned = o->precond == SPCG_PRECOND_LEARNED;
-    char *p = base;
+    size_t off = 0;
     auto take = [&](size_t bytes) {
-        char *q = p;
-        p += align256(bytes);
+        char *q = base ? base + off : nullptr;
+        off += align256(bytes);
         return q;
     };
-    const int64_t ns = n_slots(A, o);
     Work W;
     memset(&W, 0, sizeof W);
-    W.nslots = ns;
+    W.nslots = n_slots(A, o);
     W.st = (CgState *)take(sizeof(CgState));
     W.hist = (double *)take(sizeof(double) * ((size_t)std::max(o->maxit, 0) + 1));
     W.r = (double *)take(sizeof(double) * n);
@@ -585,15 +623,10 @@ static size_t carve(const spcg_csr *A, const spcg_cg_opts *o, char *base, Work *
         W.dinv32 = (float *)take(sizeof(float) * n);
         W.vals32 = (float *)take(sizeof(float) * (size_t)A->nnz);
     }
-    // reductions (carved without the take() rounding, which they do themselves)
-    if (base) {
-        W.Rd = reduce_carve<double>(p, ns, 2);
-        W.Rf = reduce_carve<float>(p, ns, 2);
-    } else {
-        p += reduce_bytes<double>(ns, 2) + reduce_bytes<float>(ns, 2);
-    }
+    W.partd = (double *)take(sizeof(double) * 2 * W.nslots);
+    W.partf = (float *)take(sizeof(float) * 2 * W.nslots);
     if (w) *w = W;
-    return (size_t)(p - base);
+    return off;
 }
 
 static unsigned grid_of(int64_t n, int per) { return (unsigned)std::max<int64_t>((n + per - 1) / per, 1); }
@@ -606,19 +639,73 @@ struct Solver {
     CgState *h;  // pinned host copy
     double *x;
     const double *b;
+    // timing mode: event pair per pass-loop SpMV launch, with its pass number
+    bool timing = false;
+    int n_timed = 0;
+    int *timed_k = nullptr;
+
+    int ensure_events(int pairs) {
+        if (A->n_events >= 2 * pairs) return SPCG_OK;
+        const int want = 2 * pairs;
+        hipEvent_t *ev = new hipEvent_t[want];
+        for (int i = 0; i < A->n_events; ++i) ev[i] = A->events[i];
+        for (int i = A->n_events; i < want; ++i) {
+            hipError_t e = hipEventCreate(&ev[i]);
+            if (e != hipSuccess) {
+                for (int j = A->n_events; j < i; ++j) (void)hipEventDestroy(ev[j]);
+                delete[] ev;
+                return hip_status(e, "hipEventCreate");
+            }
+        }
+        delete[] A->events;
+        A->events = ev;
+        A->n_events = want;
+        return SPCG_OK;
+    }
+    int cap_timed = 0;
+    int grow_timed(int need) {
+        if (need <= cap_timed) return SPCG_OK;
+        const int cap = std::max(need, 2 * cap_timed);
+        int *t = new int[cap];
+        for (int i = 0; i < n_timed; ++i) t[i] = timed_k[i];
+        delete[] timed_k;
+        timed_k = t;
+        cap_timed = cap;
+        return SPCG_OK;
+    }
+    ~Solver() { delete[] timed_k; }
+    // summed duration of the timed launches whose pass actually ran (k < k_end)
+    void collect(int k_end, spcg_cg_result *res) {
+        float tot = 0.0f;
+        int calls = 0;
+        for (int i = 0; i < n_timed; ++i) {
+            if (timed_k[i] >= k_end) continue;
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, A->events[2 * i], A->events[2 * i + 1]) == hipSuccess) {
+                tot += ms;
+                ++calls;
+            }
+        }
+        res->spmv_ms += tot;
+        res->spmv_calls += calls;
+        n_timed = 0;
+    }
 
     int read_state() {
         SPCG_TRY(hipMemcpyAsync(h, w.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
         SPCG_TRY(hipStreamSynchronize(s));
         return SPCG_OK;
     }
-    int64_t ncnt(int64_t ns) const { return (ns + kGroup - 1) / kGroup + 1; }
+    unsigned gv() const { return grid_of(A->n_rows, kVecBlock); }
+    unsigned gA() const { return spmv_grid(A->n_blocks); }
+    unsigned gG() const { return spmv_grid(o->G->n_blocks); }
+    unsigned gGT() const { return spmv_grid(o->GT->n_blocks); }
 
     int resid(int mode, float *r32) {
-        if (A->n_rows == 0) return SPCG_OK;
-        hipLaunchKernelGGL(k_resid, dim3((unsigned)A->n_blocks), dim3(kBlock), 0, s, dev_view(A),
-                           (const double *)A->vals, x, b, w.r, r32, w.st, w.Rd, w.hist, mode,
-                           o->tol);
+        hipLaunchKernelGGL(k_resid, dim3(gA()), dim3(kBlock), 0, s, dev_view(A),
+                           (const double *)A->vals, x, b, w.r, r32, w.st, w.partd, mode);
+        hipLaunchKernelGGL(k_fin_resid, dim3(1), dim3(kFinThreads), 0, s, w.st,
+                           (const double *)w.partd, (int)gA(), w.hist, mode, o->tol);
         SPCG_LAUNCH_CHECK("k_resid");
         return SPCG_OK;
     }
@@ -626,100 +713,132 @@ struct Solver {
     // z = M^-1 r, p = z, rho; the phase's first history entry
     int start(int pre) {
         const int n = A->n_rows;
-        const unsigned gv = grid_of(n, kVecBlock);
         if (pre == SPCG_PRECOND_LEARNED) {
-            hipLaunchKernelGGL(k_gt_apply, dim3((unsigned)o->GT->n_blocks), dim3(kBlock), 0, s,
+            hipLaunchKernelGGL(k_gt_apply, dim3(gGT()), dim3(kBlock), 0, s,
                                dev_view(o->GT), (const float *)o->GT->vals, (const double *)w.r,
                                w.t, w.st, -1);
-            SPCG_LAUNCH_CHECK("k_gt_apply");
-            hipLaunchKernelGGL(k_g_apply_rz, dim3((unsigned)o->G->n_blocks), dim3(kBlock), 0, s,
+            hipLaunchKernelGGL(k_g_apply, dim3(gG()), dim3(kBlock), 0, s,
                                dev_view(o->G), (const float *)o->G->vals, (const double *)w.t,
-                               (const double *)w.r, w.z, w.st, w.Rd, -1);
-            SPCG_LAUNCH_CHECK("k_g_apply_rz");
-            hipLaunchKernelGGL(k_start<SPCG_PRECOND_LEARNED>, dim3(gv), dim3(kBlock), 0, s, n,
-                               w.r, w.dinv, w.z, w.p, w.st, w.Rd, w.hist);
+                               (const double *)w.r, w.z, w.st, w.partd, -1);
+            hipLaunchKernelGGL(k_start<SPCG_PRECOND_LEARNED>, dim3(gv()), dim3(kBlock), 0, s, n,
+                               w.r, w.dinv, w.z, w.p, w.st, w.partd);
         } else if (pre == SPCG_PRECOND_JACOBI) {
-            hipLaunchKernelGGL(k_start<SPCG_PRECOND_JACOBI>, dim3(gv), dim3(kBlock), 0, s, n, w.r,
-                               w.dinv, w.z, w.p, w.st, w.Rd, w.hist);
+            hipLaunchKernelGGL(k_start<SPCG_PRECOND_JACOBI>, dim3(gv()), dim3(kBlock), 0, s, n,
+                               w.r, w.dinv, w.z, w.p, w.st, w.partd);
         } else {
-            hipLaunchKernelGGL(k_start<SPCG_PRECOND_NONE>, dim3(gv), dim3(kBlock), 0, s, n, w.r,
-                               w.dinv, w.z, w.p, w.st, w.Rd, w.hist);
+            hipLaunchKernelGGL(k_start<SPCG_PRECOND_NONE>, dim3(gv()), dim3(kBlock), 0, s, n,
+                               w.r, w.dinv, w.z, w.p, w.st, w.partd);
         }
+        hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(kFinThreads), 0, s, w.st,
+                           (const double *)w.partd, (int)gv(), w.hist);
         SPCG_LAUNCH_CHECK("k_start");
         return SPCG_OK;
     }
 
-    int pass64(int pre, int expect) {
+    int pass64(int pre, int e) {
         const int n = A->n_rows;
-        const unsigned gv = grid_of(n, kVecBlock);
-        hipLaunchKernelGGL((k_cg_q<double, double>), dim3((unsigned)A->n_blocks), dim3(kBlock), 0,
-                           s, dev_view(A), (const double *)A->vals, (const double *)w.p, w.q, w.st,
-                           w.Rd, expect);
-        if (pre == SPCG_PRECOND_JACOBI) {
-            hipLaunchKernelGGL((k_cg_xr<double, SPCG_PRECOND_JACOBI, false>), dim3(gv),
-                               dim3(kBlock), 0, s, n, expect, x, w.r, w.p, w.q, w.dinv, w.st, w.Rd,
-                               w.hist);
-            hipLaunchKernelGGL((k_cg_p<double, SPCG_PRECOND_JACOBI>), dim3(gv), dim3(kBlock), 0, s,
-                               n, expect, w.r, w.dinv, w.z, w.p, w.st);
-        } else if (pre == SPCG_PRECOND_NONE) {
-            hipLaunchKernelGGL((k_cg_xr<double, SPCG_PRECOND_NONE, false>), dim3(gv), dim3(kBlock),
-                               0, s, n, expect, x, w.r, w.p, w.q, w.dinv, w.st, w.Rd, w.hist);
-            hipLaunchKernelGGL((k_cg_p<double, SPCG_PRECOND_NONE>), dim3(gv), dim3(kBlock), 0, s,
-                               n, expect, w.r, w.dinv, w.z, w.p, w.st);
+        const double *pd = w.partd;
+        if (timing) {
+            hipExtLaunchKernelGGL((k_cg_q<double, double>), dim3(gA()), dim3(kBlock), 0, s,
+                                  A->events[2 * n_timed], A->events[2 * n_timed + 1], 0,
+                                  dev_view(A), (const double *)A->vals, (const double *)w.p, w.q,
+                                  w.st, w.partd, e);
+            timed_k[n_timed++] = e;
         } else {
-            hipLaunchKernelGGL((k_cg_xr<double, SPCG_PRECOND_LEARNED, false>), dim3(gv),
-                               dim3(kBlock), 0, s, n, expect, x, w.r, w.p, w.q, w.dinv, w.st, w.Rd,
-                               w.hist);
-            hipLaunchKernelGGL(k_gt_apply, dim3((unsigned)o->GT->n_blocks), dim3(kBlock), 0, s,
+            hipLaunchKernelGGL((k_cg_q<double, double>), dim3(gA()), dim3(kBlock), 0, s,
+                               dev_view(A), (const double *)A->vals, (const double *)w.p, w.q,
+                               w.st, w.partd, e);
+        }
+        hipLaunchKernelGGL(k_fin_q<double>, dim3(1), dim3(kFinThreads), 0, s, w.st, pd, (int)gA(), e);
+        if (pre == SPCG_PRECOND_JACOBI) {
+            hipLaunchKernelGGL((k_cg_xr<double, SPCG_PRECOND_JACOBI>), dim3(gv()), dim3(kBlock), 0,
+                               s, n, e, x, w.r, w.p, w.q, w.dinv, w.st, w.partd);
+            hipLaunchKernelGGL((k_fin_xr<double, SPCG_PRECOND_JACOBI, false>), dim3(1),
+                               dim3(kFinThreads), 0, s, w.st, pd, (int)gv(), w.hist, e);
+            hipLaunchKernelGGL((k_cg_p<double, SPCG_PRECOND_JACOBI>), dim3(gv()), dim3(kBlock), 0,
+                               s, n, e, w.r, w.dinv, w.z, w.p, w.st);
+        } else if (pre == SPCG_PRECOND_NONE) {
+            hipLaunchKernelGGL((k_cg_xr<double, SPCG_PRECOND_NONE>), dim3(gv()), dim3(kBlock), 0, s,
+                               n, e, x, w.r, w.p, w.q, w.dinv, w.st, w.partd);
+            hipLaunchKernelGGL((k_fin_xr<double, SPCG_PRECOND_NONE, false>), dim3(1),
+                               dim3(kFinThreads), 0, s, w.st, pd, (int)gv(), w.hist, e);
+            hipLaunchKernelGGL((k_cg_p<double, SPCG_PRECOND_NONE>), dim3(gv()), dim3(kBlock), 0, s,
+                               n, e, w.r, w.dinv, w.z, w.p, w.st);
+        } else {
+            hipLaunchKernelGGL((k_cg_xr<double, SPCG_PRECOND_LEARNED>), dim3(gv()), dim3(kBlock),
+                               0, s, n, e, x, w.r, w.p, w.q, w.dinv, w.st, w.partd);
+            hipLaunchKernelGGL((k_fin_xr<double, SPCG_PRECOND_LEARNED, false>), dim3(1),
+                               dim3(kFinThreads), 0, s, w.st, pd, (int)gv(), w.hist, e);
+            hipLaunchKernelGGL(k_gt_apply, dim3(gGT()), dim3(kBlock), 0, s,
                                dev_view(o->GT), (const float *)o->GT->vals, (const double *)w.r,
-                               w.t, w.st, expect);
-            hipLaunchKernelGGL(k_g_apply_rz, dim3((unsigned)o->G->n_blocks), dim3(kBlock), 0, s,
+                               w.t, w.st, e);
+            hipLaunchKernelGGL(k_g_apply, dim3(gG()), dim3(kBlock), 0, s,
                                dev_view(o->G), (const float *)o->G->vals, (const double *)w.t,
-                               (const double *)w.r, w.z, w.st, w.Rd, expect);
-            hipLaunchKernelGGL((k_cg_p<double, SPCG_PRECOND_LEARNED>), dim3(gv), dim3(kBlock), 0,
-                               s, n, expect, w.r, w.dinv, w.z, w.p, w.st);
+                               (const double *)w.r, w.z, w.st, w.partd, e);
+            hipLaunchKernelGGL(k_fin_grz, dim3(1), dim3(kFinThreads), 0, s, w.st, pd,
+                               (int)gG(), e);
+            hipLaunchKernelGGL((k_cg_p<double, SPCG_PRECOND_LEARNED>), dim3(gv()), dim3(kBlock),
+                               0, s, n, e, w.r, w.dinv, w.z, w.p, w.st);
         }
         SPCG_LAUNCH_CHECK("cg pass");
         return SPCG_OK;
     }
 
-    int pass32(int expect) {
+    int pass32(int e) {
         const int n = A->n_rows;
-        const unsigned gv = grid_of(n, kVecBlock);
-        hipLaunchKernelGGL((k_cg_q<float, float>), dim3((unsigned)A->n_blocks), dim3(kBlock), 0, s,
-                           dev_view(A), (const float *)w.vals32, (const float *)w.p32, w.q32, w.st,
-                           w.Rf, expect);
-        hipLaunchKernelGGL((k_cg_xr<float, SPCG_PRECOND_JACOBI, true>), dim3(gv), dim3(kBlock), 0,
-                           s, n, expect, w.x32, w.r32, w.p32, w.q32, w.dinv32, w.st, w.Rf, w.hist);
-        hipLaunchKernelGGL((k_cg_p<float, SPCG_PRECOND_JACOBI>), dim3(gv), dim3(kBlock), 0, s, n,
-                           expect, w.r32, w.dinv32, (const float *)nullptr, w.p32, w.st);
+        const float *pf = w.partf;
+        if (timing) {
+            hipExtLaunchKernelGGL((k_cg_q<float, float>), dim3(gA()), dim3(kBlock), 0, s,
+                                  A->events[2 * n_timed], A->events[2 * n_timed + 1], 0,
+                                  dev_view(A), (const float *)w.vals32, (const float *)w.p32,
+                                  w.q32, w.st, w.partf, e);
+            timed_k[n_timed++] = e;
+        } else {
+            hipLaunchKernelGGL((k_cg_q<float, float>), dim3(gA()), dim3(kBlock), 0, s,
+                               dev_view(A), (const float *)w.vals32, (const float *)w.p32, w.q32,
+                               w.st, w.partf, e);
+        }
+        hipLaunchKernelGGL(k_fin_q<float>, dim3(1), dim3(kFinThreads), 0, s, w.st, pf, (int)gA(), e);
+        hipLaunchKernelGGL((k_cg_xr<float, SPCG_PRECOND_JACOBI>), dim3(gv()), dim3(kBlock), 0, s,
+                           n, e, w.x32, w.r32, w.p32, w.q32, w.dinv32, w.st, w.partf);
+        hipLaunchKernelGGL((k_fin_xr<float, SPCG_PRECOND_JACOBI, true>), dim3(1),
+                           dim3(kFinThreads), 0, s, w.st, pf, (int)gv(), w.hist, e);
+        hipLaunchKernelGGL((k_cg_p<float, SPCG_PRECOND_JACOBI>), dim3(gv()), dim3(kBlock), 0, s, n,
+                           e, w.r32, w.dinv32, (const float *)nullptr, w.p32, w.st);
         SPCG_LAUNCH_CHECK("mixed pass");
         return SPCG_OK;
     }
 
+    int mp_rz(int init) {
+        hipLaunchKernelGGL(k_mp_rz, dim3(gv()), dim3(kBlock), 0, s, A->n_rows, (const float *)w.r32,
+                           (const float *)w.dinv32, w.p32, w.st, w.partf, init);
+        hipLaunchKernelGGL(k_fin_mprz, dim3(1), dim3(kFinThreads), 0, s, w.st,
+                           (const float *)w.partf, (int)gv(), w.hist, init);
+        SPCG_LAUNCH_CHECK("k_mp_rz");
+        return SPCG_OK;
+    }
+
+    // FP64 residual replacement: x64 += x32, r64 = b - A x64, r32 = fl32(r64), rho
     int replace() {
-        const int n = A->n_rows;
-        const unsigned gv = grid_of(n, kVecBlock);
-        hipLaunchKernelGGL(k_mp_fold, dim3(gv), dim3(kBlock), 0, s, n, x, w.x32, w.st, 0);
+        hipLaunchKernelGGL(k_mp_fold, dim3(gv()), dim3(kBlock), 0, s, A->n_rows, x, w.x32, w.st, 0);
         SPCG_LAUNCH_CHECK("k_mp_fold");
         int rc = resid(R_REPLACE, w.r32);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_mp_rz, dim3(gv), dim3(kBlock), 0, s, n, (const float *)w.r32,
-                           (const float *)w.dinv32, w.p32, w.st, w.Rf, w.hist, 0);
-        SPCG_LAUNCH_CHECK("k_mp_rz");
-        return SPCG_OK;
+        return mp_rz(0);
     }
 
     // Run passes until the device state halts.  Batches are sized from the
     // observed residual decay so that few empty passes are enqueued.
     int loop(bool mixed, int pre) {
         int rc;
-        double prev_rr = mixed ? (double)h->rlast * h->rlast : h->rr;
+        double prev_rr = mixed ? h->rlast * h->rlast : h->rr;
         int prev_k = h->k;
         int batch = o->check_every > 0 ? o->check_every : 8;
         while (h->halt == RUN) {
             const int k0 = h->k;
             const int nb = std::min(batch, std::max(h->maxit - k0, 1));
+            if (timing && (rc = ensure_events(n_timed + nb))) return rc;
+            if (timing && (rc = grow_timed(n_timed + nb))) return rc;
             for (int j = 0; j < nb; ++j) {
                 rc = mixed ? pass32(k0 + j) : pass64(pre, k0 + j);
                 if (rc) return rc;
@@ -775,7 +894,7 @@ void spcg_cg_default_opts(spcg_cg_opts *o) {
 
 size_t spcg_cg_workspace_bytes(spcg_csr_t A, const spcg_cg_opts *o) {
     if (!A || !o) return 0;
-    return carve(A, o, nullptr, nullptr) + 256;
+    return carve(A, o, nullptr, nullptr);
 }
 
 int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o, void *d_work,
@@ -798,8 +917,7 @@ int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o
     }
     const int n = A->n_rows;
     if (n > 0 && (!d_b || !d_x)) return SPCG_INVALID_ARG;
-    if (!d_work || ((uintptr_t)d_work & 255) != 0 ||
-        work_bytes < spcg_cg_workspace_bytes(A, o) - 256)
+    if (!d_work || ((uintptr_t)d_work & 255) != 0 || work_bytes < spcg_cg_workspace_bytes(A, o))
         return SPCG_INVALID_ARG;
     if (n == 0) {
         if (h_hist) h_hist[0] = 0.0;
@@ -813,14 +931,13 @@ int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o
     S.x = d_x;
     S.b = d_b;
     S.h = (CgState *)A->h_pinned;
+    S.timing = o->timing != 0;
     static_assert(sizeof(CgState) <= 256, "pinned status buffer");
     carve(A, o, (char *)d_work, &S.w);
     Work &w = S.w;
     int rc;
-    const int64_t ns = w.nslots;
     const int budget = learned ? std::min(o->budget, o->maxit) : o->maxit;
-    hipLaunchKernelGGL(k_init_state, dim3(1), dim3(256), 0, s, w.st, w.Rd.counters,
-                       (int)S.ncnt(ns), w.Rf.counters, (int)S.ncnt(ns), learned ? budget : o->maxit,
+    hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, s, w.st, learned ? budget : o->maxit,
                        o->delta, budget);
     SPCG_LAUNCH_CHECK("k_init_state");
     if (o->precond == SPCG_PRECOND_JACOBI || learned) {
@@ -843,10 +960,7 @@ int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o
     if ((rc = S.resid(R_INIT, mixed ? w.r32 : nullptr))) return rc;
     if ((rc = S.read_state())) return rc;
     CgState *h = S.h;
-    if (h->bad_diag) {
-        rc = (h->bad_diag & 2) ? SPCG_NON_FINITE : SPCG_NOT_SPD;
-        return rc;
-    }
+    if (h->bad_diag) return (h->bad_diag & 2) ? SPCG_NON_FINITE : SPCG_NOT_SPD;
     if (h->halt == H_ZERO) {
         hipLaunchKernelGGL(k_fill<double>, dim3(grid_of(n, kBlock * 8)), dim3(kBlock), 0, s,
                            (int64_t)n, d_x, 0.0);
@@ -857,25 +971,17 @@ int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o
     }
     if (h->halt == H_BREAK) return h->status;
 
-    const int pre0 = o->precond;
     int status = SPCG_OK;
     int restarts = 0;
     bool fell_back = false;
     int learned_iters = 0;
-    int pre = pre0;
-    if (mixed) {
-        hipLaunchKernelGGL(k_mp_rz, dim3(grid_of(n, kVecBlock)), dim3(kBlock), 0, s, n,
-                           (const float *)w.r32, (const float *)w.dinv32, w.p32, w.st, w.Rf,
-                           w.hist, 1);
-        SPCG_LAUNCH_CHECK("k_mp_rz");
-    } else if ((rc = S.start(pre))) {
-        return rc;
-    }
+    int pre = o->precond;
+    if ((rc = mixed ? S.mp_rz(1) : S.start(pre))) return rc;
     if ((rc = S.read_state())) return rc;
 
     for (;;) {
         if (h->halt == RUN) {
-            if (!mixed && !learned && small_ok(A, o) && pre != SPCG_PRECOND_LEARNED) {
+            if (!mixed && !learned && small_ok(A, o)) {
                 if (pre == SPCG_PRECOND_JACOBI)
                     hipLaunchKernelGGL(k_cg_small<SPCG_PRECOND_JACOBI>, dim3(1),
                                        dim3(kSmallThreads), 0, s, n, A->row_ptr, A->col,
@@ -887,13 +993,14 @@ int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o
                                        w.r, w.p, w.q, w.dinv, w.st, w.hist);
                 SPCG_LAUNCH_CHECK("k_cg_small");
                 if ((rc = S.read_state())) return rc;
-            } else if ((rc = S.loop(mixed, pre))) {
-                return rc;
+            } else {
+                if ((rc = S.loop(mixed, pre))) return rc;
+                if (S.timing) S.collect(h->k, res);
             }
         }
         const int halt = h->halt;
-        if (pre == SPCG_PRECOND_LEARNED && (halt == H_BUDGET || halt == H_BREAK ||
-                                            (halt == H_MAXIT))) {
+        if (pre == SPCG_PRECOND_LEARNED &&
+            (halt == H_BUDGET || halt == H_BREAK || halt == H_MAXIT)) {
             // fall back to Jacobi-PCG: from x0 after a breakdown, else from x
             learned_iters = h->k;
             fell_back = true;
@@ -903,8 +1010,7 @@ int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o
                                    (int64_t)n, (const double *)w.x0, d_x);
                 SPCG_LAUNCH_CHECK("k_copy");
             }
-            hipLaunchKernelGGL(k_init_state, dim3(1), dim3(256), 0, s, w.st, w.Rd.counters,
-                               (int)S.ncnt(ns), w.Rf.counters, (int)S.ncnt(ns),
+            hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, s, w.st,
                                o->maxit - (halt == H_BREAK ? 0 : learned_iters), o->delta,
                                o->maxit);
             SPCG_LAUNCH_CHECK("k_init_state");
@@ -920,8 +1026,7 @@ int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o
         }
         // exit check: fold the FP32 correction, recompute b - A x in FP64
         if (mixed) {
-            hipLaunchKernelGGL(k_mp_fold, dim3(grid_of(n, kVecBlock)), dim3(kBlock), 0, s, n, d_x,
-                               w.x32, w.st, 1);
+            hipLaunchKernelGGL(k_mp_fold, dim3(S.gv()), dim3(kBlock), 0, s, n, d_x, w.x32, w.st, 1);
             SPCG_LAUNCH_CHECK("k_mp_fold");
         }
         if ((rc = S.resid(R_TRUE, nullptr))) return rc;
@@ -938,7 +1043,7 @@ int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o
         }
         // residual gap: restart from the true residual (r holds b - A x)
         ++restarts;
-        hipLaunchKernelGGL(k_phase_state, dim3(1), dim3(64), 0, s, w.st, h->maxit, h->budget);
+        hipLaunchKernelGGL(k_phase_state, dim3(1), dim3(64), 0, s, w.st);
         SPCG_LAUNCH_CHECK("k_phase_state");
         if ((rc = S.start(pre))) return rc;
         if ((rc = S.read_state())) return rc;

@@ -55,23 +55,26 @@ k_validate(int n, int ncols, int64_t nnz, const int32_t *__restrict__ rp,
     if (mx) atomicMax(&flags[1], mx);
 }
 
-// block_row[b] = first row i with row_ptr[i] + i >= b * kChunk (b < nb), block_row[nb] = n
+// block_row[b] = first row i with row_ptr[i] + i >= b * kChunk (b < nb),
+// block_row[nb] = n; block_k[b] = row_ptr[block_row[b]]
 __global__ void __launch_bounds__(kBlock)
-k_partition(int n, const int32_t *__restrict__ rp, int64_t nb, int32_t *block_row) {
+k_partition(int n, const int32_t *__restrict__ rp, int64_t nb, int32_t *block_row,
+            int32_t *block_k) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b > nb) return;
-    if (b == nb) {
-        block_row[b] = n;
-        return;
-    }
-    const int64_t target = b * kChunk;
-    int lo = 0, hi = n;  // answer in [lo, hi]
-    while (lo < hi) {
-        const int mid = lo + ((hi - lo) >> 1);
-        if ((int64_t)rp[mid] + mid >= target) hi = mid;
-        else lo = mid + 1;
+    int lo = n;
+    if (b < nb) {
+        const int64_t target = b * kChunk;
+        lo = 0;
+        int hi = n;  // answer in [lo, hi]
+        while (lo < hi) {
+            const int mid = lo + ((hi - lo) >> 1);
+            if ((int64_t)rp[mid] + mid >= target) hi = mid;
+            else lo = mid + 1;
+        }
     }
     block_row[b] = lo;
+    block_k[b] = rp[lo];
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -92,18 +95,19 @@ struct EpiStore {
 };
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock)
+SPCG_ROWBLOCK_KERNEL
 k_spmv(CsrDev A, const T *__restrict__ vals, const T *__restrict__ x, T *__restrict__ y) {
     __shared__ SpmvSmem<T> sm;
-    const int blk = xcd_remap(blockIdx.x, A.n_blocks);
+    int bs, be;
+    block_range(A.n_blocks, bs, be);
     EpiStore<T> epi{y};
-    spmv_block<T, T, T>(A, vals, x, blk, sm, epi);
+    for (int b = bs; b < be; ++b) spmv_block<T, T, T>(A, vals, x, b, sm, epi);
 }
 
 template <typename T>
 int launch_spmv(const spcg_csr *A, const T *x, T *y, hipStream_t s) {
     if (A->n_rows == 0) return SPCG_OK;
-    hipLaunchKernelGGL(k_spmv<T>, dim3((unsigned)A->n_blocks), dim3(kBlock), 0, s, dev_view(A),
+    hipLaunchKernelGGL(k_spmv<T>, dim3(spmv_grid(A->n_blocks)), dim3(kBlock), 0, s, dev_view(A),
                        (const T *)A->vals, x, y);
     SPCG_LAUNCH_CHECK("k_spmv");
     return SPCG_OK;
@@ -162,8 +166,11 @@ const char *spcg_last_error(void) { return g_err; }
 static void release(spcg_csr *h) {
     if (!h) return;
     if (h->block_row) (void)hipFree(h->block_row);
+    if (h->block_k) (void)hipFree(h->block_k);
     if (h->flags) (void)hipFree(h->flags);
     if (h->h_pinned) (void)hipHostFree(h->h_pinned);
+    for (int i = 0; i < h->n_events; ++i) (void)hipEventDestroy(h->events[i]);
+    delete[] h->events;
     delete h;
 }
 
@@ -213,10 +220,11 @@ int spcg_csr_create(spcg_csr_t *out, int32_t n_rows, int32_t n_cols, int64_t nnz
     h->n_blocks = n_row_blocks(n_rows, nnz);
     if (h->n_blocks > INT32_MAX / 2) { release(h); return SPCG_INVALID_ARG; }
     CREATE_TRY(hipMalloc(&h->block_row, sizeof(int32_t) * (h->n_blocks + 1)));
+    CREATE_TRY(hipMalloc(&h->block_k, sizeof(int32_t) * (h->n_blocks + 1)));
     {
         const unsigned grid = (unsigned)((h->n_blocks + 1 + kBlock - 1) / kBlock);
         hipLaunchKernelGGL(k_partition, dim3(grid), dim3(kBlock), 0, stream, n_rows, d_row_ptr,
-                           h->n_blocks, h->block_row);
+                           h->n_blocks, h->block_row, h->block_k);
         CREATE_TRY(hipGetLastError());
         if (h->n_blocks > 0) {
             const unsigned g2 = (unsigned)((h->n_blocks + kBlock - 1) / kBlock);

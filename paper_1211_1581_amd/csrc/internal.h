@@ -7,17 +7,17 @@
 //    Every row but the last of a block has fewer than kChunk entries; a
 //    block's entries fit the LDS slab (kSlab) unless its last row is long,
 //    and then that row is reduced separately by the whole workgroup.
-//  * One 256-thread workgroup per row block.  Phase 1 streams the block's
+//  * A 256-thread workgroup walks a contiguous range of row blocks (at most
+//    kMaxGrid workgroups, 8 resident per CU).  Phase 1 streams the block's
 //    contiguous values and column indices with coalesced non-temporal loads,
 //    gathers x and writes the products into LDS.  Phase 2 reduces each row
 //    from LDS with a group of L lanes (L ~ the block's mean row length) and a
 //    wavefront butterfly.  The summation order depends only on the matrix,
 //    so results are bitwise reproducible.
-//  * Block indices are remapped so that each XCD walks one contiguous range
-//    of row blocks: x reuse of stencil matrices then stays in that XCD's L2.
-//  * Scalar reductions (inner products) are deterministic: per-block partials
-//    in fixed slots, reduced by the last block of each group of 256 to a group
-//    partial, then by the last group to the final value, each in fixed order.
+//  * Workgroup indices are remapped so that each XCD walks one contiguous
+//    range of row blocks: x reuse of stencil matrices stays in that XCD's L2.
+//  * Scalar reductions (inner products) are deterministic: per-workgroup
+//    partials in fixed slots, summed in fixed order by a finalize kernel.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -34,19 +34,26 @@ struct spcg_csr {
     int32_t dtype = SPCG_F64;
     int device = 0;
     int32_t *block_row = nullptr;  // [n_blocks + 1], owned
+    int32_t *block_k = nullptr;    // [n_blocks + 1], owned
     int64_t n_blocks = 0;
     int64_t n_long = 0;            // blocks whose last row is reduced separately
     int64_t max_len = 0;
     int32_t *flags = nullptr;      // small device scratch for the analysis, owned
     void *h_pinned = nullptr;      // pinned host words for status reads, owned
+    hipEvent_t *events = nullptr;  // timing mode: event pool, owned
+    int n_events = 0;
 };
 
 namespace spcg {
 
 constexpr int kBlock = 256;              // threads per workgroup of the streaming kernels
 constexpr int kChunk = 1024;             // merge-coordinate span of one row block
-constexpr int kSlab = 1792;               // LDS products per row block (>= kChunk; longer last rows go strided)
-constexpr int kGroup = 256;              // partial slots reduced per group in the two-level reduction
+constexpr int kSlab = 1792;              // LDS products per row block (>= kChunk; longer last rows go strided)
+constexpr int kMaxGrid = 8192;           // workgroups of a row-block kernel (each walks a range)
+
+// Row-block kernels run 8 waves per SIMD (8 workgroups of 256 per CU): the
+// register budget is capped at 64 VGPRs so latency hiding is not traded away.
+#define SPCG_ROWBLOCK_KERNEL __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
 
 void set_error(hipError_t e, const char *what);
 int hip_status(hipError_t e, const char *what);
@@ -65,6 +72,11 @@ inline int64_t n_row_blocks(int64_t n_rows, int64_t nnz) {
 }
 
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Workgroups launched for a row-block kernel over nb row blocks.
+inline unsigned spmv_grid(int64_t nb) {
+    return (unsigned)(nb < kMaxGrid ? (nb > 0 ? nb : 1) : kMaxGrid);
+}
 
 // ------------------------------------------------------------ reductions --
 
@@ -96,86 +108,48 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     return (b & 7) * per + (b >> 3);
 }
 
-// Control block of the two-level reduction (lives in the workspace).
-template <typename T>
-struct Reduce {
-    T *partials;          // [nslots * NV]
-    T *gpartials;         // [ngroups * NV]
-    unsigned *counters;   // [ngroups + 1], zero between uses
-};
+// Deterministic scalar reductions: every workgroup of a producing kernel
+// writes its NV partial sums to a fixed slot; a one-workgroup finalize kernel
+// (kFinThreads threads) then sums the slots in a fixed order and acts on the
+// totals.  (A "last workgroup finishes" scheme inside the producer needs a
+// device-scope release/acquire per workgroup, which on CDNA writes back and
+// invalidates the XCD's L2 and costs far more than the extra launch.)
+constexpr int kFinThreads = 1024;
 
-// Called by every thread of a workgroup after the workgroup has reduced its
-// NV values (valid in all threads).  The last workgroup overall calls
-// fin(total) from thread 0 with the fixed-order totals.  Counters are left at
-// zero for the next kernel.
-template <int NV, typename T, class Fin>
-__device__ __forceinline__ void reduce_arrive(const T (&v)[NV], int slot, int nslots,
-                                              const Reduce<T> &R, Fin &fin) {
-    __shared__ int s_last;
-    __shared__ T s_red[4];
-    const int ngroups = (nslots + kGroup - 1) / kGroup;
-    const int g = slot / kGroup;
-    const int gsize = min(kGroup, nslots - g * kGroup);
+template <typename T, int NV>
+__device__ __forceinline__ void store_partials(T *part, int slot, const T (&v)[NV]) {
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int j = 0; j < NV; ++j) R.partials[(size_t)slot * NV + j] = v[j];
-        __threadfence();
-        unsigned prev = atomicAdd(&R.counters[g], 1u);
-        s_last = (prev == (unsigned)(gsize - 1));
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    T gs[NV];
-#pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        T t = (threadIdx.x < gsize) ? R.partials[(size_t)(g * kGroup + threadIdx.x) * NV + j]
-                                    : T(0);
-        gs[j] = block_sum(t, s_red);
-    }
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int j = 0; j < NV; ++j) R.gpartials[(size_t)g * NV + j] = gs[j];
-        R.counters[g] = 0u;
-        __threadfence();
-        unsigned prev = atomicAdd(&R.counters[ngroups], 1u);
-        s_last = (prev == (unsigned)(ngroups - 1));
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    T tot[NV];
-#pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        T t = T(0);
-        for (int i = threadIdx.x; i < ngroups; i += kBlock)
-            t += R.gpartials[(size_t)i * NV + j];
-        tot[j] = block_sum(t, s_red);
-    }
-    if (threadIdx.x == 0) {
-        R.counters[ngroups] = 0u;
-        fin(tot);
+        for (int j = 0; j < NV; ++j) part[(size_t)slot * NV + j] = v[j];
     }
 }
 
-template <typename T>
-inline size_t reduce_bytes(int64_t nslots, int nv) {
-    const int64_t ng = (nslots + kGroup - 1) / kGroup;
-    return align256(sizeof(T) * nslots * nv) + align256(sizeof(T) * ng * nv) +
-           align256(sizeof(unsigned) * (ng + 1));
-}
-
-template <typename T>
-inline Reduce<T> reduce_carve(char *&p, int64_t nslots, int nv) {
-    const int64_t ng = (nslots + kGroup - 1) / kGroup;
-    Reduce<T> R;
-    R.partials = reinterpret_cast<T *>(p);
-    p += align256(sizeof(T) * nslots * nv);
-    R.gpartials = reinterpret_cast<T *>(p);
-    p += align256(sizeof(T) * ng * nv);
-    R.counters = reinterpret_cast<unsigned *>(p);
-    p += align256(sizeof(unsigned) * (ng + 1));
-    return R;
+// Fixed-order total of nslots x NV partials; call from all kFinThreads
+// threads of a one-workgroup kernel; every thread receives the totals.
+template <typename T, int NV>
+__device__ __forceinline__ void finalize_sum(const T *__restrict__ part, int nslots, T (&tot)[NV]) {
+    __shared__ T sh[kFinThreads / 64][NV];
+    T acc[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) acc[j] = T(0);
+    for (int i = threadIdx.x; i < nslots; i += kFinThreads) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) acc[j] += part[(size_t)i * NV + j];
+    }
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        acc[j] = wave_sum(acc[j]);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6][j] = acc[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        T s = T(0);
+#pragma unroll
+        for (int w = 0; w < kFinThreads / 64; ++w) s += sh[w][j];
+        tot[j] = s;
+    }
+    __syncthreads();
 }
 
 // ------------------------------------------------------------- SpMV core --
@@ -183,7 +157,8 @@ inline Reduce<T> reduce_carve(char *&p, int64_t nslots, int nv) {
 struct CsrDev {
     const int32_t *__restrict__ row_ptr;
     const int32_t *__restrict__ col;
-    const int32_t *__restrict__ block_row;
+    const int32_t *__restrict__ block_row;  // first row of each row block  [n_blocks + 1]
+    const int32_t *__restrict__ block_k;    // row_ptr[block_row[b]]        [n_blocks + 1]
     int n_blocks;
 };
 
@@ -192,11 +167,13 @@ struct SpmvSmem {
     TA slab[kSlab];
     int32_t rp[kChunk + 1];
     TA red[4];
+    TA last;
 };
 
 // Row products of one row block.  TV: value type, TX: vector type, TA:
 // accumulation type.  epi.row(i, s) is called exactly once for every row i
-// of the block, by one thread.  Must be called by all 256 threads.
+// of the block, by one thread, with consecutive threads on consecutive rows.
+// Must be called by all 256 threads.
 template <typename TV, typename TX, typename TA, class Epi>
 __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict__ vals,
                                            const TX *__restrict__ x, int blk,
@@ -205,18 +182,19 @@ __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict
     const int r0 = A.block_row[blk];
     const int r1 = A.block_row[blk + 1];
     if (r0 >= r1) return;  // uniform over the workgroup
-    const int k0 = A.row_ptr[r0];
-    const int klast = A.row_ptr[r1 - 1];
-    const int kend = A.row_ptr[r1];
+    const int k0 = A.block_k[blk];
+    const int kend = A.block_k[blk + 1];
+    // a block whose entries overflow the slab ends in a long row (every other
+    // row of a block has fewer than kChunk entries); that row is reduced below
     const bool long_last = (kend - k0) > kSlab;
-    const int rs_end = long_last ? r1 - 1 : r1;  // rows reduced from LDS: [r0, rs_end)
-    const int cnt = (long_last ? klast : kend) - k0;
-    const int nr = rs_end - r0;
+    const int cnt = min(kend - k0, kSlab);
+    const int nr = r1 - r0;
 
-    // phase 1: coalesced streams of col/vals, gather of x, products to LDS
+    // phase 1: coalesced streams of col/vals, then the gather of x, products to LDS
     constexpr int U = kSlab / kBlock;
     int c[U];
     TV v[U];
+    TX xv[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int t = tid + u * kBlock;
@@ -225,31 +203,40 @@ __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict
             v[u] = __builtin_nontemporal_load(vals + k0 + t);
         }
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int t = tid + u * kBlock;
+        if (t < cnt) xv[u] = x[c[u]];
+    }
     for (int t = tid; t <= nr; t += kBlock) sm.rp[t] = A.row_ptr[r0 + t] - k0;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int t = tid + u * kBlock;
-        if (t < cnt) sm.slab[t] = TA(v[u]) * TA(x[c[u]]);
+        if (t < cnt) sm.slab[t] = TA(v[u]) * TA(xv[u]);
     }
     __syncthreads();
 
-    // phase 2: L lanes per row, L = pow2 floor of the mean row length (<= 64)
-    if (nr > 0) {
-        const int avg = cnt / nr;
+    // phase 2: L lanes per row, L = pow2 floor of the mean row length (<= 64);
+    // each row's sum is parked in LDS on its first product slot
+    const int nrs = long_last ? nr - 1 : nr;        // rows reduced from LDS
+    const int cnts = long_last ? sm.rp[nr - 1] : cnt;  // their entries
+    if (nrs > 0) {
+        const int avg = cnts / nrs;
         const int L = avg >= 64 ? 64 : (avg <= 1 ? 1 : (1 << (31 - __clz(avg))));
         const int lane = tid & (L - 1);
         const int grp = tid / L;
         const int ngrp = kBlock / L;
-        for (int r = grp; r < nr; r += ngrp) {
+        for (int r = grp; r < nrs; r += ngrp) {
             const int a = sm.rp[r], e = sm.rp[r + 1];
             TA s = TA(0);
             for (int t = a + lane; t < e; t += L) s += sm.slab[t];
             for (int o = L >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-            if (lane == 0) epi.row(r0 + r, s);
+            if (lane == 0 && e > a) sm.slab[a] = s;
         }
     }
     if (long_last) {
-        // the block's last row is longer than the slab: whole workgroup, strided
+        // the long last row: whole workgroup, strided over global memory
+        const int klast = k0 + sm.rp[nr - 1];
         TA s0 = TA(0), s1 = TA(0), s2 = TA(0), s3 = TA(0);
         int k = klast + tid;
         for (; k + 3 * kBlock < kend; k += 4 * kBlock) {
@@ -260,12 +247,32 @@ __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict
         }
         for (; k < kend; k += kBlock) s0 += TA(vals[k]) * TA(x[A.col[k]]);
         TA s = block_sum((s0 + s1) + (s2 + s3), sm.red);
-        if (tid == 0) epi.row(r1 - 1, s);
+        if (tid == 0) sm.last = s;
     }
+    __syncthreads();
+    // epilogue: consecutive threads take consecutive rows (coalesced y and
+    // per-row vector accesses in epi.row)
+    for (int t = tid; t < nr; t += kBlock) {
+        TA s;
+        if (long_last && t == nr - 1) s = sm.last;
+        else s = sm.rp[t + 1] > sm.rp[t] ? sm.slab[sm.rp[t]] : TA(0);
+        epi.row(r0 + t, s);
+    }
+    __syncthreads();  // the LDS slab is reused by the next row block
+}
+
+// Contiguous range of row blocks owned by this workgroup; the workgroup's
+// logical index (XCD-remapped) is also its partial-sum slot.
+__device__ __forceinline__ int block_range(int nb, int &bs, int &be) {
+    const int P = gridDim.x;
+    const int w = xcd_remap(blockIdx.x, P);
+    bs = (int)((int64_t)nb * w / P);
+    be = (int)((int64_t)nb * (w + 1) / P);
+    return w;
 }
 
 inline CsrDev dev_view(const spcg_csr *A) {
-    return CsrDev{A->row_ptr, A->col, A->block_row, (int)A->n_blocks};
+    return CsrDev{A->row_ptr, A->col, A->block_row, A->block_k, (int)A->n_blocks};
 }
 
 }  // namespace spcg

@@ -33,13 +33,15 @@ class CgOpts(ctypes.Structure):
                 ("precond", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("delta", ctypes.c_double),
                 ("G", ctypes.c_void_p), ("GT", ctypes.c_void_p),
-                ("budget", ctypes.c_int32), ("small_path", ctypes.c_int32)]
+                ("budget", ctypes.c_int32), ("small_path", ctypes.c_int32),
+                ("timing", ctypes.c_int32)]
 
 
 class CgResult(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("iters_fallback", ctypes.c_int32),
                 ("n_updates", ctypes.c_int32), ("n_restarts", ctypes.c_int32),
-                ("true_relres", ctypes.c_double)]
+                ("true_relres", ctypes.c_double), ("spmv_ms", ctypes.c_double),
+                ("spmv_calls", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -178,7 +180,7 @@ def dot(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
 
 
 def cg_opts(tol=1e-10, maxit=20000, precond="jacobi", precision="f64", check_every=0,
-            delta=0.1, G=None, GT=None, budget=None, small_path=True) -> CgOpts:
+            delta=0.1, G=None, GT=None, budget=None, small_path=True, timing=False) -> CgOpts:
     o = CgOpts()
     lib().spcg_cg_default_opts(ctypes.byref(o))
     o.tol = tol
@@ -192,6 +194,7 @@ def cg_opts(tol=1e-10, maxit=20000, precond="jacobi", precision="f64", check_eve
     if budget is not None:
         o.budget = budget
     o.small_path = 1 if small_path else 0
+    o.timing = 1 if timing else 0
     return o
 
 
@@ -223,7 +226,7 @@ def cg_solve(A: CsrMatrix, b: torch.Tensor, x: torch.Tensor | None = None, *, op
     k = res.iters_fallback if res.iters_fallback > 0 or st == FELL_BACK else res.iters
     out = dict(status=st, x=x, iters=res.iters, iters_fallback=res.iters_fallback,
                n_updates=res.n_updates, n_restarts=res.n_restarts,
-               true_relres=res.true_relres)
+               true_relres=res.true_relres, spmv_ms=res.spmv_ms, spmv_calls=res.spmv_calls)
     if want_hist:
         import numpy as np
         out["hist"] = np.ctypeslib.as_array(hist)[:k + 1].copy()

@@ -40,9 +40,9 @@ def test_status_strings_and_struct_sizes():
     from paper_1211_1581_amd import spcg
     assert spcg.status_str(spcg.OK) == "OK"
     assert spcg.status_str(spcg.NOT_SPD) == "NOT_SPD"
-    # spcg_cg_opts: double, 4 x int32, double, 2 pointers, 2 x int32
-    assert ctypes.sizeof(spcg.CgOpts) == 8 + 16 + 8 + 16 + 8
-    assert ctypes.sizeof(spcg.CgResult) == 16 + 8
+    # spcg_cg_opts: double, 4 x int32, double, 2 pointers, 3 x int32 (+ pad)
+    assert ctypes.sizeof(spcg.CgOpts) == 8 + 16 + 8 + 16 + 16
+    assert ctypes.sizeof(spcg.CgResult) == 16 + 8 + 8 + 8
     o = spcg.CgOpts()
     spcg.lib().spcg_cg_default_opts(ctypes.byref(o))
     assert o.tol == 1e-10 and o.maxit == 20000 and o.precond == 1 and o.delta == 0.1
