@@ -72,8 +72,8 @@ const char *spcg_last_error(void);
  *   spcg_csr_destroy.  Columns need not be sorted; duplicates are summed.
  * The structure is validated on the device (row_ptr[0] = 0, non-decreasing,
  * row_ptr[n] = nnz, 0 <= col < n_cols) -> SPCG_INVALID_CSR.  Then the row
- * analysis runs: a partition of the rows into blocks of bounded work and the
- * position of each row's diagonal.  Synchronous: returns after `stream` has
+ * analysis runs: a partition of the rows into blocks of bounded work (and the
+ * value offset of each block).  Synchronous: returns after `stream` has
  * finished the analysis.  The handle owns its analysis arrays (device memory).
  */
 int spcg_csr_create(spcg_csr_t *out, int32_t n_rows, int32_t n_cols, int64_t nnz,
@@ -160,6 +160,64 @@ size_t spcg_cg_workspace_bytes(spcg_csr_t A, const spcg_cg_opts *opts);
 int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *opts,
              void *d_work, size_t work_bytes, spcg_cg_result *res, double *h_hist,
              hipStream_t stream);
+
+/* ------------------------------------------- learned factor (G on tril(A)) */
+
+/*
+ * Message-passing network that predicts the factor G of M^-1 = G G^T on A's
+ * own lower-triangular pattern (G_ii = a_ii^-1/2 exp(o_ii), G_ij = a_ii^-1/2 o_ij,
+ * j < i): width 32, SiLU, 4 edge/node layers, BF16 matrix-core MLPs with FP32
+ * accumulation.  Its weights are one FP32 vector of SPCG_MPNN_PARAMS values in
+ * this order (row-major [out][in] matrices):
+ *   node encoder W (32x2), b (32); edge encoder W (32x2), b (32);
+ *   4 x { W1e (32x96), c1e, W2e (32x32), c2e, W1n (32x64), c1n, W2n (32x32), c2n };
+ *   head w_e (32), c_e (1), w_n (32), c_n (1).
+ * A zero head makes G = D^-1/2, i.e. Jacobi.
+ */
+#define SPCG_MPNN_PARAMS 29442
+#define SPCG_MPNN_TRAIN 1
+
+typedef struct spcg_mpnn *spcg_mpnn_t;
+
+/*
+ * Graph state of the network for matrix A (F64 handle, square, sorted
+ * columns, one positive diagonal entry per row, structurally symmetric):
+ * edge lists, reverse-edge map, the patterns of G = tril and G^T = triu,
+ * features, activation buffers (every layer's when flags has SPCG_MPNN_TRAIN,
+ * needed by spcg_mpnn_loss_grad).  A must outlive the graph.  Allocates;
+ * synchronous.  SPCG_INVALID_CSR for a pattern that breaks the rules above,
+ * SPCG_NOT_SPD for a non-positive diagonal.
+ */
+int spcg_mpnn_create(spcg_mpnn_t *out, spcg_csr_t A, int32_t flags, hipStream_t stream);
+int spcg_mpnn_destroy(spcg_mpnn_t g);
+int spcg_mpnn_info(spcg_mpnn_t g, int64_t *n_edges, int64_t *nnz_factor);
+
+/* Handles of G and G^T (FP32 values owned by the graph, filled by predict),
+ * ready for spcg_cg_opts.G / .GT.  Valid until spcg_mpnn_destroy. */
+int spcg_mpnn_factor(spcg_mpnn_t g, spcg_csr_t *G, spcg_csr_t *GT);
+
+/* Device arrays of G (row_ptr int32[n+1], col int32[nnz_factor], values
+ * float[nnz_factor], CSR order) and of G^T's values in G^T's CSR order. */
+int spcg_mpnn_factor_arrays(spcg_mpnn_t g, const int32_t **d_row_ptr, const int32_t **d_col,
+                            const float **d_vals, const float **d_t_vals);
+
+/* Inference: G and G^T values from the weights d_w (float[SPCG_MPNN_PARAMS]).  Asynchronous. */
+int spcg_mpnn_predict(spcg_mpnn_t g, const float *d_w, hipStream_t stream);
+
+/*
+ * Probe loss L = sum_k ||G^T A G v_k - v_k||^2 / (n m) for the m probe vectors
+ * d_probes (float[m][n], 1 <= m <= 64) and, if d_grad is not NULL, dL/dw into
+ * d_grad (float[SPCG_MPNN_PARAMS], overwritten).  Needs a graph created with
+ * SPCG_MPNN_TRAIN.  Runs the forward pass too (G and G^T values are updated).
+ * h_loss: NULL or receives L (then the call synchronises `stream`).
+ */
+int spcg_mpnn_loss_grad(spcg_mpnn_t g, const float *d_w, const float *d_probes, int32_t m,
+                        float *d_grad, double *h_loss, hipStream_t stream);
+
+/* One Adam step on FP32 master weights: m, v moments in place, bias-corrected
+ * with step t >= 1.  Asynchronous. */
+int spcg_adam_step(float *d_w, const float *d_g, float *d_m, float *d_v, int64_t n, int32_t t,
+                   float lr, float beta1, float beta2, float eps, hipStream_t stream);
 
 #ifdef __cplusplus
 }

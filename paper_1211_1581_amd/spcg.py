@@ -231,3 +231,122 @@ def cg_solve(A: CsrMatrix, b: torch.Tensor, x: torch.Tensor | None = None, *, op
         import numpy as np
         out["hist"] = np.ctypeslib.as_array(hist)[:k + 1].copy()
     return out
+
+
+# ------------------------------------------------------------ learned factor --
+
+MPNN_PARAMS = 29442
+
+
+def _mpnn_sigs(L):
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    if getattr(L, "_mpnn_ready", False):
+        return L
+    L.spcg_mpnn_create.argtypes = [ctypes.POINTER(P), P, i32, P]
+    L.spcg_mpnn_destroy.argtypes = [P]
+    L.spcg_mpnn_info.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.spcg_mpnn_factor.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P)]
+    L.spcg_mpnn_factor_arrays.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P),
+                                          ctypes.POINTER(P), ctypes.POINTER(P)]
+    L.spcg_mpnn_predict.argtypes = [P, P, P]
+    L.spcg_mpnn_loss_grad.argtypes = [P, P, P, i32, P, ctypes.POINTER(ctypes.c_double), P]
+    L.spcg_adam_step.argtypes = [P, P, P, P, i64, i32, ctypes.c_float, ctypes.c_float,
+                                 ctypes.c_float, ctypes.c_float, P]
+    L._mpnn_ready = True
+    return L
+
+
+class _Borrowed:
+    """A matrix handle owned by another object (no destroy)."""
+
+    def __init__(self, h, owner):
+        self._h = ctypes.c_void_p(h)
+        self.owner = owner
+
+    @property
+    def handle(self):
+        return self._h
+
+
+class MpnnGraph:
+    """Network state for one matrix (see spcg_mpnn_create)."""
+
+    def __init__(self, A: CsrMatrix, train: bool = False):
+        L = _mpnn_sigs(lib())
+        self.A = A
+        self.train = train
+        self._h = ctypes.c_void_p(0)
+        st = L.spcg_mpnn_create(ctypes.byref(self._h), A.handle, 1 if train else 0, _stream())
+        if st != OK:
+            self._h = ctypes.c_void_p(0)
+            raise SpcgError(st, "spcg_mpnn_create")
+        e, g = ctypes.c_int64(), ctypes.c_int64()
+        _check(L.spcg_mpnn_info(self._h, ctypes.byref(e), ctypes.byref(g)), "spcg_mpnn_info")
+        self.n_edges, self.nnz_factor = e.value, g.value
+        hg, hgt = ctypes.c_void_p(0), ctypes.c_void_p(0)
+        _check(L.spcg_mpnn_factor(self._h, ctypes.byref(hg), ctypes.byref(hgt)), "spcg_mpnn_factor")
+        self.G, self.GT = _Borrowed(hg.value, self), _Borrowed(hgt.value, self)
+
+    def predict(self, w: torch.Tensor):
+        assert w.dtype == torch.float32 and w.numel() == MPNN_PARAMS and w.is_contiguous()
+        _check(lib().spcg_mpnn_predict(self._h, _ptr(w), _stream()), "spcg_mpnn_predict")
+
+    def loss_grad(self, w: torch.Tensor, probes: torch.Tensor, grad: torch.Tensor | None = None):
+        """Returns the probe loss (float); fills grad if given."""
+        assert probes.dtype == torch.float32 and probes.is_contiguous()
+        m = probes.shape[0]
+        loss = ctypes.c_double(0.0)
+        _check(lib().spcg_mpnn_loss_grad(self._h, _ptr(w), _ptr(probes), m, _ptr(grad),
+                                         ctypes.byref(loss), _stream()), "spcg_mpnn_loss_grad")
+        return loss.value
+
+    def factor_arrays(self):
+        """(row_ptr, col, G values, G^T values) as host numpy arrays."""
+        import numpy as np
+        P = ctypes.c_void_p
+        rp, c, v, vt = P(), P(), P(), P()
+        _check(lib().spcg_mpnn_factor_arrays(self._h, ctypes.byref(rp), ctypes.byref(c),
+                                             ctypes.byref(v), ctypes.byref(vt)),
+               "spcg_mpnn_factor_arrays")
+        torch.cuda.synchronize()
+        n, k = self.A.n_rows, self.nnz_factor
+
+        def grab(ptr, count, ctype, dt):
+            buf = (ctype * count)()
+            import ctypes as C
+            hip = _hip()
+            assert hip.hipMemcpy(C.cast(buf, C.c_void_p), C.c_void_p(ptr.value),
+                                 C.c_size_t(count * C.sizeof(ctype)), 2) == 0
+            return np.frombuffer(buf, dtype=dt).copy()
+
+        return (grab(rp, n + 1, ctypes.c_int32, np.int32), grab(c, k, ctypes.c_int32, np.int32),
+                grab(v, k, ctypes.c_float, np.float32), grab(vt, k, ctypes.c_float, np.float32))
+
+    def close(self):
+        if self._h and self._h.value:
+            lib().spcg_mpnn_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_hip_lib = None
+
+
+def _hip():
+    global _hip_lib
+    if _hip_lib is None:
+        _hip_lib = ctypes.CDLL("libamdhip64.so")
+        _hip_lib.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                       ctypes.c_int]
+    return _hip_lib
+
+
+def adam_step(w, g, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    L = _mpnn_sigs(lib())
+    _check(L.spcg_adam_step(_ptr(w), _ptr(g), _ptr(m), _ptr(v), w.numel(), t, lr, beta1, beta2,
+                            eps, _stream()), "spcg_adam_step")
