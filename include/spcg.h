@@ -178,19 +178,30 @@ int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o
 #define SPCG_MPNN_TRAIN 1
 
 typedef struct spcg_mpnn *spcg_mpnn_t;
+typedef struct spcg_mpnn_ws *spcg_mpnn_ws_t;
 
 /*
- * Graph state of the network for matrix A (F64 handle, square, sorted
- * columns, one positive diagonal entry per row, structurally symmetric):
- * edge lists, reverse-edge map, the patterns of G = tril and G^T = triu,
- * features, activation buffers (every layer's when flags has SPCG_MPNN_TRAIN,
- * needed by spcg_mpnn_loss_grad).  A must outlive the graph.  Allocates;
+ * Per-matrix network state for A (F64 handle, square, sorted columns, one
+ * positive diagonal entry per row, structurally symmetric): edge lists,
+ * reverse-edge map, the patterns of G = tril and G^T = triu, features, and
+ * the factor values.  With SPCG_MPNN_TRAIN it also keeps an FP32 copy of A's
+ * values for the probe loss.  A must outlive the graph.  Allocates;
  * synchronous.  SPCG_INVALID_CSR for a pattern that breaks the rules above,
  * SPCG_NOT_SPD for a non-positive diagonal.
  */
 int spcg_mpnn_create(spcg_mpnn_t *out, spcg_csr_t A, int32_t flags, hipStream_t stream);
 int spcg_mpnn_destroy(spcg_mpnn_t g);
 int spcg_mpnn_info(spcg_mpnn_t g, int64_t *n_edges, int64_t *nnz_factor);
+
+/*
+ * Activation and gradient buffers for graphs of up to max_rows rows and
+ * max_edges off-diagonal entries, shareable by many graphs used one at a time
+ * on one stream.  SPCG_MPNN_TRAIN keeps every layer's activations and the
+ * backward scratch (needed by spcg_mpnn_loss_grad).  Allocates.
+ */
+int spcg_mpnn_ws_create(spcg_mpnn_ws_t *out, int64_t max_rows, int64_t max_edges, int32_t flags,
+                        hipStream_t stream);
+int spcg_mpnn_ws_destroy(spcg_mpnn_ws_t ws);
 
 /* Handles of G and G^T (FP32 values owned by the graph, filled by predict),
  * ready for spcg_cg_opts.G / .GT.  Valid until spcg_mpnn_destroy. */
@@ -201,18 +212,19 @@ int spcg_mpnn_factor(spcg_mpnn_t g, spcg_csr_t *G, spcg_csr_t *GT);
 int spcg_mpnn_factor_arrays(spcg_mpnn_t g, const int32_t **d_row_ptr, const int32_t **d_col,
                             const float **d_vals, const float **d_t_vals);
 
-/* Inference: G and G^T values from the weights d_w (float[SPCG_MPNN_PARAMS]).  Asynchronous. */
-int spcg_mpnn_predict(spcg_mpnn_t g, const float *d_w, hipStream_t stream);
+/* Inference: G and G^T values from the weights d_w (float[SPCG_MPNN_PARAMS]).
+ * ws must fit the graph (else SPCG_INVALID_ARG).  Asynchronous. */
+int spcg_mpnn_predict(spcg_mpnn_t g, spcg_mpnn_ws_t ws, const float *d_w, hipStream_t stream);
 
 /*
  * Probe loss L = sum_k ||G^T A G v_k - v_k||^2 / (n m) for the m probe vectors
  * d_probes (float[m][n], 1 <= m <= 64) and, if d_grad is not NULL, dL/dw into
- * d_grad (float[SPCG_MPNN_PARAMS], overwritten).  Needs a graph created with
+ * d_grad (float[SPCG_MPNN_PARAMS], overwritten).  Graph and workspace need
  * SPCG_MPNN_TRAIN.  Runs the forward pass too (G and G^T values are updated).
  * h_loss: NULL or receives L (then the call synchronises `stream`).
  */
-int spcg_mpnn_loss_grad(spcg_mpnn_t g, const float *d_w, const float *d_probes, int32_t m,
-                        float *d_grad, double *h_loss, hipStream_t stream);
+int spcg_mpnn_loss_grad(spcg_mpnn_t g, spcg_mpnn_ws_t ws, const float *d_w, const float *d_probes,
+                        int32_t m, float *d_grad, double *h_loss, hipStream_t stream);
 
 /* One Adam step on FP32 master weights: m, v moments in place, bias-corrected
  * with step t >= 1.  Asynchronous. */

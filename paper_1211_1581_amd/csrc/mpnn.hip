@@ -55,30 +55,33 @@ constexpr int kWavesPerWg = 4;  // 256-thread workgroups, one tile per wave at a
 using namespace spcg;
 using namespace spcg::mp;
 
+// Per-matrix state: edge lists, factor patterns, features, factor values.
 struct spcg_mpnn {
     spcg_csr *A = nullptr;
     int n = 0, E = 0, nG = 0;
     bool train = false;
-    int device = 0;
-    // graph
     int32_t *erow = nullptr, *ecol = nullptr, *eptr = nullptr, *rev = nullptr, *dpos = nullptr;
     int32_t *cntL = nullptr, *cntU = nullptr;
     int32_t *g_rp = nullptr, *g_col = nullptr, *g_row = nullptr, *gdiag = nullptr;
     int32_t *gt_rp = nullptr, *gt_col = nullptr, *gt_src = nullptr;
     double *s64 = nullptr;
     float *s32 = nullptr, *logd = nullptr, *fe = nullptr, *ge = nullptr;
-    float *gvals = nullptr, *gtvals = nullptr, *a32 = nullptr;
-    // activations: train keeps every layer, inference ping-pongs two
-    __bf16 *h[NL + 1] = {}, *e[NL + 1] = {};
-    LayerBf *wbf = nullptr;
-    // training
-    float *dh[2] = {}, *de[2] = {}, *dxi = nullptr, *dxj = nullptr, *dagg = nullptr;
-    float *pw = nullptr, *pu = nullptr, *pt = nullptr, *ps = nullptr, *py = nullptr, *pq = nullptr;
-    float *gG = nullptr, *wpart = nullptr, *lpart = nullptr;
-    int n_wpart = 0;
+    float *gvals = nullptr, *gtvals = nullptr, *a32 = nullptr, *lpart = nullptr;
     spcg_csr *G = nullptr, *GT = nullptr, *A32 = nullptr;
     int32_t *flags = nullptr;
-    float *scal = nullptr;  // [0] mean log d, [1] loss
+    float *scal = nullptr;  // [0] mean log a_ii
+    void *h_pinned = nullptr;
+};
+
+// Activations and training scratch, shareable by the graphs of many matrices.
+struct spcg_mpnn_ws {
+    int64_t max_n = 0, max_E = 0, max_nG = 0;
+    bool train = false;
+    __bf16 *h[NL + 1] = {}, *e[NL + 1] = {};
+    LayerBf *wbf = nullptr;
+    float *dh[2] = {}, *de[2] = {}, *dxi = nullptr, *dxj = nullptr, *dagg = nullptr;
+    float *pw = nullptr, *pu = nullptr, *ps = nullptr, *py = nullptr, *pq = nullptr;
+    float *gG = nullptr, *wpart = nullptr, *lpart = nullptr, *scal = nullptr;
     void *h_pinned = nullptr;
 };
 
@@ -853,25 +856,44 @@ __global__ void k_adam(int64_t n, float *w, const float *g, float *m, float *v, 
 
 namespace {
 
+template <typename T>
+void free_dev(T *&p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
 int release(spcg_mpnn *g) {
     if (!g) return SPCG_OK;
     if (g->G) spcg_csr_destroy(g->G);
     if (g->GT) spcg_csr_destroy(g->GT);
     if (g->A32) spcg_csr_destroy(g->A32);
-    void *ptrs[] = {g->erow, g->ecol, g->eptr, g->rev, g->dpos, g->cntL, g->cntU, g->g_rp,
-                    g->g_col, g->g_row, g->gdiag, g->gt_rp, g->gt_col, g->gt_src, g->s64,
-                    g->s32, g->logd, g->fe, g->ge, g->gvals, g->gtvals, g->a32, g->wbf,
-                    g->dh[0], g->dh[1], g->de[0], g->de[1], g->dxi, g->dxj, g->dagg, g->pw,
-                    g->pu, g->pt, g->ps, g->py, g->pq, g->gG, g->wpart, g->lpart, g->flags,
-                    g->scal};
-    for (void *p : ptrs)
-        if (p) (void)hipFree(p);
-    for (int l = 0; l <= NL; ++l) {
-        if (g->h[l]) (void)hipFree(g->h[l]);
-        if (g->e[l]) (void)hipFree(g->e[l]);
-    }
+    free_dev(g->erow); free_dev(g->ecol); free_dev(g->eptr); free_dev(g->rev); free_dev(g->dpos);
+    free_dev(g->cntL); free_dev(g->cntU); free_dev(g->g_rp); free_dev(g->g_col); free_dev(g->g_row);
+    free_dev(g->gdiag); free_dev(g->gt_rp); free_dev(g->gt_col); free_dev(g->gt_src);
+    free_dev(g->s64); free_dev(g->s32); free_dev(g->logd); free_dev(g->fe); free_dev(g->ge);
+    free_dev(g->gvals); free_dev(g->gtvals); free_dev(g->a32); free_dev(g->lpart);
+    free_dev(g->flags); free_dev(g->scal);
     if (g->h_pinned) (void)hipHostFree(g->h_pinned);
     delete g;
+    return SPCG_OK;
+}
+
+int release_ws(spcg_mpnn_ws *w) {
+    if (!w) return SPCG_OK;
+    for (int l = 0; l <= NL; ++l) {
+        free_dev(w->h[l]);
+        free_dev(w->e[l]);
+    }
+    free_dev(w->wbf);
+    for (int q = 0; q < 2; ++q) {
+        free_dev(w->dh[q]);
+        free_dev(w->de[q]);
+    }
+    free_dev(w->dxi); free_dev(w->dxj); free_dev(w->dagg); free_dev(w->pw); free_dev(w->pu);
+    free_dev(w->ps); free_dev(w->py); free_dev(w->pq); free_dev(w->gG); free_dev(w->wpart);
+    free_dev(w->lpart); free_dev(w->scal);
+    if (w->h_pinned) (void)hipHostFree(w->h_pinned);
+    delete w;
     return SPCG_OK;
 }
 
@@ -884,24 +906,28 @@ unsigned tile_wgs(int64_t items, int cap) {
 }
 constexpr int kFwdCap = 2048, kBwdCap = 256, kSmallCap = 512, kMaxProbes = 64;
 
-__bf16 *hbuf(spcg_mpnn *g, int l) { return g->train ? g->h[l] : g->h[l & 1]; }
-__bf16 *ebuf(spcg_mpnn *g, int l) { return g->train ? g->e[l] : g->e[l & 1]; }
+__bf16 *hbuf(const spcg_mpnn_ws *w, int l) { return w->train ? w->h[l] : w->h[l & 1]; }
+__bf16 *ebuf(const spcg_mpnn_ws *w, int l) { return w->train ? w->e[l] : w->e[l & 1]; }
 
-int forward(spcg_mpnn *g, const float *w, hipStream_t s) {
-    hipLaunchKernelGGL(k_prep_weights, dim3(NL), dim3(256), 0, s, w, g->wbf);
+bool fits(const spcg_mpnn *g, const spcg_mpnn_ws *w) {
+    return g->n <= w->max_n && g->E <= w->max_E && g->nG <= w->max_nG;
+}
+
+int forward(spcg_mpnn *g, spcg_mpnn_ws *ws, const float *w, hipStream_t s) {
+    hipLaunchKernelGGL(k_prep_weights, dim3(NL), dim3(256), 0, s, w, ws->wbf);
     hipLaunchKernelGGL(k_encode, dim3(g1(std::max(g->n, g->E))), dim3(256), 0, s, g->n, g->E, w,
-                       (const float *)g->fe, (const float *)g->ge, hbuf(g, 0), ebuf(g, 0));
+                       (const float *)g->fe, (const float *)g->ge, hbuf(ws, 0), ebuf(ws, 0));
     for (int l = 1; l <= NL; ++l) {
         const float *Lw = w + L0 + (l - 1) * LSZ;
         if (g->E > 0)
             hipLaunchKernelGGL(k_edge_fwd, dim3(tile_wgs(g->E, kFwdCap)), dim3(256), 0, s, g->E,
-                               g->erow, g->ecol, hbuf(g, l - 1), ebuf(g, l - 1), ebuf(g, l),
-                               g->wbf + (l - 1), Lw);
+                               g->erow, g->ecol, hbuf(ws, l - 1), ebuf(ws, l - 1), ebuf(ws, l),
+                               ws->wbf + (l - 1), Lw);
         hipLaunchKernelGGL(k_node_fwd, dim3(tile_wgs(g->n, kFwdCap)), dim3(256), 0, s, g->n,
-                           g->eptr, hbuf(g, l - 1), ebuf(g, l), hbuf(g, l), g->wbf + (l - 1), Lw);
+                           g->eptr, hbuf(ws, l - 1), ebuf(ws, l), hbuf(ws, l), ws->wbf + (l - 1), Lw);
     }
     hipLaunchKernelGGL(k_head, dim3(g1(g->n)), dim3(256), 0, s, g->n, g->eptr, g->cntL, g->g_rp,
-                       hbuf(g, NL), ebuf(g, NL), w, (const float *)g->s32, g->gvals);
+                       hbuf(ws, NL), ebuf(ws, NL), w, (const float *)g->s32, g->gvals);
     hipLaunchKernelGGL(k_gt_fill, dim3(g1(g->nG)), dim3(256), 0, s, g->nG, g->gt_src,
                        (const float *)g->gvals, g->gtvals);
     SPCG_LAUNCH_CHECK("mpnn forward");
@@ -911,6 +937,59 @@ int forward(spcg_mpnn *g, const float *w, hipStream_t s) {
 }  // namespace
 
 extern "C" {
+
+int spcg_mpnn_ws_create(spcg_mpnn_ws_t *out, int64_t max_rows, int64_t max_edges, int32_t flags,
+                        hipStream_t s) {
+    (void)s;
+    if (!out || max_rows < 1 || max_edges < 0) return SPCG_INVALID_ARG;
+    *out = nullptr;
+    spcg_mpnn_ws *w = new (std::nothrow) spcg_mpnn_ws;
+    if (!w) return SPCG_INVALID_ARG;
+    w->max_n = max_rows;
+    w->max_E = max_edges;
+    w->max_nG = max_rows + max_edges / 2;
+    w->train = (flags & SPCG_MPNN_TRAIN) != 0;
+#define WS_TRY(expr)                                                            \
+    do {                                                                        \
+        hipError_t e_ = (expr);                                                 \
+        if (e_ != hipSuccess) { release_ws(w); return hip_status(e_, #expr); } \
+    } while (0)
+#define WS_ALLOC(ptr, count) WS_TRY(hipMalloc(&(ptr), sizeof(*(ptr)) * (size_t)std::max<int64_t>((count), 1)))
+    const int64_t n = max_rows, E = max_edges;
+    const int nbuf = w->train ? NL + 1 : 2;
+    for (int l = 0; l < nbuf; ++l) {
+        WS_ALLOC(w->h[l], n * H);
+        WS_ALLOC(w->e[l], E * H);
+    }
+    WS_ALLOC(w->wbf, NL);
+    WS_ALLOC(w->scal, 64);
+    WS_TRY(hipHostMalloc(&w->h_pinned, 256, hipHostMallocDefault));
+    if (w->train) {
+        for (int q = 0; q < 2; ++q) {
+            WS_ALLOC(w->dh[q], n * H);
+            WS_ALLOC(w->de[q], E * H);
+        }
+        WS_ALLOC(w->dxi, E * H);
+        WS_ALLOC(w->dxj, E * H);
+        WS_ALLOC(w->dagg, n * H);
+        float **vecs[] = {&w->pw, &w->pu, &w->ps, &w->py, &w->pq};
+        for (float **v : vecs) WS_ALLOC(*v, n);
+        WS_ALLOC(w->gG, w->max_nG);
+        WS_ALLOC(w->wpart, (int64_t)std::max<int64_t>(kBwdCap * kWavesPerWg * 4160, g1(n) * 66));
+        WS_ALLOC(w->lpart, (int64_t)kMaxProbes * kMaxGrid);
+    }
+#undef WS_ALLOC
+#undef WS_TRY
+    *out = w;
+    return SPCG_OK;
+}
+
+int spcg_mpnn_ws_destroy(spcg_mpnn_ws_t w) {
+    if (!w) return SPCG_INVALID_ARG;
+    hipError_t e = hipDeviceSynchronize();
+    release_ws(w);
+    return e == hipSuccess ? SPCG_OK : hip_status(e, "hipDeviceSynchronize");
+}
 
 int spcg_mpnn_create(spcg_mpnn_t *out, spcg_csr_t A, int32_t flags, hipStream_t s) {
     if (!out || !A) return SPCG_INVALID_ARG;
@@ -922,7 +1001,6 @@ int spcg_mpnn_create(spcg_mpnn_t *out, spcg_csr_t A, int32_t flags, hipStream_t 
     g->n = A->n_rows;
     g->E = (int)(A->nnz - A->n_rows);
     g->train = (flags & SPCG_MPNN_TRAIN) != 0;
-    g->device = A->device;
     const int n = g->n;
     const int64_t E = std::max(g->E, 0);
 #define MP_TRY(expr)                                                         \
@@ -978,7 +1056,7 @@ int spcg_mpnn_create(spcg_mpnn_t *out, spcg_csr_t A, int32_t flags, hipStream_t 
     MP_ALLOC(g->fe, 2 * (int64_t)n);
     MP_ALLOC(g->ge, 2 * E);
     const int nfp = (int)g1(n);
-    MP_ALLOC(g->lpart, std::max<int64_t>(nfp, (int64_t)kMaxProbes * kMaxGrid));
+    MP_ALLOC(g->lpart, nfp);
     hipLaunchKernelGGL(k_nodefeat, dim3(nfp), dim3(256), 0, s, n, (const double *)A->vals, g->dpos,
                        g->s64, g->s32, g->logd, g->lpart, g->flags);
     hipLaunchKernelGGL(k_mean, dim3(1), dim3(kFinThreads), 0, s, nfp, (const float *)g->lpart, n,
@@ -987,27 +1065,10 @@ int spcg_mpnn_create(spcg_mpnn_t *out, spcg_csr_t A, int32_t flags, hipStream_t 
                        (const float *)g->logd, (const float *)g->scal, (const double *)A->vals,
                        A->row_ptr, g->erow, g->ecol, g->dpos, (const double *)g->s64, g->fe, g->ge);
     MP_TRY(hipGetLastError());
-    const int nbuf = g->train ? NL + 1 : 2;
-    for (int l = 0; l < nbuf; ++l) {
-        MP_ALLOC(g->h[l], (int64_t)n * H);
-        MP_ALLOC(g->e[l], E * H);
-    }
-    MP_ALLOC(g->wbf, NL);
     if (g->train) {
         MP_ALLOC(g->a32, A->nnz);
         hipLaunchKernelGGL(k_to_f32v, dim3(g1(A->nnz, 2048)), dim3(256), 0, s, A->nnz,
                            (const double *)A->vals, g->a32);
-        for (int q = 0; q < 2; ++q) {
-            MP_ALLOC(g->dh[q], (int64_t)n * H);
-            MP_ALLOC(g->de[q], E * H);
-        }
-        MP_ALLOC(g->dxi, E * H);
-        MP_ALLOC(g->dxj, E * H);
-        MP_ALLOC(g->dagg, (int64_t)n * H);
-        float **vecs[] = {&g->pw, &g->pu, &g->pt, &g->ps, &g->py, &g->pq};
-        for (float **v : vecs) MP_ALLOC(*v, n);
-        MP_ALLOC(g->gG, g->nG);
-        MP_ALLOC(g->wpart, (int64_t)kBwdCap * kWavesPerWg * 4160);
     }
     MP_TRY(hipStreamSynchronize(s));
     MP_TRY(hipMemcpyAsync(hp, g->flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -1062,15 +1123,17 @@ int spcg_mpnn_factor_arrays(spcg_mpnn_t g, const int32_t **d_row_ptr, const int3
     return SPCG_OK;
 }
 
-int spcg_mpnn_predict(spcg_mpnn_t g, const float *d_w, hipStream_t s) {
-    if (!g || !d_w) return SPCG_INVALID_ARG;
-    return forward(g, d_w, s);
+int spcg_mpnn_predict(spcg_mpnn_t g, spcg_mpnn_ws_t ws, const float *d_w, hipStream_t s) {
+    if (!g || !ws || !d_w || !fits(g, ws)) return SPCG_INVALID_ARG;
+    return forward(g, ws, d_w, s);
 }
 
-int spcg_mpnn_loss_grad(spcg_mpnn_t g, const float *d_w, const float *d_probes, int32_t m,
-                        float *d_grad, double *h_loss, hipStream_t s) {
-    if (!g || !d_w || !d_probes || m < 1 || m > kMaxProbes || !g->train) return SPCG_INVALID_ARG;
-    int rc = forward(g, d_w, s);
+int spcg_mpnn_loss_grad(spcg_mpnn_t g, spcg_mpnn_ws_t ws, const float *d_w, const float *d_probes,
+                        int32_t m, float *d_grad, double *h_loss, hipStream_t s) {
+    if (!g || !ws || !d_w || !d_probes || m < 1 || m > kMaxProbes || !g->train || !ws->train ||
+        !fits(g, ws))
+        return SPCG_INVALID_ARG;
+    int rc = forward(g, ws, d_w, s);
     if (rc) return rc;
     const int n = g->n, E = g->E;
     const CsrDev Gd = dev_view(g->G), GTd = dev_view(g->GT), Ad = dev_view(g->A32);
@@ -1079,69 +1142,69 @@ int spcg_mpnn_loss_grad(spcg_mpnn_t g, const float *d_w, const float *d_probes, 
     const float scale = 2.0f / ((float)n * (float)m);
     for (int k = 0; k < m; ++k) {
         const float *v = d_probes + (size_t)k * n;
-        hipLaunchKernelGGL(k_sp32, dim3(gG), dim3(256), 0, s, Gd, (const float *)g->gvals, v, g->pw);
+        hipLaunchKernelGGL(k_sp32, dim3(gG), dim3(256), 0, s, Gd, (const float *)g->gvals, v, ws->pw);
         hipLaunchKernelGGL(k_sp32, dim3(gA), dim3(256), 0, s, Ad, (const float *)g->a32,
-                           (const float *)g->pw, g->pu);
+                           (const float *)ws->pw, ws->pu);
         hipLaunchKernelGGL(k_sp32_resid, dim3(gGT), dim3(256), 0, s, GTd, (const float *)g->gtvals,
-                           (const float *)g->pu, v, g->ps, scale, g->lpart + (size_t)k * gGT);
+                           (const float *)ws->pu, v, ws->ps, scale, ws->lpart + (size_t)k * gGT);
         hipLaunchKernelGGL(k_sp32, dim3(gG), dim3(256), 0, s, Gd, (const float *)g->gvals,
-                           (const float *)g->ps, g->py);
+                           (const float *)ws->ps, ws->py);
         hipLaunchKernelGGL(k_sp32, dim3(gA), dim3(256), 0, s, Ad, (const float *)g->a32,
-                           (const float *)g->py, g->pq);
+                           (const float *)ws->py, ws->pq);
         hipLaunchKernelGGL(k_sddmm, dim3(g1(g->nG)), dim3(256), 0, s, g->nG, g->g_row, g->g_col,
-                           (const float *)g->pu, (const float *)g->ps, (const float *)g->pq, v,
-                           g->gG, k == 0 ? 1 : 0);
+                           (const float *)ws->pu, (const float *)ws->ps, (const float *)ws->pq, v,
+                           ws->gG, k == 0 ? 1 : 0);
     }
     hipLaunchKernelGGL(k_loss_fin, dim3(1), dim3(kFinThreads), 0, s, (int)(m * gGT),
-                       (const float *)g->lpart, g->scal);
+                       (const float *)ws->lpart, ws->scal);
     SPCG_LAUNCH_CHECK("mpnn loss");
     if (d_grad) {
         const unsigned hw = g1(n);
         hipLaunchKernelGGL(k_head_bwd, dim3(hw), dim3(256), 0, s, n, g->eptr, g->cntL, g->g_rp,
-                           (const __bf16 *)g->h[NL], (const __bf16 *)g->e[NL], d_w,
-                           (const float *)g->s32, (const float *)g->gvals, (const float *)g->gG,
-                           g->dh[0], g->de[0], g->wpart);
+                           (const __bf16 *)ws->h[NL], (const __bf16 *)ws->e[NL], d_w,
+                           (const float *)g->s32, (const float *)g->gvals, (const float *)ws->gG,
+                           ws->dh[0], ws->de[0], ws->wpart);
         hipLaunchKernelGGL(k_wreduce, dim3(1), dim3(128), 0, s, (int)hw, 66,
-                           (const float *)g->wpart, d_grad, HEAD);
+                           (const float *)ws->wpart, d_grad, HEAD);
         int c = 0;
         for (int l = NL; l >= 1; --l) {
             const int li = l - 1;
             const float *Lw = d_w + L0 + li * LSZ;
             const unsigned wn = tile_wgs(n, kBwdCap), we = tile_wgs(E, kBwdCap);
             hipLaunchKernelGGL(k_node_bwd, dim3(wn), dim3(256), 0, s, n, g->eptr,
-                               (const __bf16 *)g->h[l - 1], (const __bf16 *)g->e[l],
-                               (const float *)g->dh[c], g->dh[1 - c], g->dagg, g->wbf + li, Lw,
-                               g->wpart);
+                               (const __bf16 *)ws->h[l - 1], (const __bf16 *)ws->e[l],
+                               (const float *)ws->dh[c], ws->dh[1 - c], ws->dagg, ws->wbf + li, Lw,
+                               ws->wpart);
             hipLaunchKernelGGL(k_wreduce, dim3(g1(3136)), dim3(256), 0, s, (int)(wn * kWavesPerWg),
-                               3136, (const float *)g->wpart, d_grad, L0 + li * LSZ + N1W);
+                               3136, (const float *)ws->wpart, d_grad, L0 + li * LSZ + N1W);
             if (E > 0) {
                 hipLaunchKernelGGL(k_edge_bwd, dim3(we), dim3(256), 0, s, E, g->erow, g->ecol,
-                                   (const __bf16 *)g->h[l - 1], (const __bf16 *)g->e[l - 1],
-                                   (const float *)g->de[c], (const float *)g->dagg, g->dxi,
-                                   g->dxj, g->de[1 - c], g->wbf + li, Lw, g->wpart);
+                                   (const __bf16 *)ws->h[l - 1], (const __bf16 *)ws->e[l - 1],
+                                   (const float *)ws->de[c], (const float *)ws->dagg, ws->dxi,
+                                   ws->dxj, ws->de[1 - c], ws->wbf + li, Lw, ws->wpart);
                 hipLaunchKernelGGL(k_wreduce, dim3(g1(4160)), dim3(256), 0, s,
-                                   (int)(we * kWavesPerWg), 4160, (const float *)g->wpart, d_grad,
+                                   (int)(we * kWavesPerWg), 4160, (const float *)ws->wpart, d_grad,
                                    L0 + li * LSZ + E1W);
                 hipLaunchKernelGGL(k_node_gather, dim3(g1((int64_t)n * H)), dim3(256), 0, s, n,
-                                   g->eptr, g->rev, (const float *)g->dxi, (const float *)g->dxj,
-                                   g->dh[1 - c]);
+                                   g->eptr, g->rev, (const float *)ws->dxi, (const float *)ws->dxj,
+                                   ws->dh[1 - c]);
             } else {
                 hipLaunchKernelGGL(k_wreduce, dim3(g1(4160)), dim3(256), 0, s, 0, 4160,
-                                   (const float *)g->wpart, d_grad, L0 + li * LSZ + E1W);
+                                   (const float *)ws->wpart, d_grad, L0 + li * LSZ + E1W);
             }
             c = 1 - c;
         }
         const unsigned we = (unsigned)std::min<int64_t>(g1(std::max(n, E), 8), kSmallCap);
         hipLaunchKernelGGL(k_enc_bwd, dim3(we), dim3(256), 0, s, n, E, (const float *)g->fe,
-                           (const float *)g->ge, (const float *)g->dh[c], (const float *)g->de[c],
-                           g->wpart);
+                           (const float *)g->ge, (const float *)ws->dh[c], (const float *)ws->de[c],
+                           ws->wpart);
         hipLaunchKernelGGL(k_wreduce, dim3(1), dim3(256), 0, s, (int)we, 192,
-                           (const float *)g->wpart, d_grad, 0);
+                           (const float *)ws->wpart, d_grad, 0);
         SPCG_LAUNCH_CHECK("mpnn backward");
     }
     if (h_loss) {
-        float *hp = (float *)g->h_pinned;
-        SPCG_TRY(hipMemcpyAsync(hp, g->scal + 1, sizeof(float), hipMemcpyDeviceToHost, s));
+        float *hp = (float *)ws->h_pinned;
+        SPCG_TRY(hipMemcpyAsync(hp, ws->scal + 1, sizeof(float), hipMemcpyDeviceToHost, s));
         SPCG_TRY(hipStreamSynchronize(s));
         *h_loss = (double)hp[0] / ((double)n * (double)m);
     }

@@ -64,3 +64,13 @@ def test_oracle_builds():
     import oracle
     path = oracle.build(force=False)
     assert os.path.exists(path)
+
+
+def test_weight_layout_matches_oracle():
+    # the library's documented flat weight order is the oracle's parameter order
+    from oracle import mpnn
+    from paper_1211_1581_amd import spcg, train
+    assert train.param_spec() == mpnn.param_spec()
+    assert spcg.MPNN_PARAMS == mpnn.n_params()
+    src = open(os.path.join(ROOT, "include", "spcg.h")).read()
+    assert "#define SPCG_MPNN_PARAMS 29442" in src

@@ -6,8 +6,10 @@ step, and a CG solve with the predicted factor.
 Tolerances: activations are stored in BF16 (unit roundoff 2^-9) before each of
 the ~10 matrix products on the path to the head, so the forward outputs
 carry relative errors of order 1e-2; the tests bound the normwise relative
-error by 5e-2 and require cosine similarity >= 0.999 (forward) / 0.99
-(gradients).  A wrong index, sign or transposition gives O(1) errors."""
+error of the factor values by 2e-2 (measured: 3e-3 .. 6e-3), the loss by
+1e-2, the gradient by 5e-2 (measured: 2e-3 .. 2.3e-2), and require cosine
+similarity >= 0.9999 (factor) / 0.999 (gradients).  A wrong index, sign or
+transposition gives O(1) errors."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -75,7 +77,7 @@ def test_forward_matches_oracle(N, seed):
     M, g = graph(A)
     g.predict(torch.tensor(mpnn.flatten(P), dtype=torch.float32, device="cuda"))
     _, _, gv, _ = g.factor_arrays()
-    assert cos(gv, ref) >= 0.999 and rel(gv, ref) <= 5e-2, (cos(gv, ref), rel(gv, ref))
+    assert cos(gv, ref) >= 0.9999 and rel(gv, ref) <= 2e-2, (cos(gv, ref), rel(gv, ref))
 
 
 @pytest.mark.parametrize("N,seed", [(6, 3), (10, 4)])
@@ -89,9 +91,9 @@ def test_loss_and_gradients_match_oracle(N, seed):
     grad = torch.zeros(spcg().MPNN_PARAMS, dtype=torch.float32, device="cuda")
     loss = g.loss_grad(w, torch.tensor(V, dtype=torch.float32, device="cuda"), grad)
     gr = grad.cpu().numpy().astype(np.float64)
-    assert abs(loss - ref["loss"]) <= 3e-2 * ref["loss"], (loss, ref["loss"])
-    assert cos(gr, ref["grads"]) >= 0.99, cos(gr, ref["grads"])
-    assert rel(gr, ref["grads"]) <= 0.1, rel(gr, ref["grads"])
+    assert abs(loss - ref["loss"]) <= 1e-2 * ref["loss"], (loss, ref["loss"])
+    assert cos(gr, ref["grads"]) >= 0.999, cos(gr, ref["grads"])
+    assert rel(gr, ref["grads"]) <= 5e-2, rel(gr, ref["grads"])
     # each parameter block points the same way as the oracle's
     o = 0
     for name, shape in mpnn.param_spec():
