@@ -10,9 +10,11 @@ Prints ONE JSON line.  `value` is the hot path's algorithmic HBM throughput
 (passes x algorithmic bytes per pass / wall time of the solves); the roofline
 object reports the dominant kernel (SpMV + p.q) from HIP events recorded
 around each of its launches on the solve's stream; `cpu_baseline` times the
-FP64 oracle on the host cores on a bounded sample of the same workload.
+FP64 oracle on the host cores on a bounded sample of the same workload;
+`forms` gives the time to tolerance of the mixed-precision and learned forms
+beside plain FP64 Jacobi-PCG on their own matrices.
 
-    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--cpu-seconds 15] [--forms]
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--cpu-seconds 15] [--no-forms]
 """
 from __future__ import annotations
 
@@ -96,8 +98,8 @@ def main():
     ap.add_argument("--calib", action="store_true",
                     help="first copy 256 MiB device-to-device once (reference dispatch for "
                          "hardware byte counters)")
-    ap.add_argument("--forms", action="store_true",
-                    help="also time the mixed-precision and learned forms (160^3 / 128^3 FV)")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the mixed-precision (160^3) and learned (128^3) time-to-tolerance")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -204,43 +206,73 @@ def main():
                      "bytes_per_launch": b_spmv, "avg_launch_us": round(avg_us, 2),
                      "launches": spmv_calls},
     }
-    if args.forms:
+    if not args.no_forms:
         line["forms"] = forms(args)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(A, b, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 
 
+def _time_solve(M, bt, opts, work, reps=3, pre=None):
+    import torch
+
+    from paper_1211_1581_amd import spcg
+    x = torch.zeros_like(bt)
+    best, r = None, None
+    for _ in range(reps + 1):
+        x.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        if pre is not None:
+            pre()
+        r = spcg.cg_solve(M, bt, x, opts=opts, work=work, want_hist=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        best = dt if best is None else min(best, dt)
+    return {"ms": round(1e3 * best, 2), "iters": r["iters"], "iters_fallback": r["iters_fallback"],
+            "n_updates": r["n_updates"], "true_relres": r["true_relres"], "status": r["status"]}
+
+
 def forms(args):
-    """Time-to-tolerance of FP64 Jacobi-PCG vs the mixed-precision form on the
-    160^3 finite-volume diffusion matrix (seed 3)."""
+    """Time to a 1e-10 FP64 relative residual of the other solver forms, each
+    beside FP64 Jacobi-PCG on the same matrix (best of 3 after a warm-up):
+    mixed precision on the 160^3 finite-volume diffusion matrix (seed 3), and
+    the learned factor (committed weights, prediction included) on the first
+    unseen 128^3 diffusion matrix (seed 1000)."""
     import torch
 
     from paper_1211_1581_amd import inputs as I
-    from paper_1211_1581_amd import spcg
+    from paper_1211_1581_amd import spcg, train
     dev = torch.device("cuda:0")
-    A, _, xs = I.fv_diffusion(160, 3)
-    b = I.rhs_from_solution(A, xs)
-    M = spcg.CsrMatrix.from_host(A, device=dev)
-    bt = torch.as_tensor(b, device=dev)
     out = {}
+    A, _, xs = I.fv_diffusion(160, 3)
+    M = spcg.CsrMatrix.from_host(A, device=dev)
+    bt = torch.as_tensor(I.rhs_from_solution(A, xs), device=dev)
+    res = {}
     for prec in ("f64", "mixed"):
         opts = spcg.cg_opts(tol=1e-10, maxit=20000, precond="jacobi", precision=prec)
-        work = spcg.CgWorkspace(M, opts)
-        x = torch.zeros_like(bt)
-        spcg.cg_solve(M, bt, x, opts=opts, work=work, want_hist=False)
-        ts = []
-        for _ in range(3):
-            x.zero_()
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            r = spcg.cg_solve(M, bt, x, opts=opts, work=work, want_hist=False)
-            torch.cuda.synchronize()
-            ts.append(time.perf_counter() - t)
-        out[prec] = {"ms": round(1e3 * min(ts), 2), "iters": r["iters"],
-                     "n_updates": r["n_updates"], "true_relres": r["true_relres"],
-                     "status": r["status"]}
-    out["workload"] = "FV diffusion 160^3, GRF seed 3, Jacobi-PCG vs FP32-inner reliable-update"
+        res[prec] = _time_solve(M, bt, opts, spcg.CgWorkspace(M, opts))
+    out["mixed_vs_jacobi"] = {"workload": "FV diffusion 160^3 (n=4096000), GRF seed 3; FP64 "
+                                          "Jacobi-PCG vs FP32-inner / FP64 reliable-update",
+                              "jacobi_f64": res["f64"], "mixed": res["mixed"],
+                              "speedup": round(res["f64"]["ms"] / res["mixed"]["ms"], 3)}
+    del M, bt
+    A, _, xs = I.fv_diffusion(128, 1000)
+    M = spcg.CsrMatrix.from_host(A, device=dev)
+    bt = torch.as_tensor(I.rhs_from_solution(A, xs), device=dev)
+    w, meta = train.load_weights()
+    wt = torch.tensor(w, device=dev)
+    g = spcg.MpnnGraph(M)
+    budget = train.budget_for(128, 117.0)
+    oj = spcg.cg_opts(tol=1e-10, maxit=20000, precond="jacobi")
+    ol = spcg.cg_opts(tol=1e-10, maxit=20000, precond="learned", G=g.G, GT=g.GT, budget=budget)
+    rj = _time_solve(M, bt, oj, spcg.CgWorkspace(M, oj))
+    rl = _time_solve(M, bt, ol, spcg.CgWorkspace(M, ol), pre=lambda: g.predict(wt))
+    out["learned_vs_jacobi"] = {"workload": "FV diffusion 128^3 (n=2097152), unseen seed 1000; "
+                                            "FP64 Jacobi-PCG vs learned G G^T (prediction "
+                                            "included, training excluded)",
+                                "jacobi_f64": rj, "learned": rl, "budget": budget,
+                                "speedup": round(rj["ms"] / rl["ms"], 3)}
     return out
 
 

@@ -51,8 +51,16 @@ k_validate(int n, int ncols, int64_t nnz, const int32_t *__restrict__ rp,
         const int c = col[k];
         if (c < 0 || c >= ncols) err |= 8;
     }
-    if (err) atomicOr(&flags[0], err);
-    if (mx) atomicMax(&flags[1], mx);
+    // one atomic per wavefront
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        err |= __shfl_xor(err, o, 64);
+        mx = max(mx, __shfl_xor(mx, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (err) atomicOr(&flags[0], err);
+        if (mx) atomicMax(&flags[1], mx);
+    }
 }
 
 // block_row[b] = first row i with row_ptr[i] + i >= b * kChunk (b < nb),

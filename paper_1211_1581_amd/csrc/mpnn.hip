@@ -150,28 +150,67 @@ __global__ void k_rev(int E, const int32_t *__restrict__ rp, const int32_t *__re
     rev[e] = (rp[j] - j) + (lo - rp[j]) - (lo > dpos[j] ? 1 : 0);
 }
 
-// exclusive scan of cnt[0..n) into out[0..n], one workgroup of 1024 threads
-__global__ void __launch_bounds__(1024) k_scan(int n, const int32_t *__restrict__ cnt, int32_t *out) {
-    __shared__ int64_t sh[1024];
+// Exclusive scan of cnt[0..n) into out[0..n] in three steps: chunk sums
+// (k_scan_sums), a one-workgroup scan of the chunk sums (k_scan_top), and a
+// rescan of every chunk from its offset (k_scan_apply).
+constexpr int kScanChunk = 4096;
+
+__global__ void __launch_bounds__(256) k_scan_sums(int n, const int32_t *__restrict__ cnt,
+                                                   int32_t *sums) {
+    __shared__ int red[4];
+    const int base = blockIdx.x * kScanChunk;
+    int s = 0;
+    for (int i = base + threadIdx.x; i < min(n, base + kScanChunk); i += 256) s += cnt[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) sums[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_top(int nb, int32_t *sums) {
+    __shared__ int32_t sh[1024];
     const int T = 1024, t = threadIdx.x;
-    const int per = (n + T - 1) / T;
-    const int a = min(n, t * per), b = min(n, a + per);
-    int64_t s = 0;
-    for (int i = a; i < b; ++i) s += cnt[i];
+    const int per = (nb + T - 1) / T;
+    const int a = min(nb, t * per), b = min(nb, a + per);
+    int32_t s = 0;
+    for (int i = a; i < b; ++i) s += sums[i];
     sh[t] = s;
     __syncthreads();
     for (int o = 1; o < T; o <<= 1) {
-        const int64_t v = t >= o ? sh[t - o] : 0;
+        const int32_t v = t >= o ? sh[t - o] : 0;
         __syncthreads();
         sh[t] += v;
         __syncthreads();
     }
-    int64_t run = sh[t] - s;
+    int32_t run = sh[t] - s;
     for (int i = a; i < b; ++i) {
-        out[i] = (int32_t)run;
+        const int32_t c = sums[i];
+        sums[i] = run;
+        run += c;
+    }
+    if (t == T - 1) sums[nb] = sh[T - 1];
+}
+
+__global__ void __launch_bounds__(256) k_scan_apply(int n, const int32_t *__restrict__ cnt,
+                                                    const int32_t *__restrict__ offs, int32_t *out) {
+    __shared__ int32_t sh[256];
+    const int base = blockIdx.x * kScanChunk;
+    const int per = kScanChunk / 256;
+    const int a = min(n, base + threadIdx.x * per), b = min(n, a + per);
+    int32_t s = 0;
+    for (int i = a; i < b; ++i) s += cnt[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const int32_t v = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int32_t run = offs[blockIdx.x] + sh[threadIdx.x] - s;
+    for (int i = a; i < b; ++i) {
+        out[i] = run;
         run += cnt[i];
     }
-    if (t == T - 1) out[n] = (int32_t)sh[T - 1];
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 255) out[n] = offs[gridDim.x];
 }
 
 // G (tril) and G^T (triu) patterns, and the G^T <- G value map
@@ -1028,8 +1067,19 @@ int spcg_mpnn_create(spcg_mpnn_t *out, spcg_csr_t A, int32_t flags, hipStream_t 
     if (E > 0)
         hipLaunchKernelGGL(k_rev, dim3(g1(E)), dim3(256), 0, s, (int)E, A->row_ptr, A->col,
                            g->erow, g->ecol, g->dpos, g->rev, g->flags);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, n, (const int32_t *)g->cntL, g->g_rp);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, n, (const int32_t *)g->cntU, g->gt_rp);
+    {
+        const int nb = (n + kScanChunk - 1) / kScanChunk;
+        MP_ALLOC(g->lpart, std::max<int64_t>(nb + 1, g1(n)));
+        int32_t *sums = reinterpret_cast<int32_t *>(g->lpart);
+        const int32_t *cnts[2] = {g->cntL, g->cntU};
+        int32_t *outs[2] = {g->g_rp, g->gt_rp};
+        for (int q = 0; q < 2; ++q) {
+            hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(256), 0, s, n, cnts[q], sums);
+            hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, nb, sums);
+            hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(256), 0, s, n, cnts[q],
+                               (const int32_t *)sums, outs[q]);
+        }
+    }
     MP_TRY(hipGetLastError());
     int32_t *hp = (int32_t *)g->h_pinned;
     MP_TRY(hipMemcpyAsync(hp, g->flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -1056,7 +1106,6 @@ int spcg_mpnn_create(spcg_mpnn_t *out, spcg_csr_t A, int32_t flags, hipStream_t 
     MP_ALLOC(g->fe, 2 * (int64_t)n);
     MP_ALLOC(g->ge, 2 * E);
     const int nfp = (int)g1(n);
-    MP_ALLOC(g->lpart, nfp);
     hipLaunchKernelGGL(k_nodefeat, dim3(nfp), dim3(256), 0, s, n, (const double *)A->vals, g->dpos,
                        g->s64, g->s32, g->logd, g->lpart, g->flags);
     hipLaunchKernelGGL(k_mean, dim3(1), dim3(kFinThreads), 0, s, nfp, (const float *)g->lpart, n,

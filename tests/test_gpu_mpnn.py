@@ -47,8 +47,10 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def test_factor_pattern_and_zero_head():
-    A, _, _ = I.fv_diffusion(7, 4, corr_len=2.0)
+@pytest.mark.parametrize("N", [7, 45])
+def test_factor_pattern_and_zero_head(N):
+    # 45^3 rows span many chunks of the device scan that builds the patterns
+    A, _, _ = I.fv_diffusion(N, 4, corr_len=2.0)
     M, g = graph(A)
     P0 = mpnn.unflatten(I.mpnn_init(mpnn.param_spec(), 0))
     w = torch.tensor(mpnn.flatten(P0), dtype=torch.float32, device="cuda")
