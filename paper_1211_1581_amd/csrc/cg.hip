@@ -370,16 +370,31 @@ struct EpiStore64 {
     __device__ __forceinline__ void row(int i, double s) { y[i] = s; }
 };
 
-// t = G^T r  (in a pass after K2, or at a phase start when expect < 0)
+// G^T and G handles as the apply kernels see them
+struct FactorDev {
+    CsrDev A;
+    const float *__restrict__ vals;
+    int n;
+};
+
+// t = G^T r.  kexp: pass number the state must be at, or -1 at a phase start.
+// SHORT: every row of G^T has at most kShortLen entries.
+template <bool SHORT>
 SPCG_ROWBLOCK_KERNEL
-k_gt_apply(CsrDev GT, const float *__restrict__ vals, const double *__restrict__ r,
-           double *__restrict__ t, const CgState *st, int expect) {
+k_gt_apply(FactorDev GT, const double *__restrict__ r, double *__restrict__ t, const CgState *st,
+           int kexp) {
     __shared__ SpmvSmem<double> sm;
-    if (st->halt != RUN || (expect >= 0 && st->k != expect + 1)) return;
+    if (st->halt != RUN || (kexp >= 0 && st->k != kexp)) return;
     int bs, be;
-    block_range(GT.n_blocks, bs, be);
     EpiStore64 epi{t};
-    for (int k = bs; k < be; ++k) spmv_block<float, double, double>(GT, vals, r, k, sm, epi);
+    if constexpr (SHORT) {
+        block_range((int)short_steps(GT.n), bs, be);
+        for (int k = bs; k < be; ++k)
+            spmv_short<float, double, double>(GT.A.row_ptr, GT.A.col, GT.vals, r, GT.n, k, epi);
+    } else {
+        block_range(GT.A.n_blocks, bs, be);
+        for (int k = bs; k < be; ++k) spmv_block<float, double, double>(GT.A, GT.vals, r, k, sm, epi);
+    }
 }
 
 struct EpiZ {
@@ -393,30 +408,53 @@ struct EpiZ {
 };
 
 // z = G t; partial r.z
+template <bool SHORT>
 SPCG_ROWBLOCK_KERNEL
-k_g_apply(CsrDev G, const float *__restrict__ vals, const double *__restrict__ t,
-          const double *__restrict__ r, double *__restrict__ z, const CgState *st, double *part,
-          int expect) {
+k_g_apply(FactorDev G, const double *__restrict__ t, const double *__restrict__ r,
+          double *__restrict__ z, const CgState *st, double *part, int kexp) {
     __shared__ SpmvSmem<double> sm;
-    if (st->halt != RUN || (expect >= 0 && st->k != expect + 1)) return;
+    if (st->halt != RUN || (kexp >= 0 && st->k != kexp)) return;
     int bs, be;
-    const int slot = block_range(G.n_blocks, bs, be);
     EpiZ epi{z, r, 0.0};
-    for (int k = bs; k < be; ++k) spmv_block<float, double, double>(G, vals, t, k, sm, epi);
+    int slot;
+    if constexpr (SHORT) {
+        slot = block_range((int)short_steps(G.n), bs, be);
+        for (int k = bs; k < be; ++k)
+            spmv_short<float, double, double>(G.A.row_ptr, G.A.col, G.vals, t, G.n, k, epi);
+    } else {
+        slot = block_range(G.A.n_blocks, bs, be);
+        for (int k = bs; k < be; ++k) spmv_block<float, double, double>(G.A, G.vals, t, k, sm, epi);
+    }
     const double v[1] = {block_sum(epi.acc, sm.red)};
     store_partials(part, slot, v);
 }
 
-// rho' = r.z, beta = rho' / rho
+// End of a learned pass (one finalize for both reductions): ||r||^2 from the
+// update kernel's partials and r.z from the G-apply partials -> pass count,
+// history, stop decision, beta and rho.  z of the last pass is computed even
+// when the pass converges; it is not used.
 __global__ void __launch_bounds__(kFinThreads)
-k_fin_grz(CgState *st, const double *part, int nslots, int expect) {
-    if (st->halt != RUN || st->k != expect + 1) return;
-    double s[1];
-    finalize_sum(part, nslots, s);
+k_fin_learned(CgState *st, const double *part_xr, int n_xr, const double *part_g, int n_g,
+              double *hist, int expect) {
+    if (st->halt != RUN || st->k != expect) return;
+    double t[2], g[1];
+    finalize_sum(part_xr, n_xr, t);
+    finalize_sum(part_g, n_g, g);
     if (threadIdx.x != 0) return;
-    const double rho = s[0];
-    if (!finite_d(rho)) set_break(st, NAN);
-    else if (st->rr > 0.0 && !(rho > 0.0)) set_break(st, rho);
+    const int k = expect + 1;
+    st->k = k;
+    const double rr = t[1], rho = g[0];
+    const double est = sqrt(rr);
+    hist[k] = est / st->nb;
+    if (!finite_d(rr) || !finite_d(rho)) {
+        set_break(st, NAN);
+        return;
+    }
+    st->rr = rr;
+    if (est <= st->thresh) st->halt = H_CONV;
+    else if (k >= st->maxit) st->halt = H_MAXIT;
+    else if (k >= st->budget) st->halt = H_BUDGET;
+    else if (rr > 0.0 && !(rho > 0.0)) set_break(st, rho);
     else {
         st->beta = rho / st->rho;
         st->rho = rho;
@@ -576,15 +614,25 @@ struct Work {
     double *r, *p, *q, *dinv, *z, *t, *x0;
     float *r32, *p32, *q32, *x32, *dinv32, *vals32;
     double *partd;  // [nslots * 2]
+    double *partg;  // [nslots]  (learned: r.z partials of the G apply)
     float *partf;   // [nslots * 2]
     int64_t nslots;
 };
 
+// Workgroups of a factor apply (row-block or short-row kernel)
+static unsigned factor_grid(const spcg_csr *F) {
+    return uses_short_rows(F) ? spmv_grid(short_steps(F->n_rows)) : spmv_grid(F->n_blocks);
+}
+
+static FactorDev factor_view(const spcg_csr *F) {
+    return FactorDev{dev_view(F), (const float *)F->vals, F->n_rows};
+}
+
 static int64_t n_slots(const spcg_csr *A, const spcg_cg_opts *o) {
     int64_t s = std::max<int64_t>(spmv_grid(A->n_blocks), vec_blocks(A->n_rows));
     if (o->precond == SPCG_PRECOND_LEARNED) {
-        if (o->G) s = std::max<int64_t>(s, spmv_grid(o->G->n_blocks));
-        if (o->GT) s = std::max<int64_t>(s, spmv_grid(o->GT->n_blocks));
+        for (const spcg_csr *F : {o->G, o->GT})
+            if (F) s = std::max<int64_t>(s, factor_grid(F));
     }
     return std::max<int64_t>(s, 1);
 }
@@ -624,6 +672,7 @@ static size_t carve(const spcg_csr *A, const spcg_cg_opts *o, char *base, Work *
         W.vals32 = (float *)take(sizeof(float) * (size_t)A->nnz);
     }
     W.partd = (double *)take(sizeof(double) * 2 * W.nslots);
+    if (learned) W.partg = (double *)take(sizeof(double) * W.nslots);
     W.partf = (float *)take(sizeof(float) * 2 * W.nslots);
     if (w) *w = W;
     return off;
@@ -698,8 +747,23 @@ struct Solver {
     }
     unsigned gv() const { return grid_of(A->n_rows, kVecBlock); }
     unsigned gA() const { return spmv_grid(A->n_blocks); }
-    unsigned gG() const { return spmv_grid(o->G->n_blocks); }
-    unsigned gGT() const { return spmv_grid(o->GT->n_blocks); }
+    unsigned gG() const { return factor_grid(o->G); }
+
+    // z = G (G^T r); r.z partials of the G apply in w.partg
+    void apply_factor(int kexp) {
+        if (uses_short_rows(o->GT))
+            hipLaunchKernelGGL(k_gt_apply<true>, dim3(factor_grid(o->GT)), dim3(kBlock), 0, s,
+                               factor_view(o->GT), (const double *)w.r, w.t, w.st, kexp);
+        else
+            hipLaunchKernelGGL(k_gt_apply<false>, dim3(factor_grid(o->GT)), dim3(kBlock), 0, s,
+                               factor_view(o->GT), (const double *)w.r, w.t, w.st, kexp);
+        if (uses_short_rows(o->G))
+            hipLaunchKernelGGL(k_g_apply<true>, dim3(gG()), dim3(kBlock), 0, s, factor_view(o->G),
+                               (const double *)w.t, (const double *)w.r, w.z, w.st, w.partg, kexp);
+        else
+            hipLaunchKernelGGL(k_g_apply<false>, dim3(gG()), dim3(kBlock), 0, s, factor_view(o->G),
+                               (const double *)w.t, (const double *)w.r, w.z, w.st, w.partg, kexp);
+    }
 
     int resid(int mode, float *r32) {
         hipLaunchKernelGGL(k_resid, dim3(gA()), dim3(kBlock), 0, s, dev_view(A),
@@ -714,12 +778,7 @@ struct Solver {
     int start(int pre) {
         const int n = A->n_rows;
         if (pre == SPCG_PRECOND_LEARNED) {
-            hipLaunchKernelGGL(k_gt_apply, dim3(gGT()), dim3(kBlock), 0, s,
-                               dev_view(o->GT), (const float *)o->GT->vals, (const double *)w.r,
-                               w.t, w.st, -1);
-            hipLaunchKernelGGL(k_g_apply, dim3(gG()), dim3(kBlock), 0, s,
-                               dev_view(o->G), (const float *)o->G->vals, (const double *)w.t,
-                               (const double *)w.r, w.z, w.st, w.partd, -1);
+            apply_factor(-1);
             hipLaunchKernelGGL(k_start<SPCG_PRECOND_LEARNED>, dim3(gv()), dim3(kBlock), 0, s, n,
                                w.r, w.dinv, w.z, w.p, w.st, w.partd);
         } else if (pre == SPCG_PRECOND_JACOBI) {
@@ -767,16 +826,9 @@ struct Solver {
         } else {
             hipLaunchKernelGGL((k_cg_xr<double, SPCG_PRECOND_LEARNED>), dim3(gv()), dim3(kBlock),
                                0, s, n, e, x, w.r, w.p, w.q, w.dinv, w.st, w.partd);
-            hipLaunchKernelGGL((k_fin_xr<double, SPCG_PRECOND_LEARNED, false>), dim3(1),
-                               dim3(kFinThreads), 0, s, w.st, pd, (int)gv(), w.hist, e);
-            hipLaunchKernelGGL(k_gt_apply, dim3(gGT()), dim3(kBlock), 0, s,
-                               dev_view(o->GT), (const float *)o->GT->vals, (const double *)w.r,
-                               w.t, w.st, e);
-            hipLaunchKernelGGL(k_g_apply, dim3(gG()), dim3(kBlock), 0, s,
-                               dev_view(o->G), (const float *)o->G->vals, (const double *)w.t,
-                               (const double *)w.r, w.z, w.st, w.partd, e);
-            hipLaunchKernelGGL(k_fin_grz, dim3(1), dim3(kFinThreads), 0, s, w.st, pd,
-                               (int)gG(), e);
+            apply_factor(e);
+            hipLaunchKernelGGL(k_fin_learned, dim3(1), dim3(kFinThreads), 0, s, w.st, pd, (int)gv(),
+                               (const double *)w.partg, (int)gG(), w.hist, e);
             hipLaunchKernelGGL((k_cg_p<double, SPCG_PRECOND_LEARNED>), dim3(gv()), dim3(kBlock),
                                0, s, n, e, w.r, w.dinv, w.z, w.p, w.st);
         }

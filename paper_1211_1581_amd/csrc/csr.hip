@@ -112,9 +112,26 @@ k_spmv(CsrDev A, const T *__restrict__ vals, const T *__restrict__ x, T *__restr
     for (int b = bs; b < be; ++b) spmv_block<T, T, T>(A, vals, x, b, sm, epi);
 }
 
+// y = A x for matrices whose rows have at most kShortLen entries
+template <typename T>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8)))
+k_spmv_short(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+             const T *__restrict__ vals, const T *__restrict__ x, T *__restrict__ y) {
+    int bs, be;
+    block_range((int)short_steps(n), bs, be);
+    EpiStore<T> epi{y};
+    for (int b = bs; b < be; ++b) spmv_short<T, T, T>(rp, col, vals, x, n, b, epi);
+}
+
 template <typename T>
 int launch_spmv(const spcg_csr *A, const T *x, T *y, hipStream_t s) {
     if (A->n_rows == 0) return SPCG_OK;
+    if (uses_short_rows(A)) {
+        hipLaunchKernelGGL(k_spmv_short<T>, dim3(spmv_grid(short_steps(A->n_rows))), dim3(kBlock),
+                           0, s, A->n_rows, A->row_ptr, A->col, (const T *)A->vals, x, y);
+        SPCG_LAUNCH_CHECK("k_spmv_short");
+        return SPCG_OK;
+    }
     hipLaunchKernelGGL(k_spmv<T>, dim3(spmv_grid(A->n_blocks)), dim3(kBlock), 0, s, dev_view(A),
                        (const T *)A->vals, x, y);
     SPCG_LAUNCH_CHECK("k_spmv");

@@ -170,6 +170,31 @@ struct SpmvSmem {
     TA last;
 };
 
+// Products of NU rounds of kBlock entries starting at k0 (cnt >= 1 entries
+// are real; the clamped tail re-reads the last one and is not stored).
+template <int NU, typename TV, typename TX, typename TA>
+__device__ __forceinline__ void block_products(const CsrDev &A, const TV *__restrict__ vals,
+                                               const TX *__restrict__ x, int k0, int cnt,
+                                               TA *__restrict__ slab) {
+    const int tid = threadIdx.x;
+    int c[NU];
+    TV v[NU];
+    TX xv[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int t = min(tid + u * kBlock, cnt - 1);
+        c[u] = __builtin_nontemporal_load(A.col + k0 + t);
+        v[u] = __builtin_nontemporal_load(vals + k0 + t);
+    }
+#pragma unroll
+    for (int u = 0; u < NU; ++u) xv[u] = x[c[u]];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int t = tid + u * kBlock;
+        if (t < cnt) slab[t] = TA(v[u]) * TA(xv[u]);
+    }
+}
+
 // Row products of one row block.  TV: value type, TX: vector type, TA:
 // accumulation type.  epi.row(i, s) is called exactly once for every row i
 // of the block, by one thread, with consecutive threads on consecutive rows.
@@ -190,30 +215,24 @@ __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict
     const int cnt = min(kend - k0, kSlab);
     const int nr = r1 - r0;
 
-    // phase 1: coalesced streams of col/vals, then the gather of x, products to LDS
-    constexpr int U = kSlab / kBlock;
-    int c[U];
-    TV v[U];
-    TX xv[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int t = tid + u * kBlock;
-        if (t < cnt) {
-            c[u] = __builtin_nontemporal_load(A.col + k0 + t);
-            v[u] = __builtin_nontemporal_load(vals + k0 + t);
-        }
+    // phase 1: coalesced streams of col/vals, then the gather of x, products
+    // to LDS.  The loads are straight-line code (indices clamped into the
+    // block, nothing guarded by a branch), so each gather waits only for its
+    // own column index and all of them are in flight together.
+    const int rv = A.row_ptr[r0 + min(tid, nr)];
+    switch ((cnt + kBlock - 1) / kBlock) {
+        case 1: block_products<1>(A, vals, x, k0, cnt, sm.slab); break;
+        case 2: block_products<2>(A, vals, x, k0, cnt, sm.slab); break;
+        case 3: block_products<3>(A, vals, x, k0, cnt, sm.slab); break;
+        case 4: block_products<4>(A, vals, x, k0, cnt, sm.slab); break;
+        case 5: block_products<5>(A, vals, x, k0, cnt, sm.slab); break;
+        case 6: block_products<6>(A, vals, x, k0, cnt, sm.slab); break;
+        case 7: block_products<7>(A, vals, x, k0, cnt, sm.slab); break;
+        default: break;  // only empty rows
     }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int t = tid + u * kBlock;
-        if (t < cnt) xv[u] = x[c[u]];
-    }
-    for (int t = tid; t <= nr; t += kBlock) sm.rp[t] = A.row_ptr[r0 + t] - k0;
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int t = tid + u * kBlock;
-        if (t < cnt) sm.slab[t] = TA(v[u]) * TA(xv[u]);
-    }
+    static_assert(kSlab <= 7 * kBlock, "block_products covers at most 7 rounds");
+    if (tid <= nr) sm.rp[tid] = rv - k0;
+    for (int t = tid + kBlock; t <= nr; t += kBlock) sm.rp[t] = A.row_ptr[r0 + t] - k0;
     __syncthreads();
 
     // phase 2: L lanes per row, L = pow2 floor of the mean row length (<= 64);
@@ -261,6 +280,65 @@ __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict
     __syncthreads();  // the LDS slab is reused by the next row block
 }
 
+// ------------------------------------------------------- short rows --
+//
+// Matrices whose rows all have at most kShortLen entries (the triangular
+// factors of a 7-point stencil have at most 4) skip the LDS staging: a group
+// of kShortLen lanes owns one row and reduces it with two butterfly steps.  A
+// workgroup handles kShortRounds rounds of 64 consecutive rows at once with
+// straight-line loads (indices clamped into the row, the product masked), so
+// all column, value and gather loads of those rows are in flight together.
+constexpr int kShortLen = 4;
+constexpr int kShortRounds = 4;
+constexpr int kShortRows = (kBlock / kShortLen) * kShortRounds;  // rows per workgroup step
+
+__host__ __device__ inline int64_t short_steps(int64_t n_rows) { return (n_rows + kShortRows - 1) / kShortRows; }
+
+// Rows [b * kShortRows, (b + 1) * kShortRows) of an n-row matrix with nnz >= 1
+// and every row at most kShortLen long.  epi.row(i, s) is called once per row,
+// by the group's first lane.
+template <typename TV, typename TX, typename TA, class Epi>
+__device__ __forceinline__ void spmv_short(const int32_t *__restrict__ rp,
+                                           const int32_t *__restrict__ col,
+                                           const TV *__restrict__ vals, const TX *__restrict__ x,
+                                           int n, int b, Epi &epi) {
+    constexpr int G = kBlock / kShortLen;
+    const int lane = threadIdx.x & (kShortLen - 1);
+    const int g = threadIdx.x / kShortLen;
+    const int base = b * kShortRows;
+    int a[kShortRounds], e[kShortRounds], c[kShortRounds];
+    TV v[kShortRounds];
+    TA s[kShortRounds];
+#pragma unroll
+    for (int u = 0; u < kShortRounds; ++u) {
+        const int r = min(base + u * G + g, n - 1);
+        a[u] = rp[r];
+        e[u] = rp[r + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kShortRounds; ++u) {
+        const int k = a[u] + lane;
+        const int kc = k < e[u] ? k : max(e[u] - 1, 0);
+        c[u] = __builtin_nontemporal_load(col + kc);
+        v[u] = __builtin_nontemporal_load(vals + kc);
+    }
+#pragma unroll
+    for (int u = 0; u < kShortRounds; ++u) {
+        const TX xv = x[c[u]];
+        s[u] = a[u] + lane < e[u] ? TA(v[u]) * TA(xv) : TA(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kShortRounds; ++u) {
+        s[u] += __shfl_xor(s[u], 1, 64);
+        s[u] += __shfl_xor(s[u], 2, 64);
+    }
+#pragma unroll
+    for (int u = 0; u < kShortRounds; ++u) {
+        const int r = base + u * G + g;
+        if (lane == 0 && r < n) epi.row(r, s[u]);
+    }
+}
+
 // Contiguous range of row blocks owned by this workgroup; the workgroup's
 // logical index (XCD-remapped) is also its partial-sum slot.
 __device__ __forceinline__ int block_range(int nb, int &bs, int &be) {
@@ -269,6 +347,11 @@ __device__ __forceinline__ int block_range(int nb, int &bs, int &be) {
     bs = (int)((int64_t)nb * w / P);
     be = (int)((int64_t)nb * (w + 1) / P);
     return w;
+}
+
+// Short-row kernels apply when every row has at most kShortLen entries.
+inline bool uses_short_rows(const spcg_csr *A) {
+    return A->n_rows > 0 && A->nnz > 0 && A->max_len <= kShortLen;
 }
 
 inline CsrDev dev_view(const spcg_csr *A) {

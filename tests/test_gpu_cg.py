@@ -106,6 +106,32 @@ def test_learned_form_with_jacobi_factor():
     assert fo["status"] == oracle.FELL_BACK and within(f["iters_fallback"], fo["iters_fallback"])
 
 
+@pytest.mark.parametrize("case", ["banded", "poisson2d"])
+def test_learned_form_general_factor(case):
+    # a factor with off-diagonal values: rows of up to 5 entries (row-block
+    # apply kernels) or at most 3 (short-row apply kernels)
+    A = I.banded_spd(3000, 9) if case == "banded" else I.poisson2d(60)
+    b = I.rhs_from_solution(A, I.uniform_vector(A.n_rows, 4))
+    Lh, _ = lower_upper(A)
+    rng = np.random.default_rng(9)
+    rows = np.repeat(np.arange(A.n_rows), np.diff(Lh.row_ptr))
+    d = A.to_scipy().diagonal()
+    gv = np.where(Lh.col == rows, 1.0, rng.uniform(0.05, 0.25, Lh.nnz)) / np.sqrt(d[rows])
+    gv = gv.astype(np.float32).astype(np.float64)
+    Lh2, Uh2 = lower_upper(A, gv)
+    S = spcg()
+    G = S.CsrMatrix.from_host(Lh2, dtype=torch.float32)
+    GT = S.CsrMatrix.from_host(Uh2, dtype=torch.float32)
+    assert (G.info()["max_row_len"] > 4) == (case == "banded")
+    M = S.CsrMatrix.from_host(A)
+    ref = oracle.pcg(A, b, tol=1e-10, maxit=5000, precond="g", G=Lh2)
+    g = S.cg_solve(M, to_dev(b), tol=1e-10, maxit=5000, precond="learned", G=G, GT=GT)
+    assert g["status"] == 0 and ref["status"] == 0 and within(g["iters"], ref["iters"])
+    assert oracle.true_relres(A, b, g["x"].cpu().numpy()) <= 1e-10
+    n = min(len(ref["hist"]), len(g["hist"]), 40)
+    assert np.allclose(g["hist"][:n], ref["hist"][:n], rtol=1e-6, atol=0)
+
+
 def test_deterministic_solves():
     A, _, xs = I.fv_diffusion(32, 8)
     b = I.rhs_from_solution(A, xs)

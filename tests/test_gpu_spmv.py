@@ -8,7 +8,7 @@ import torch
 
 import oracle
 from paper_1211_1581_amd import inputs as I
-from gpu_util import U32, check_f64, dense_abs_product, gamma, spcg, to_dev
+from gpu_util import U32, check_f64, dense_abs_product, gamma, lower_upper, spcg, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -53,6 +53,35 @@ def test_edge_shapes():
     A, x = I.random_csr_small(50, 20000, 3, max_len=3, long_rows=[(49, 20000), (0, 12000)])
     y, M = run(A, x)
     check_f64(y, oracle.spmv(A, x), A, x, "long rows")
+
+
+@pytest.mark.parametrize("n", [1, 5, 255, 257, 1000, 70001])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_short_rows_bit_exact(n, dtype):
+    # every row at most 4 entries: the short-row kernel (empty rows, ragged
+    # tail of a workgroup step, unsorted columns)
+    A, x = I.random_csr_small(n, max(n, 7), n + 11, max_len=4, integer=True, unsorted=True)
+    if A.nnz == 0:
+        A, x = I.random_csr_small(n, max(n, 7), n + 12, max_len=4, integer=True, empty_frac=0.0)
+    y, M = run(A, x, dtype)
+    assert M.info()["max_row_len"] <= 4
+    assert np.array_equal(y.astype(np.float64), oracle.spmv(A, x))
+
+
+def test_short_rows_factor_pattern():
+    # lower and upper triangles of the 7-point stencil (at most 4 per row),
+    # and the 5-entry boundary case that stays on the row-block kernel
+    A = I.poisson3d(24)
+    L, U = lower_upper(A, np.random.default_rng(0).uniform(-1, 1, (A.nnz + A.n_rows) // 2))
+    x = np.random.default_rng(1).uniform(-1, 1, A.n_rows)
+    for F in (L, U):
+        y, M = run(F, x)
+        assert M.info()["max_row_len"] == 4
+        check_f64(y, oracle.spmv(F, x), F, x, "factor pattern")
+    B, xb = I.random_csr_small(3000, 3000, 5, max_len=5, empty_frac=0.0)
+    y, M = run(B, xb)
+    assert M.info()["max_row_len"] == 5
+    check_f64(y, oracle.spmv(B, xb), B, xb, "len 5")
 
 
 @pytest.mark.parametrize("n,maxlen", [(257, 5), (4099, 80), (20011, 300)])
