@@ -14,6 +14,10 @@ FP64 oracle on the host cores on a bounded sample of the same workload;
 `forms` gives the time to tolerance of the mixed-precision and learned forms
 beside plain FP64 Jacobi-PCG on their own matrices.
 
+`workloads` adds plain CG on the 2-D Poisson 64^2 system and the cold
+standalone SpMV of the other matrices and precisions; `copy_gbs` is the
+measured device-copy ceiling.
+
     python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--cpu-seconds 15] [--no-forms]
 """
 from __future__ import annotations
@@ -82,10 +86,39 @@ def cpu_baseline(A, b, seconds):
     r = oracle.pcg(A, b, tol=0.0, maxit=passes, precond="jacobi")
     dt = time.perf_counter() - t
     gbs = r["iters"] * jpcg_pass_bytes(n, nnz) / dt / 1e9
-    return {"value": round(gbs, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
-            "sample": f"{r['iters']} Jacobi-PCG passes (with set-up) of the 128^3 Poisson "
-                      f"system in {dt:.1f} s; a full solve takes 425 passes",
-            "est_time_to_tol_s": round(dt / r["iters"] * 425, 2)}
+    out = {"value": round(gbs, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
+           "sample": f"{r['iters']} Jacobi-PCG passes (with set-up) of the 128^3 Poisson "
+                     f"system in {dt:.1f} s; a full solve takes 425 passes",
+           "est_time_to_tol_s": round(dt / r["iters"] * 425, 2)}
+    out["spmv_gbs"] = cpu_spmv_rates(A)
+    return out
+
+
+def cpu_spmv_rates(A):
+    """Oracle SpMV rate (median of 5) on all threads and on one thread, for the
+    128^3 Poisson matrix and the lognormal irregular matrix (FP64)."""
+    import numpy as np
+
+    import oracle
+    from paper_1211_1581_amd import inputs as I
+    L, xl = I.lognormal_irregular()
+    res = {}
+    full = oracle.set_threads(0)
+    for name, M, x in (("poisson128_f64", A, np.linspace(-1.0, 1.0, A.n_cols)),
+                       ("lognormal_f64", L, xl)):
+        row = {}
+        for label, th in (("all_threads", full), ("one_thread", 1)):
+            oracle.set_threads(th)
+            ts = []
+            for _ in range(5):
+                t = time.perf_counter()
+                oracle.spmv(M, x)
+                ts.append(time.perf_counter() - t)
+            row[label] = round(spmv_bytes(M.n_rows, M.nnz) / sorted(ts)[2] / 1e9, 2)
+        res[name] = row
+    oracle.set_threads(full)
+    res["threads"] = full
+    return res
 
 
 def main():
@@ -100,6 +133,13 @@ def main():
                          "hardware byte counters)")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the mixed-precision (160^3) and learned (128^3) time-to-tolerance")
+    ap.add_argument("--tables", action="store_true",
+                    help="run the paper's own input tables instead (SpMV over the Table 1 "
+                         "matrices, plain CG over the Table 2 banded systems) beside the "
+                         "oracle on the host, and print that record")
+    ap.add_argument("--form", choices=("mixed", "learned"), default=None,
+                    help="run only this solver form beside FP64 Jacobi-PCG and print its "
+                         "record (for kernel traces of one workload)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -114,6 +154,12 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.form:
+        print(json.dumps(forms(args, only=args.form)), flush=True)
+        return
+    if args.tables:
+        print(json.dumps(tables()), flush=True)
+        return
     if args.calib:
         src = torch.ones(2 ** 25, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -206,11 +252,154 @@ def main():
                      "bytes_per_launch": b_spmv, "avg_launch_us": round(avg_us, 2),
                      "launches": spmv_calls},
     }
+    line["copy_gbs"] = copy_rate()
     if not args.no_forms:
+        line["workloads"] = workloads(A, xs)
         line["forms"] = forms(args)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(A, b, args.cpu_seconds)
     print(json.dumps(line), flush=True)
+
+
+def copy_rate():
+    """Device-to-device copy of 512 MiB (read + write bytes / time, median of
+    10): the streaming ceiling the SpMV rates can be read against."""
+    import numpy as np
+    import torch
+    src = torch.ones(2 ** 26, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    ts = []
+    for _ in range(10):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    del src, dst
+    return round(2 * 2 ** 29 / float(np.median(ts)) / 1e9, 1)
+
+
+def cold_spmv(A, x, dtype, reps=30):
+    """Median duration of spmv_csr rotating over enough device copies of A
+    that their total exceeds 600 MB (more than twice the 256 MB last-level
+    cache), so every launch streams the matrix from HBM."""
+    import numpy as np
+    import torch
+
+    from paper_1211_1581_amd import spcg
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    sv = 8 if dtype == "f64" else 4
+    b = spmv_bytes(A.n_rows, A.nnz, sv=sv, sx=sv)
+    ncopy = max(3, -(-600_000_000 // b))
+    copies = [spcg.CsrMatrix.from_host(A, dtype=tdt) for _ in range(ncopy)]
+    xt = torch.as_tensor(x).to(tdt).cuda()
+    y = torch.empty(A.n_rows, dtype=tdt, device="cuda")
+    for i in range(2 * ncopy):
+        spcg.spmv_csr(copies[i % ncopy], xt, y)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    for i, (e0, e1) in enumerate(evs):
+        e0.record()
+        spcg.spmv_csr(copies[i % ncopy], xt, y)
+        e1.record()
+    torch.cuda.synchronize()
+    us = float(np.median([e0.elapsed_time(e1) * 1e3 for e0, e1 in evs]))
+    del copies
+    gbs = b / (us * 1e-6) / 1e9
+    return {"us": round(us, 2), "gbs": round(gbs, 1), "pct_peak": round(100 * gbs / PEAK_HBM_GBS, 1),
+            "bytes": b, "copies": ncopy}
+
+
+def workloads(A128, x128):
+    """The other measured configurations: plain CG on the 2-D Poisson 64^2
+    system (cache-resident, latency-bound: time and per-pass cost, no
+    bandwidth figure), and the cold standalone SpMV of the 128^3 Poisson
+    matrix in FP32 and of the lognormal irregular matrix in FP64 and FP32."""
+    import torch
+
+    from paper_1211_1581_amd import inputs as I
+    from paper_1211_1581_amd import spcg
+    out = {}
+    P = I.poisson2d(64)
+    b = I.rhs_from_solution(P, I.uniform_vector(P.n_rows, 0))
+    M = spcg.CsrMatrix.from_host(P)
+    bt = torch.as_tensor(b, device="cuda")
+    opts = spcg.cg_opts(tol=1e-10, maxit=2000, precond="none")
+    r = _time_solve(M, bt, opts, spcg.CgWorkspace(M, opts), reps=10)
+    out["cg_poisson2d_64"] = {"workload": "2-D 5-point Poisson 64^2, plain CG to 1e-10 (one "
+                                          "workgroup holds the whole loop)",
+                              "ms": r["ms"], "iters": r["iters"],
+                              "us_per_pass": round(1e3 * r["ms"] / max(r["iters"], 1), 2),
+                              "true_relres": r["true_relres"], "status": r["status"]}
+    del M, bt
+    out["spmv_cold"] = {"poisson128_f32": cold_spmv(A128, x128, "f32")}
+    L, xl = I.lognormal_irregular()
+    out["spmv_cold"]["lognormal_f64"] = cold_spmv(L, xl, "f64")
+    out["spmv_cold"]["lognormal_f32"] = cold_spmv(L, xl, "f32")
+    out["spmv_cold"]["lognormal_workload"] = ("n = 200000, lognormal row lengths (median 48, "
+                                              "max 4096), nnz = 15788355, seed 2")
+    return out
+
+
+def tables():
+    """The paper's input tables on one GPU (all cache-resident, so latency
+    rather than HBM bandwidth bounds them): spmv_csr over the Table 1 square
+    matrices (median of 50 launches; GFLOP/s = 2 nnz / time) and plain CG to
+    1e-10 over the Table 2 banded systems (best of 5 solves), each beside the
+    FP64 oracle on the host cores."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1211_1581_amd import inputs as I
+    from paper_1211_1581_amd import spcg
+    out = {"table1_spmv": [], "table2_cg": [], "cpu_threads": oracle.set_threads(0)}
+    for n, fill in I.TABLE1_MOD2AS:
+        A, x = I.random_fill(n, fill, seed=n)
+        M = spcg.CsrMatrix.from_host(A)
+        xt = torch.as_tensor(x, device="cuda")
+        y = torch.empty(n, dtype=torch.float64, device="cuda")
+        for _ in range(5):
+            spcg.spmv_csr(M, xt, y)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(50)]
+        for e0, e1 in evs:
+            e0.record()
+            spcg.spmv_csr(M, xt, y)
+            e1.record()
+        torch.cuda.synchronize()
+        us = float(np.median([e0.elapsed_time(e1) * 1e3 for e0, e1 in evs]))
+        ts = []
+        for _ in range(20):
+            t = time.perf_counter()
+            oracle.spmv(A, x)
+            ts.append(time.perf_counter() - t)
+        cus = 1e6 * float(np.median(ts))
+        out["table1_spmv"].append({"n": n, "fill_percent": fill, "nnz": A.nnz,
+                                   "gpu_us": round(us, 2),
+                                   "gpu_gflops": round(2 * A.nnz / us / 1e3, 2),
+                                   "gpu_gbs": round(spmv_bytes(n, A.nnz) / us / 1e3, 1),
+                                   "cpu_us": round(cus, 2),
+                                   "cpu_gflops": round(2 * A.nnz / cus / 1e3, 2)})
+    for n, bw in I.TABLE2_CG:
+        A = I.banded_spd(n, bw)
+        b = I.rhs_from_solution(A, I.uniform_vector(n, n + bw))
+        M = spcg.CsrMatrix.from_host(A)
+        bt = torch.as_tensor(b, device="cuda")
+        opts = spcg.cg_opts(tol=1e-10, maxit=2000, precond="none")
+        r = _time_solve(M, bt, opts, spcg.CgWorkspace(M, opts), reps=5)
+        t = time.perf_counter()
+        ro = oracle.pcg(A, b, tol=1e-10, maxit=2000, precond="none")
+        cms = 1e3 * (time.perf_counter() - t)
+        out["table2_cg"].append({"n": n, "bw": bw, "nnz": A.nnz, "gpu_ms": r["ms"],
+                                 "iters": r["iters"],
+                                 "gpu_us_per_pass": round(1e3 * r["ms"] / max(r["iters"], 1), 2),
+                                 "true_relres": r["true_relres"], "status": r["status"],
+                                 "cpu_ms": round(cms, 3), "cpu_iters": ro["iters"]})
+    return out
 
 
 def _time_solve(M, bt, opts, work, reps=3, pre=None):
@@ -233,18 +422,26 @@ def _time_solve(M, bt, opts, work, reps=3, pre=None):
             "n_updates": r["n_updates"], "true_relres": r["true_relres"], "status": r["status"]}
 
 
-def forms(args):
+def forms(args, only=None):
     """Time to a 1e-10 FP64 relative residual of the other solver forms, each
     beside FP64 Jacobi-PCG on the same matrix (best of 3 after a warm-up):
     mixed precision on the 160^3 finite-volume diffusion matrix (seed 3), and
     the learned factor (committed weights, prediction included) on the first
     unseen 128^3 diffusion matrix (seed 1000)."""
+    out = {}
+    if only != "learned":
+        out["mixed_vs_jacobi"] = _mixed_form()
+    if only != "mixed":
+        out["learned_vs_jacobi"] = _learned_form()
+    return out
+
+
+def _mixed_form():
     import torch
 
     from paper_1211_1581_amd import inputs as I
-    from paper_1211_1581_amd import spcg, train
+    from paper_1211_1581_amd import spcg
     dev = torch.device("cuda:0")
-    out = {}
     A, _, xs = I.fv_diffusion(160, 3)
     M = spcg.CsrMatrix.from_host(A, device=dev)
     bt = torch.as_tensor(I.rhs_from_solution(A, xs), device=dev)
@@ -252,11 +449,18 @@ def forms(args):
     for prec in ("f64", "mixed"):
         opts = spcg.cg_opts(tol=1e-10, maxit=20000, precond="jacobi", precision=prec)
         res[prec] = _time_solve(M, bt, opts, spcg.CgWorkspace(M, opts))
-    out["mixed_vs_jacobi"] = {"workload": "FV diffusion 160^3 (n=4096000), GRF seed 3; FP64 "
-                                          "Jacobi-PCG vs FP32-inner / FP64 reliable-update",
-                              "jacobi_f64": res["f64"], "mixed": res["mixed"],
-                              "speedup": round(res["f64"]["ms"] / res["mixed"]["ms"], 3)}
-    del M, bt
+    return {"workload": "FV diffusion 160^3 (n=4096000), GRF seed 3; FP64 "
+                        "Jacobi-PCG vs FP32-inner / FP64 reliable-update",
+            "jacobi_f64": res["f64"], "mixed": res["mixed"],
+            "speedup": round(res["f64"]["ms"] / res["mixed"]["ms"], 3)}
+
+
+def _learned_form():
+    import torch
+
+    from paper_1211_1581_amd import inputs as I
+    from paper_1211_1581_amd import spcg, train
+    dev = torch.device("cuda:0")
     A, _, xs = I.fv_diffusion(128, 1000)
     M = spcg.CsrMatrix.from_host(A, device=dev)
     bt = torch.as_tensor(I.rhs_from_solution(A, xs), device=dev)
@@ -268,12 +472,18 @@ def forms(args):
     ol = spcg.cg_opts(tol=1e-10, maxit=20000, precond="learned", G=g.G, GT=g.GT, budget=budget)
     rj = _time_solve(M, bt, oj, spcg.CgWorkspace(M, oj))
     rl = _time_solve(M, bt, ol, spcg.CgWorkspace(M, ol), pre=lambda: g.predict(wt))
-    out["learned_vs_jacobi"] = {"workload": "FV diffusion 128^3 (n=2097152), unseen seed 1000; "
-                                            "FP64 Jacobi-PCG vs learned G G^T (prediction "
-                                            "included, training excluded)",
-                                "jacobi_f64": rj, "learned": rl, "budget": budget,
-                                "speedup": round(rj["ms"] / rl["ms"], 3)}
-    return out
+    # classical FSAI on the same pattern (set-up included), the non-learned comparator
+    gf = spcg.MpnnGraph(M, ws=g.ws)
+    of = spcg.cg_opts(tol=1e-10, maxit=20000, precond="learned", G=gf.G, GT=gf.GT, budget=20000)
+    rf = _time_solve(M, bt, of, spcg.CgWorkspace(M, of),
+                     pre=lambda: spcg.fsai_values(M, gf.G, gf.GT))
+    return {"workload": "FV diffusion 128^3 (n=2097152), unseen seed 1000; "
+                        "FP64 Jacobi-PCG vs learned G G^T (prediction "
+                        "included, training excluded) and FSAI G G^T on the same "
+                        "pattern (set-up included)",
+            "jacobi_f64": rj, "learned": rl, "fsai": rf, "budget": budget,
+            "speedup": round(rj["ms"] / rl["ms"], 3),
+            "fsai_speedup": round(rj["ms"] / rf["ms"], 3)}
 
 
 if __name__ == "__main__":

@@ -161,6 +161,28 @@ int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o
              void *d_work, size_t work_bytes, spcg_cg_result *res, double *h_hist,
              hipStream_t stream);
 
+/* ------------------------------ factorized sparse approximate inverse (FSAI) */
+
+/*
+ * Values of the classical factorized sparse approximate inverse (Kolotilina
+ * and Yeremin) on a given lower pattern: a non-learned factor G for
+ * M^-1 = G G^T (cg_solve with SPCG_PRECOND_LEARNED and opts.G / opts.GT).
+ * Column i of G has the row set J_i = {j >= i : G_ji in the pattern}, sorted,
+ * J_i[0] = i; the library solves the dense SPD system A[J_i, J_i] y = e_1 and
+ * sets G[J_i, i] = y / sqrt(y_1), so (G^T A G)_ii = 1; with the full lower
+ * pattern G G^T = A^-1 exactly.
+ * A: square F64 handle (entries of A[J_i, J_i] are read from the rows in J_i;
+ * duplicates are summed).  G, GT: F32 handles of the same order, GT the
+ * transpose of G with the diagonal first in every row (sorted columns do
+ * that), at most SPCG_FSAI_MAX_SET entries per row of GT; both value arrays
+ * are overwritten, so they must be writable device memory.
+ * Errors: SPCG_INVALID_ARG for types, sizes or patterns that break these
+ * rules, SPCG_NOT_SPD if a local system is not positive definite,
+ * SPCG_NON_FINITE for NaN/Inf.  Synchronous.
+ */
+#define SPCG_FSAI_MAX_SET 8
+int spcg_fsai_values(spcg_csr_t A, spcg_csr_t G, spcg_csr_t GT, hipStream_t stream);
+
 /* ------------------------------------------- learned factor (G on tril(A)) */
 
 /*

@@ -49,6 +49,8 @@ def lib():
         P = ctypes.c_void_p
         i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         L.oracle_csr_check.argtypes = [i32, i32, i64, P, P]
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_threads.restype = ctypes.c_int
         L.oracle_spmv_csr.argtypes = [i32, P, P, P, P, P]
         L.oracle_spmv_csr.restype = None
         L.oracle_spmv_csr_f32in.argtypes = [i32, P, P, P, P, P]
@@ -84,6 +86,11 @@ def csr_check(A) -> int:
     if rp.size != A.n_rows + 1:
         return INVALID_CSR
     return lib().oracle_csr_check(A.n_rows, A.n_cols, c.size, _p(rp), _p(c))
+
+
+def set_threads(n: int) -> int:
+    """Threads of the OpenMP row loops (n <= 0: unchanged); returns the previous count."""
+    return lib().oracle_set_threads(int(n))
 
 
 def spmv(A, x) -> np.ndarray:

@@ -33,6 +33,7 @@
  * the precision the mixed form prescribes.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -71,6 +72,15 @@ int oracle_csr_check(int32_t n_rows, int32_t n_cols, int64_t nnz,
 /* y = A x, all n rows, overwrite (Sec. 3.2).  Each row is summed from zero in
  * index order; rows are independent, so threading over rows leaves every
  * bit of y unchanged. */
+/* Thread count of the OpenMP row loops (host plumbing for timing runs; the
+ * results do not depend on it).  n <= 0 leaves it unchanged.  Returns the
+ * previous maximum. */
+int oracle_set_threads(int n) {
+    const int old = omp_get_max_threads();
+    if (n > 0) omp_set_num_threads(n);
+    return old;
+}
+
 void oracle_spmv_csr(int32_t n_rows, const int32_t *row_ptr, const int32_t *col,
                      const double *vals, const double *x, double *y) {
 #pragma omp parallel for schedule(static)

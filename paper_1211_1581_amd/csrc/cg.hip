@@ -134,8 +134,8 @@ struct EpiResid {
     double *__restrict__ r;
     float *__restrict__ r32;
     double bb, rr;
-    __device__ __forceinline__ void row(int i, double s) {
-        const double bi = b[i];
+    __device__ __forceinline__ double load(int i) const { return b[i]; }
+    __device__ __forceinline__ void row(int i, double s, double bi) {
         const double ri = bi - s;
         r[i] = ri;
         if (r32) r32[i] = (float)ri;
@@ -235,9 +235,10 @@ struct EpiPQ {
     T *__restrict__ q;
     const T *__restrict__ p;
     T acc;
-    __device__ __forceinline__ void row(int i, T s) {
+    __device__ __forceinline__ T load(int i) const { return p[i]; }
+    __device__ __forceinline__ void row(int i, T s, T pi) {
         q[i] = s;
-        acc += p[i] * s;
+        acc += pi * s;
     }
 };
 
@@ -367,7 +368,8 @@ k_cg_p(int n, int expect, const T *__restrict__ r, const T *__restrict__ dinv,
 
 struct EpiStore64 {
     double *__restrict__ y;
-    __device__ __forceinline__ void row(int i, double s) { y[i] = s; }
+    __device__ __forceinline__ NoOperand load(int) const { return {}; }
+    __device__ __forceinline__ void row(int i, double s, NoOperand) { y[i] = s; }
 };
 
 // G^T and G handles as the apply kernels see them
@@ -401,9 +403,10 @@ struct EpiZ {
     double *__restrict__ z;
     const double *__restrict__ r;
     double acc;
-    __device__ __forceinline__ void row(int i, double s) {
+    __device__ __forceinline__ double load(int i) const { return r[i]; }
+    __device__ __forceinline__ void row(int i, double s, double ri) {
         z[i] = s;
-        acc += r[i] * s;
+        acc += ri * s;
     }
 };
 
@@ -438,8 +441,7 @@ k_fin_learned(CgState *st, const double *part_xr, int n_xr, const double *part_g
               double *hist, int expect) {
     if (st->halt != RUN || st->k != expect) return;
     double t[2], g[1];
-    finalize_sum(part_xr, n_xr, t);
-    finalize_sum(part_g, n_g, g);
+    finalize_sum2<double, 2, 1>(part_xr, n_xr, t, part_g, n_g, g);
     if (threadIdx.x != 0) return;
     const int k = expect + 1;
     st->k = k;
@@ -621,7 +623,7 @@ struct Work {
 
 // Workgroups of a factor apply (row-block or short-row kernel)
 static unsigned factor_grid(const spcg_csr *F) {
-    return uses_short_rows(F) ? spmv_grid(short_steps(F->n_rows)) : spmv_grid(F->n_blocks);
+    return uses_short_rows(F) ? short_grid(F->n_rows) : spmv_grid(F->n_blocks);
 }
 
 static FactorDev factor_view(const spcg_csr *F) {
@@ -920,9 +922,12 @@ struct Solver {
     }
 };
 
+// The single-workgroup solver runs on one CU: a pass costs about 6 us plus
+// ~0.85 ns per nonzero there, against ~30 us for the five-launch pass of the
+// grid-wide kernels on a tiny matrix, so it only pays up to ~32K nonzeros.
 static int small_ok(const spcg_csr *A, const spcg_cg_opts *o) {
     return o->small_path && o->precision == SPCG_PREC_F64 && o->precond != SPCG_PRECOND_LEARNED &&
-           A->n_rows <= 16384 && A->nnz <= (int64_t)1 << 18;
+           A->n_rows <= 16384 && A->nnz <= (int64_t)1 << 15;
 }
 
 }  // namespace spcg

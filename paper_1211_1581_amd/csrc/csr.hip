@@ -99,7 +99,8 @@ k_count_long(const int32_t *__restrict__ rp, const int32_t *__restrict__ block_r
 template <typename T>
 struct EpiStore {
     T *__restrict__ y;
-    __device__ __forceinline__ void row(int i, T s) { y[i] = s; }
+    __device__ __forceinline__ NoOperand load(int) const { return {}; }
+    __device__ __forceinline__ void row(int i, T s, NoOperand) { y[i] = s; }
 };
 
 template <typename T>
@@ -127,7 +128,7 @@ template <typename T>
 int launch_spmv(const spcg_csr *A, const T *x, T *y, hipStream_t s) {
     if (A->n_rows == 0) return SPCG_OK;
     if (uses_short_rows(A)) {
-        hipLaunchKernelGGL(k_spmv_short<T>, dim3(spmv_grid(short_steps(A->n_rows))), dim3(kBlock),
+        hipLaunchKernelGGL(k_spmv_short<T>, dim3(short_grid(A->n_rows)), dim3(kBlock),
                            0, s, A->n_rows, A->row_ptr, A->col, (const T *)A->vals, x, y);
         SPCG_LAUNCH_CHECK("k_spmv_short");
         return SPCG_OK;

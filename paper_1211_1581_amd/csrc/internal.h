@@ -53,7 +53,7 @@ constexpr int kMaxGrid = 8192;           // workgroups of a row-block kernel (ea
 
 // Row-block kernels run 8 waves per SIMD (8 workgroups of 256 per CU): the
 // register budget is capped at 64 VGPRs so latency hiding is not traded away.
-#define SPCG_ROWBLOCK_KERNEL __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
+#define SPCG_ROWBLOCK_KERNEL __global__ void __launch_bounds__(256)
 
 void set_error(hipError_t e, const char *what);
 int hip_status(hipError_t e, const char *what);
@@ -124,32 +124,66 @@ __device__ __forceinline__ void store_partials(T *part, int slot, const T (&v)[N
     }
 }
 
-// Fixed-order total of nslots x NV partials; call from all kFinThreads
-// threads of a one-workgroup kernel; every thread receives the totals.
-template <typename T, int NV>
-__device__ __forceinline__ void finalize_sum(const T *__restrict__ part, int nslots, T (&tot)[NV]) {
+// Fixed-order totals of two partial arrays at once: a (na >= 1 slots x NA
+// values) and b (nb >= 1 slots x NB values).  Call from all kFinThreads
+// threads of a one-workgroup kernel; every thread receives the totals.  The
+// slots are loaded kFinPer per thread and round together (clamped indices,
+// no branch around the loads), then added in slot order.
+template <typename T, int NA, int NB>
+__device__ __forceinline__ void finalize_sum2(const T *__restrict__ a, int na, T (&ta)[NA],
+                                              const T *__restrict__ b, int nb, T *tb) {
+    constexpr int NV = NA + NB;
+    constexpr int kFinPer = 8;
     __shared__ T sh[kFinThreads / 64][NV];
     T acc[NV];
 #pragma unroll
     for (int j = 0; j < NV; ++j) acc[j] = T(0);
-    for (int i = threadIdx.x; i < nslots; i += kFinThreads) {
+    const int tid = threadIdx.x;
+    const int nmax = na > nb ? na : nb;
+    for (int base = 0; base < nmax; base += kFinThreads * kFinPer) {
+        T v[kFinPer][NV];
 #pragma unroll
-        for (int j = 0; j < NV; ++j) acc[j] += part[(size_t)i * NV + j];
+        for (int u = 0; u < kFinPer; ++u) {
+            const int i = base + tid + u * kFinThreads;
+            const int ia = min(i, na - 1);
+#pragma unroll
+            for (int j = 0; j < NA; ++j) v[u][j] = a[(size_t)ia * NA + j];
+            if constexpr (NB > 0) {
+                const int ib = min(i, nb - 1);
+#pragma unroll
+                for (int j = 0; j < NB; ++j) v[u][NA + j] = b[(size_t)ib * NB + j];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kFinPer; ++u) {
+            const int i = base + tid + u * kFinThreads;
+#pragma unroll
+            for (int j = 0; j < NA; ++j) acc[j] += i < na ? v[u][j] : T(0);
+#pragma unroll
+            for (int j = NA; j < NV; ++j) acc[j] += i < nb ? v[u][j] : T(0);
+        }
     }
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
         acc[j] = wave_sum(acc[j]);
-        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6][j] = acc[j];
+        if ((tid & 63) == 0) sh[tid >> 6][j] = acc[j];
     }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
-        T s = T(0);
+        T t = T(0);
 #pragma unroll
-        for (int w = 0; w < kFinThreads / 64; ++w) s += sh[w][j];
-        tot[j] = s;
+        for (int w = 0; w < kFinThreads / 64; ++w) t += sh[w][j];
+        if (j < NA) ta[j] = t;
+        else if constexpr (NB > 0) tb[j - NA] = t;
     }
     __syncthreads();
+}
+
+// Fixed-order total of nslots >= 1 x NV partials (see finalize_sum2).
+template <typename T, int NV>
+__device__ __forceinline__ void finalize_sum(const T *__restrict__ part, int nslots, T (&tot)[NV]) {
+    finalize_sum2<T, NV, 0>(part, nslots, tot, part, 1, nullptr);
 }
 
 // ------------------------------------------------------------- SpMV core --
@@ -195,20 +229,34 @@ __device__ __forceinline__ void block_products(const CsrDev &A, const TV *__rest
     }
 }
 
+// Per-row operand of an epilogue that needs none.
+struct NoOperand {};
+
+// Read of an array that no kernel running at the same time writes, at an
+// index that is uniform over the workgroup (row-block descriptors): through
+// the constant address space the compiler issues a scalar load, which does not
+// wait for the workgroup's outstanding vector stores the way a vector load
+// followed by a full vmcnt wait would.
+__device__ __forceinline__ int32_t load_uniform(const int32_t *p, int i) {
+    return ((const __attribute__((address_space(4))) int32_t *)p)[i];
+}
+
 // Row products of one row block.  TV: value type, TX: vector type, TA:
-// accumulation type.  epi.row(i, s) is called exactly once for every row i
-// of the block, by one thread, with consecutive threads on consecutive rows.
-// Must be called by all 256 threads.
+// accumulation type.  epi.row(i, s, epi.load(i)) is called exactly once for
+// every row i of the block, by one thread, with consecutive threads on
+// consecutive rows; epi.load(i) (the epilogue's per-row operand, e.g. p_i for
+// p.q) is issued at the start of the block so its latency hides behind the
+// block's loads.  Must be called by all 256 threads.
 template <typename TV, typename TX, typename TA, class Epi>
 __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict__ vals,
                                            const TX *__restrict__ x, int blk,
                                            SpmvSmem<TA> &sm, Epi &epi) {
     const int tid = threadIdx.x;
-    const int r0 = A.block_row[blk];
-    const int r1 = A.block_row[blk + 1];
+    const int r0 = load_uniform(A.block_row, blk);
+    const int r1 = load_uniform(A.block_row, blk + 1);
     if (r0 >= r1) return;  // uniform over the workgroup
-    const int k0 = A.block_k[blk];
-    const int kend = A.block_k[blk + 1];
+    const int k0 = load_uniform(A.block_k, blk);
+    const int kend = load_uniform(A.block_k, blk + 1);
     // a block whose entries overflow the slab ends in a long row (every other
     // row of a block has fewer than kChunk entries); that row is reduced below
     const bool long_last = (kend - k0) > kSlab;
@@ -220,6 +268,7 @@ __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict
     // block, nothing guarded by a branch), so each gather waits only for its
     // own column index and all of them are in flight together.
     const int rv = A.row_ptr[r0 + min(tid, nr)];
+    const auto pre = epi.load(r0 + min(tid, nr - 1));  // the epilogue's operand of row r0 + tid
     switch ((cnt + kBlock - 1) / kBlock) {
         case 1: block_products<1>(A, vals, x, k0, cnt, sm.slab); break;
         case 2: block_products<2>(A, vals, x, k0, cnt, sm.slab); break;
@@ -275,7 +324,7 @@ __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict
         TA s;
         if (long_last && t == nr - 1) s = sm.last;
         else s = sm.rp[t + 1] > sm.rp[t] ? sm.slab[sm.rp[t]] : TA(0);
-        epi.row(r0 + t, s);
+        epi.row(r0 + t, s, t == tid ? pre : epi.load(r0 + t));
     }
     __syncthreads();  // the LDS slab is reused by the next row block
 }
@@ -294,9 +343,12 @@ constexpr int kShortRows = (kBlock / kShortLen) * kShortRounds;  // rows per wor
 
 __host__ __device__ inline int64_t short_steps(int64_t n_rows) { return (n_rows + kShortRows - 1) / kShortRows; }
 
+// Workgroups of a short-row kernel (each walks a contiguous range of steps)
+inline unsigned short_grid(int64_t n_rows) { return spmv_grid(short_steps(n_rows)); }
+
 // Rows [b * kShortRows, (b + 1) * kShortRows) of an n-row matrix with nnz >= 1
-// and every row at most kShortLen long.  epi.row(i, s) is called once per row,
-// by the group's first lane.
+// and every row at most kShortLen long.  epi.row(i, s, epi.load(i)) is called
+// once per row, by the group's first lane (the loads are issued up front).
 template <typename TV, typename TX, typename TA, class Epi>
 __device__ __forceinline__ void spmv_short(const int32_t *__restrict__ rp,
                                            const int32_t *__restrict__ col,
@@ -309,11 +361,13 @@ __device__ __forceinline__ void spmv_short(const int32_t *__restrict__ rp,
     int a[kShortRounds], e[kShortRounds], c[kShortRounds];
     TV v[kShortRounds];
     TA s[kShortRounds];
+    decltype(epi.load(0)) pre[kShortRounds];
 #pragma unroll
     for (int u = 0; u < kShortRounds; ++u) {
         const int r = min(base + u * G + g, n - 1);
         a[u] = rp[r];
         e[u] = rp[r + 1];
+        pre[u] = epi.load(r);
     }
 #pragma unroll
     for (int u = 0; u < kShortRounds; ++u) {
@@ -335,7 +389,7 @@ __device__ __forceinline__ void spmv_short(const int32_t *__restrict__ rp,
 #pragma unroll
     for (int u = 0; u < kShortRounds; ++u) {
         const int r = base + u * G + g;
-        if (lane == 0 && r < n) epi.row(r, s[u]);
+        if (lane == 0 && r < n) epi.row(r, s[u], pre[u]);
     }
 }
 

@@ -484,7 +484,8 @@ namespace mp {
 
 struct EpiStore32 {
     float *__restrict__ y;
-    __device__ __forceinline__ void row(int i, float s) { y[i] = s; }
+    __device__ __forceinline__ NoOperand load(int) const { return {}; }
+    __device__ __forceinline__ void row(int i, float s, NoOperand) { y[i] = s; }
 };
 
 // t = G^T u (row sums), r = t - v, s = 2 r / (n m); partial sum of r^2
@@ -493,8 +494,9 @@ struct EpiResidLoss {
     float *__restrict__ s;
     float scale;
     float acc;
-    __device__ __forceinline__ void row(int i, float t) {
-        const float r = t - v[i];
+    __device__ __forceinline__ float load(int i) const { return v[i]; }
+    __device__ __forceinline__ void row(int i, float t, float vi) {
+        const float r = t - vi;
         s[i] = scale * r;
         acc += r * r;
     }

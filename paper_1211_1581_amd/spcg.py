@@ -388,3 +388,22 @@ def adam_step(w, g, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     L = _mpnn_sigs(lib())
     _check(L.spcg_adam_step(_ptr(w), _ptr(g), _ptr(m), _ptr(v), w.numel(), t, lr, beta1, beta2,
                             eps, _stream()), "spcg_adam_step")
+
+
+# --------------------------------------------- factorized sparse approximate inverse --
+
+FSAI_MAX_SET = 8
+
+
+def fsai_values(A: CsrMatrix, G, GT):
+    """Overwrite the FP32 values of the lower factor G and of its transpose GT
+    (handles on one pattern, e.g. an MpnnGraph's G and GT) with the classical
+    factorized sparse approximate inverse of A (see spcg_fsai_values)."""
+    L = lib()
+    if not getattr(L, "_fsai_ready", False):
+        P = ctypes.c_void_p
+        L.spcg_fsai_values.argtypes = [P, P, P, P]
+        L._fsai_ready = True
+    st = L.spcg_fsai_values(A.handle, G.handle, GT.handle, _stream())
+    if st != OK:  # a local system that is not SPD is an error here, not a solver outcome
+        raise SpcgError(st, "spcg_fsai_values")
