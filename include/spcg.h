@@ -53,6 +53,9 @@ extern "C" {
 #define SPCG_PRECOND_LEARNED 2
 #define SPCG_PREC_F64 0
 #define SPCG_PREC_MIXED 1
+/* CG variants of cg_solve */
+#define SPCG_CG_STANDARD 0          /* the loop of Sec. 3.4: two reductions per pass */
+#define SPCG_CG_SINGLE_REDUCTION 1  /* Chronopoulos-Gear: one joint reduction per pass */
 
 typedef struct spcg_csr *spcg_csr_t;
 
@@ -116,9 +119,14 @@ typedef struct {
     spcg_csr_t GT;       /* learned: its transpose (pattern of triu(A)), F32 values */
     int32_t budget;      /* learned: passes allowed before the Jacobi fallback */
     int32_t small_path;  /* 1 = allow the single-workgroup solver for small n, 0 = never */
-    int32_t timing;      /* 1 = bracket every SpMV launch of the pass loop with HIP events on
-                            `stream` and report their summed duration (events are created on the
-                            handle the first time; adds an event record per launch) */
+    int32_t timing;      /* N > 0: bracket the SpMV launch of every N-th pass of the loop with
+                            HIP events on `stream` and report their summed duration and count
+                            (events are created on the handle the first time; each bracketed
+                            launch costs a few microseconds more, so N > 1 samples) */
+    int32_t variant;     /* SPCG_CG_STANDARD, or SPCG_CG_SINGLE_REDUCTION (FP64 with NONE or
+                            JACOBI only): u = M^-1 r, w = A u and s = A p by recurrence, so
+                            r.u, w.u and r.r come from one reduction per pass (Chronopoulos
+                            and Gear); the same iterates in exact arithmetic */
 } spcg_cg_opts;
 
 typedef struct {
@@ -127,12 +135,13 @@ typedef struct {
     int32_t n_updates;      /* mixed: FP64 residual replacements */
     int32_t n_restarts;     /* true-residual restarts */
     double true_relres;     /* ||b - A x||_2 / ||b||_2 recomputed in FP64 at exit */
-    double spmv_ms;         /* timing = 1: summed duration of the timed SpMV launches */
-    int32_t spmv_calls;     /* timing = 1: number of SpMV launches that ran and were timed */
+    double spmv_ms;         /* timing > 0: summed duration of the timed SpMV launches */
+    int32_t spmv_calls;     /* timing > 0: number of SpMV launches that ran and were timed */
     int32_t reserved;
 } spcg_cg_result;
 
-/* Fill opts with defaults: tol 1e-10, maxit 20000, Jacobi, FP64, adaptive checks, delta 0.1. */
+/* Fill opts with defaults: tol 1e-10, maxit 20000, Jacobi, FP64, adaptive checks, delta 0.1,
+ * standard variant. */
 void spcg_cg_default_opts(spcg_cg_opts *opts);
 
 /* Bytes of device workspace cg_solve needs for A and opts (256-byte aligned pointer). */

@@ -65,6 +65,7 @@ def lib():
         L.oracle_pcg_learned.argtypes = [i32, P, P, P, P, P, P, P, P, f64, i32, i32,
                                          P, P, P, P, P]
         L.oracle_cg_mixed.argtypes = [i32, P, P, P, P, P, f64, i32, f64, P, P, P, P]
+        L.oracle_cg_single_reduction.argtypes = [i32, P, P, P, P, P, ctypes.c_int, f64, i32, P, P, P]
         _lib = L
     return _lib
 
@@ -146,6 +147,22 @@ def pcg(A, b, x0=None, tol=1e-10, maxit=2000, precond="jacobi", G=None):
     st = lib().oracle_pcg(A.n_rows, _p(rp), _p(c), _p(v), _p(b), _p(x), kind, None,
                           _p(grp), _p(gc), _p(gv), tol, maxit, ctypes.byref(it),
                           _p(hist), ctypes.byref(tr))
+    k = it.value
+    return dict(status=st, x=x, iters=k, hist=hist[:k + 1].copy(), true_relres=tr.value)
+
+
+def cg_single_reduction(A, b, x0=None, tol=1e-10, maxit=2000, precond="jacobi"):
+    """Chronopoulos-Gear single-reduction PCG.  Returns dict(status, x, iters,
+    hist, true_relres)."""
+    kind = {"none": PRECOND_NONE, "jacobi": PRECOND_JACOBI}[precond]
+    rp, c, v, b = _i32(A.row_ptr), _i32(A.col), _f64(A.vals), _f64(b)
+    x = np.zeros(A.n_rows) if x0 is None else _f64(x0).copy()
+    hist = np.full(maxit + 1, np.nan)
+    it = ctypes.c_int32(0)
+    tr = ctypes.c_double(0.0)
+    st = lib().oracle_cg_single_reduction(A.n_rows, _p(rp), _p(c), _p(v), _p(b), _p(x), kind,
+                                          tol, maxit, ctypes.byref(it), _p(hist),
+                                          ctypes.byref(tr))
     k = it.value
     return dict(status=st, x=x, iters=k, hist=hist[:k + 1].copy(), true_relres=tr.value)
 

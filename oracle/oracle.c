@@ -292,6 +292,104 @@ done:
 }
 
 /*
+ * Single-reduction PCG (Chronopoulos and Gear, 1989): the same Krylov iterates
+ * as the loop above in exact arithmetic, with the two inner products of a
+ * pass replaced by one joint reduction.  With u = M^-1 r and w = A u:
+ *
+ *   r = b - A x0;  u = M^-1 r;  w = A u;  gamma = r.u;  delta = w.u
+ *   alpha = gamma / delta;  beta = 0;  p = s = 0
+ *   while ||r|| > tol ||b||  and  k < maxit:
+ *       p = u + beta p;  s = w + beta s          (s = A p by recurrence)
+ *       x += alpha p;  r -= alpha s;  u = M^-1 r;  w = A u
+ *       gamma' = r.u;  delta = w.u;  (and ||r||^2)      -- one reduction
+ *       beta = gamma' / gamma;  alpha = gamma' / (delta - beta gamma' / alpha)
+ *       k += 1;  hist[k] = ||r|| / ||b||
+ *
+ * A non-positive gamma (with r != 0) or denominator means A or M is not SPD.
+ * Exit, true-residual restart (from u = M^-1 r, p = s = 0), ||b|| = 0 and
+ * status codes as oracle_pcg.  precond_kind: NONE or JACOBI.
+ */
+int oracle_cg_single_reduction(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                               const double *vals, const double *b, double *x, int precond_kind,
+                               double tol, int32_t maxit, int32_t *iters, double *hist,
+                               double *true_relres) {
+    *iters = 0;
+    *true_relres = 0.0;
+    if (n < 0 || maxit < 0 || !(tol >= 0.0)) return OR_INVALID_ARG;
+    if (precond_kind != OR_PRECOND_NONE && precond_kind != OR_PRECOND_JACOBI) return OR_INVALID_ARG;
+    if (!all_finite(n, b) || !all_finite(n, x)) return OR_NON_FINITE;
+    double nb = sqrt(oracle_dot(n, b, b));
+    if (nb == 0.0) {
+        for (int32_t i = 0; i < n; ++i) x[i] = 0.0;
+        if (hist) hist[0] = 0.0;
+        return OR_OK;
+    }
+    size_t bytes = (size_t)(n > 0 ? n : 1) * sizeof(double);
+    double *r = malloc(bytes), *u = malloc(bytes), *w = malloc(bytes), *p = malloc(bytes);
+    double *sv = malloc(bytes), *dinv = NULL;
+    precond_t M = {precond_kind, NULL, NULL, NULL, NULL, NULL};
+    int status = OR_OK;
+    if (precond_kind == OR_PRECOND_JACOBI) {
+        dinv = malloc(bytes);
+        status = oracle_jacobi_dinv(n, row_ptr, col, vals, dinv);
+        M.dinv = dinv;
+    }
+    int32_t k = 0;
+    int restarts = 0;
+    if (status != OR_OK) goto done;
+
+    oracle_spmv_csr(n, row_ptr, col, vals, x, w);
+    for (int32_t i = 0; i < n; ++i) r[i] = b[i] - w[i];
+    for (;;) {
+        apply_precond(&M, n, r, u);
+        oracle_spmv_csr(n, row_ptr, col, vals, u, w);
+        double gamma = oracle_dot(n, r, u);
+        double delta = oracle_dot(n, w, u);
+        double rr = oracle_dot(n, r, r);
+        if (hist) hist[k] = sqrt(rr) / nb;
+        if (!isfinite(gamma) || !isfinite(delta) || !isfinite(rr)) { status = OR_NON_FINITE; goto done; }
+        if (rr > 0.0 && (!(gamma > 0.0) || !(delta > 0.0))) { status = OR_NOT_SPD; goto done; }
+        double alpha = rr > 0.0 ? gamma / delta : 0.0, beta = 0.0;
+        for (int32_t i = 0; i < n; ++i) p[i] = sv[i] = 0.0;
+
+        while (sqrt(rr) > tol * nb && k < maxit) {
+            for (int32_t i = 0; i < n; ++i) p[i] = u[i] + beta * p[i];
+            for (int32_t i = 0; i < n; ++i) sv[i] = w[i] + beta * sv[i];
+            for (int32_t i = 0; i < n; ++i) x[i] += alpha * p[i];
+            for (int32_t i = 0; i < n; ++i) r[i] -= alpha * sv[i];
+            apply_precond(&M, n, r, u);
+            oracle_spmv_csr(n, row_ptr, col, vals, u, w);
+            double gamma_new = oracle_dot(n, r, u);
+            delta = oracle_dot(n, w, u);
+            rr = oracle_dot(n, r, r);
+            ++k;
+            if (hist) hist[k] = sqrt(rr) / nb;
+            if (!isfinite(gamma_new) || !isfinite(delta) || !isfinite(rr)) { status = OR_NON_FINITE; goto done; }
+            if (sqrt(rr) <= tol * nb) break;
+            if (!(gamma_new > 0.0)) { status = OR_NOT_SPD; goto done; }
+            beta = gamma_new / gamma;
+            double denom = delta - beta * gamma_new / alpha;
+            if (!isfinite(denom)) { status = OR_NON_FINITE; goto done; }
+            if (!(denom > 0.0)) { status = OR_NOT_SPD; goto done; }
+            alpha = gamma_new / denom;
+            gamma = gamma_new;
+        }
+        /* true residual, FP64 */
+        oracle_spmv_csr(n, row_ptr, col, vals, x, w);
+        for (int32_t i = 0; i < n; ++i) r[i] = b[i] - w[i];
+        double tr = sqrt(oracle_dot(n, r, r)) / nb;
+        *true_relres = tr;
+        if (tr <= tol) { status = OR_OK; break; }
+        if (k >= maxit || restarts >= 4) { status = OR_NOT_CONVERGED; break; }
+        ++restarts;
+    }
+done:
+    *iters = k;
+    free(r); free(u); free(w); free(p); free(sv); free(dinv);
+    return status;
+}
+
+/*
  * Learned-preconditioner solve with Jacobi fallback.  Runs PCG with
  * M^-1 = G G^T for at most `budget` passes; if that does not reach tol, or
  * breaks down (not SPD / non-finite), Jacobi-PCG finishes from the current x

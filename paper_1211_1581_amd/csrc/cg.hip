@@ -463,6 +463,150 @@ k_fin_learned(CgState *st, const double *part_xr, int n_xr, const double *part_g
     }
 }
 
+// ------------------------------- single reduction (Chronopoulos-Gear) --
+//
+// u = M^-1 r, w = A u and s = A p (kept by recurrence) let one joint
+// reduction (r.u, w.u, r.r) serve a whole pass:
+//   K1  p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s, u = M^-1 r
+//   K2  w = A u with the three partial sums folded into the row epilogue
+//   F   gamma' = r.u, delta = w.u -> beta = gamma'/gamma,
+//       alpha = gamma' / (delta - beta gamma' / alpha), stop decision
+
+// start of a phase (r is set): u = M^-1 r, p = s = 0
+template <int PRE>
+__global__ void __launch_bounds__(kBlock)
+k_sr_start(int n, const double *__restrict__ r, const double *__restrict__ dinv,
+           double *__restrict__ u, double *__restrict__ p, double *__restrict__ s, const CgState *st) {
+    if (st->halt != RUN) return;
+    const int base = blockIdx.x * kVecBlock + threadIdx.x;
+#pragma unroll
+    for (int v = 0; v < kVecPer; ++v) {
+        const int i = base + v * kBlock;
+        if (i < n) {
+            u[i] = PRE == SPCG_PRECOND_JACOBI ? dinv[i] * r[i] : r[i];
+            p[i] = 0.0;
+            s[i] = 0.0;
+        }
+    }
+}
+
+// K1 of pass `expect`
+template <int PRE>
+__global__ void __launch_bounds__(kBlock)
+k_sr_vec(int n, int expect, double *__restrict__ x, double *__restrict__ r, double *__restrict__ p,
+         double *__restrict__ s, double *__restrict__ u, const double *__restrict__ w,
+         const double *__restrict__ dinv, const CgState *st) {
+    if (st->halt != RUN || st->k != expect) return;
+    const double alpha = st->alpha, beta = st->beta;
+    const int base = blockIdx.x * kVecBlock + threadIdx.x;
+#pragma unroll
+    for (int v = 0; v < kVecPer; ++v) {
+        const int i = base + v * kBlock;
+        if (i < n) {
+            const double pi = u[i] + beta * p[i];
+            const double si = w[i] + beta * s[i];
+            x[i] += alpha * pi;
+            const double ri = r[i] - alpha * si;
+            p[i] = pi;
+            s[i] = si;
+            r[i] = ri;
+            u[i] = PRE == SPCG_PRECOND_JACOBI ? dinv[i] * ri : ri;
+        }
+    }
+}
+
+struct RU {
+    double r, u;
+};
+
+struct EpiSR {
+    double *__restrict__ w;
+    const double *__restrict__ r;
+    const double *__restrict__ u;
+    double g, d, rr;
+    __device__ __forceinline__ RU load(int i) const { return RU{r[i], u[i]}; }
+    __device__ __forceinline__ void row(int i, double s, RU v) {
+        w[i] = s;
+        g += v.r * v.u;
+        d += s * v.u;
+        rr += v.r * v.r;
+    }
+};
+
+// K2: w = A u; partials (r.u, w.u, r.r).  kexp: pass number, or -1 at a phase start.
+SPCG_ROWBLOCK_KERNEL
+k_sr_w(CsrDev A, const double *__restrict__ vals, const double *__restrict__ u,
+       const double *__restrict__ r, double *__restrict__ w, const CgState *st, double *part,
+       int kexp) {
+    __shared__ SpmvSmem<double> sm;
+    if (st->halt != RUN || (kexp >= 0 && st->k != kexp)) return;
+    int bs, be;
+    const int slot = block_range(A.n_blocks, bs, be);
+    EpiSR epi{w, r, u, 0.0, 0.0, 0.0};
+    for (int k = bs; k < be; ++k) spmv_block<double, double, double>(A, vals, u, k, sm, epi);
+    const double v[3] = {block_sum(epi.g, sm.red), block_sum(epi.d, sm.red), block_sum(epi.rr, sm.red)};
+    store_partials(part, slot, v);
+}
+
+// F at a phase start: gamma, delta -> alpha, beta = 0, history entry
+__global__ void __launch_bounds__(kFinThreads)
+k_fin_sr_start(CgState *st, const double *part, int nslots, double *hist) {
+    if (st->halt != RUN) return;
+    double t[3];
+    finalize_sum(part, nslots, t);
+    if (threadIdx.x != 0) return;
+    const double gamma = t[0], delta = t[1], rr = t[2];
+    hist[st->k] = sqrt(rr) / st->nb;
+    st->rr = rr;
+    if (!finite_d(gamma) || !finite_d(delta) || !finite_d(rr)) set_break(st, NAN);
+    else if (sqrt(rr) <= st->thresh) st->halt = H_CONV;
+    else if (!(gamma > 0.0)) set_break(st, gamma);
+    else if (!(delta > 0.0)) set_break(st, delta);
+    else {
+        st->rho = gamma;
+        st->alpha = gamma / delta;
+        st->beta = 0.0;
+        if (st->k >= st->maxit) st->halt = H_MAXIT;
+    }
+}
+
+// F of pass `expect`
+__global__ void __launch_bounds__(kFinThreads)
+k_fin_sr(CgState *st, const double *part, int nslots, double *hist, int expect) {
+    if (st->halt != RUN || st->k != expect) return;
+    double t[3];
+    finalize_sum(part, nslots, t);
+    if (threadIdx.x != 0) return;
+    const int k = expect + 1;
+    st->k = k;
+    const double gamma = t[0], delta = t[1], rr = t[2];
+    const double est = sqrt(rr);
+    hist[k] = est / st->nb;
+    st->rr = rr;
+    if (!finite_d(gamma) || !finite_d(delta) || !finite_d(rr)) {
+        set_break(st, NAN);
+        return;
+    }
+    if (est <= st->thresh) {
+        st->halt = H_CONV;
+        return;
+    }
+    if (!(gamma > 0.0)) {
+        set_break(st, gamma);
+        return;
+    }
+    const double beta = gamma / st->rho;
+    const double denom = delta - beta * gamma / st->alpha;
+    if (!finite_d(denom)) set_break(st, NAN);
+    else if (!(denom > 0.0)) set_break(st, denom);
+    else {
+        st->beta = beta;
+        st->alpha = gamma / denom;
+        st->rho = gamma;
+        if (k >= st->maxit) st->halt = H_MAXIT;
+    }
+}
+
 // ------------------------------------------------------------ mixed --
 
 // x64 += x32, x32 = 0  (replacement or final fold)
@@ -660,11 +804,11 @@ static size_t carve(const spcg_csr *A, const spcg_cg_opts *o, char *base, Work *
         W.p = (double *)take(sizeof(double) * n);
         W.q = (double *)take(sizeof(double) * n);
     }
-    if (learned) {
-        W.z = (double *)take(sizeof(double) * n);
-        W.t = (double *)take(sizeof(double) * n);
-        W.x0 = (double *)take(sizeof(double) * n);
+    if (learned || o->variant == SPCG_CG_SINGLE_REDUCTION) {
+        W.z = (double *)take(sizeof(double) * n);  // learned: z;  single reduction: u
+        W.t = (double *)take(sizeof(double) * n);  // learned: t;  single reduction: w = A u
     }
+    if (learned) W.x0 = (double *)take(sizeof(double) * n);
     if (mixed) {
         W.r32 = (float *)take(sizeof(float) * n);
         W.p32 = (float *)take(sizeof(float) * n);
@@ -690,8 +834,11 @@ struct Solver {
     CgState *h;  // pinned host copy
     double *x;
     const double *b;
-    // timing mode: event pair per pass-loop SpMV launch, with its pass number
+    // timing mode: event pair around the SpMV launch of every timing_every-th
+    // pass of the loop, with its pass number
     bool timing = false;
+    int timing_every = 1;
+    bool timed(int e) const { return timing && e % timing_every == 0; }
     int n_timed = 0;
     int *timed_k = nullptr;
 
@@ -776,8 +923,56 @@ struct Solver {
         return SPCG_OK;
     }
 
+    bool single_reduction() const { return o->variant == SPCG_CG_SINGLE_REDUCTION; }
+
+    // single reduction: u = M^-1 r, p = s = 0, w = A u, (gamma, delta) -> alpha
+    int start_sr(int pre) {
+        const int n = A->n_rows;
+        if (pre == SPCG_PRECOND_JACOBI)
+            hipLaunchKernelGGL(k_sr_start<SPCG_PRECOND_JACOBI>, dim3(gv()), dim3(kBlock), 0, s, n,
+                               (const double *)w.r, (const double *)w.dinv, w.z, w.p, w.q, w.st);
+        else
+            hipLaunchKernelGGL(k_sr_start<SPCG_PRECOND_NONE>, dim3(gv()), dim3(kBlock), 0, s, n,
+                               (const double *)w.r, (const double *)w.dinv, w.z, w.p, w.q, w.st);
+        hipLaunchKernelGGL(k_sr_w, dim3(gA()), dim3(kBlock), 0, s, dev_view(A),
+                           (const double *)A->vals, (const double *)w.z, (const double *)w.r, w.t,
+                           w.st, w.partd, -1);
+        hipLaunchKernelGGL(k_fin_sr_start, dim3(1), dim3(kFinThreads), 0, s, w.st,
+                           (const double *)w.partd, (int)gA(), w.hist);
+        SPCG_LAUNCH_CHECK("single-reduction start");
+        return SPCG_OK;
+    }
+
+    int pass_sr(int pre, int e) {
+        const int n = A->n_rows;
+        if (pre == SPCG_PRECOND_JACOBI)
+            hipLaunchKernelGGL(k_sr_vec<SPCG_PRECOND_JACOBI>, dim3(gv()), dim3(kBlock), 0, s, n, e,
+                               x, w.r, w.p, w.q, w.z, (const double *)w.t, (const double *)w.dinv,
+                               w.st);
+        else
+            hipLaunchKernelGGL(k_sr_vec<SPCG_PRECOND_NONE>, dim3(gv()), dim3(kBlock), 0, s, n, e, x,
+                               w.r, w.p, w.q, w.z, (const double *)w.t, (const double *)w.dinv,
+                               w.st);
+        if (timed(e)) {
+            hipExtLaunchKernelGGL(k_sr_w, dim3(gA()), dim3(kBlock), 0, s, A->events[2 * n_timed],
+                                  A->events[2 * n_timed + 1], 0, dev_view(A),
+                                  (const double *)A->vals, (const double *)w.z,
+                                  (const double *)w.r, w.t, w.st, w.partd, e);
+            timed_k[n_timed++] = e;
+        } else {
+            hipLaunchKernelGGL(k_sr_w, dim3(gA()), dim3(kBlock), 0, s, dev_view(A),
+                               (const double *)A->vals, (const double *)w.z, (const double *)w.r,
+                               w.t, w.st, w.partd, e);
+        }
+        hipLaunchKernelGGL(k_fin_sr, dim3(1), dim3(kFinThreads), 0, s, w.st,
+                           (const double *)w.partd, (int)gA(), w.hist, e);
+        SPCG_LAUNCH_CHECK("single-reduction pass");
+        return SPCG_OK;
+    }
+
     // z = M^-1 r, p = z, rho; the phase's first history entry
     int start(int pre) {
+        if (single_reduction()) return start_sr(pre);
         const int n = A->n_rows;
         if (pre == SPCG_PRECOND_LEARNED) {
             apply_factor(-1);
@@ -799,7 +994,7 @@ struct Solver {
     int pass64(int pre, int e) {
         const int n = A->n_rows;
         const double *pd = w.partd;
-        if (timing) {
+        if (timed(e)) {
             hipExtLaunchKernelGGL((k_cg_q<double, double>), dim3(gA()), dim3(kBlock), 0, s,
                                   A->events[2 * n_timed], A->events[2 * n_timed + 1], 0,
                                   dev_view(A), (const double *)A->vals, (const double *)w.p, w.q,
@@ -841,7 +1036,7 @@ struct Solver {
     int pass32(int e) {
         const int n = A->n_rows;
         const float *pf = w.partf;
-        if (timing) {
+        if (timed(e)) {
             hipExtLaunchKernelGGL((k_cg_q<float, float>), dim3(gA()), dim3(kBlock), 0, s,
                                   A->events[2 * n_timed], A->events[2 * n_timed + 1], 0,
                                   dev_view(A), (const float *)w.vals32, (const float *)w.p32,
@@ -894,7 +1089,9 @@ struct Solver {
             if (timing && (rc = ensure_events(n_timed + nb))) return rc;
             if (timing && (rc = grow_timed(n_timed + nb))) return rc;
             for (int j = 0; j < nb; ++j) {
-                rc = mixed ? pass32(k0 + j) : pass64(pre, k0 + j);
+                rc = mixed                ? pass32(k0 + j)
+                     : single_reduction() ? pass_sr(pre, k0 + j)
+                                          : pass64(pre, k0 + j);
                 if (rc) return rc;
             }
             if ((rc = read_state())) return rc;
@@ -927,7 +1124,7 @@ struct Solver {
 // grid-wide kernels on a tiny matrix, so it only pays up to ~32K nonzeros.
 static int small_ok(const spcg_csr *A, const spcg_cg_opts *o) {
     return o->small_path && o->precision == SPCG_PREC_F64 && o->precond != SPCG_PRECOND_LEARNED &&
-           A->n_rows <= 16384 && A->nnz <= (int64_t)1 << 15;
+           o->variant == SPCG_CG_STANDARD && A->n_rows <= 16384 && A->nnz <= (int64_t)1 << 15;
 }
 
 }  // namespace spcg
@@ -962,6 +1159,10 @@ int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o
     if (o->maxit < 0 || !(o->tol >= 0.0)) return SPCG_INVALID_ARG;
     if (o->precond < SPCG_PRECOND_NONE || o->precond > SPCG_PRECOND_LEARNED) return SPCG_INVALID_ARG;
     if (o->precision != SPCG_PREC_F64 && o->precision != SPCG_PREC_MIXED) return SPCG_INVALID_ARG;
+    if (o->variant != SPCG_CG_STANDARD && o->variant != SPCG_CG_SINGLE_REDUCTION) return SPCG_INVALID_ARG;
+    if (o->variant == SPCG_CG_SINGLE_REDUCTION &&
+        (o->precision != SPCG_PREC_F64 || o->precond == SPCG_PRECOND_LEARNED))
+        return SPCG_INVALID_ARG;
     const bool mixed = o->precision == SPCG_PREC_MIXED;
     const bool learned = o->precond == SPCG_PRECOND_LEARNED;
     if (mixed && (o->precond != SPCG_PRECOND_JACOBI || !(o->delta > 0.0 && o->delta < 1.0)))
@@ -988,7 +1189,8 @@ int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o
     S.x = d_x;
     S.b = d_b;
     S.h = (CgState *)A->h_pinned;
-    S.timing = o->timing != 0;
+    S.timing = o->timing > 0;
+    S.timing_every = o->timing > 0 ? o->timing : 1;
     static_assert(sizeof(CgState) <= 256, "pinned status buffer");
     carve(A, o, (char *)d_work, &S.w);
     Work &w = S.w;

@@ -34,7 +34,7 @@ class CgOpts(ctypes.Structure):
                 ("check_every", ctypes.c_int32), ("delta", ctypes.c_double),
                 ("G", ctypes.c_void_p), ("GT", ctypes.c_void_p),
                 ("budget", ctypes.c_int32), ("small_path", ctypes.c_int32),
-                ("timing", ctypes.c_int32)]
+                ("timing", ctypes.c_int32), ("variant", ctypes.c_int32)]
 
 
 class CgResult(ctypes.Structure):
@@ -179,8 +179,12 @@ def dot(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
     return out
 
 
+VARIANT = {"standard": 0, "single_reduction": 1}
+
+
 def cg_opts(tol=1e-10, maxit=20000, precond="jacobi", precision="f64", check_every=0,
-            delta=0.1, G=None, GT=None, budget=None, small_path=True, timing=False) -> CgOpts:
+            delta=0.1, G=None, GT=None, budget=None, small_path=True, timing=False,
+            variant="standard") -> CgOpts:
     o = CgOpts()
     lib().spcg_cg_default_opts(ctypes.byref(o))
     o.tol = tol
@@ -194,7 +198,8 @@ def cg_opts(tol=1e-10, maxit=20000, precond="jacobi", precision="f64", check_eve
     if budget is not None:
         o.budget = budget
     o.small_path = 1 if small_path else 0
-    o.timing = 1 if timing else 0
+    o.timing = int(timing)  # N > 0: time every N-th pass's SpMV (True = every pass)
+    o.variant = VARIANT[variant]
     return o
 
 

@@ -40,7 +40,7 @@ def test_status_strings_and_struct_sizes():
     from paper_1211_1581_amd import spcg
     assert spcg.status_str(spcg.OK) == "OK"
     assert spcg.status_str(spcg.NOT_SPD) == "NOT_SPD"
-    # spcg_cg_opts: double, 4 x int32, double, 2 pointers, 3 x int32 (+ pad)
+    # spcg_cg_opts: double, 4 x int32, double, 2 pointers, 4 x int32
     assert ctypes.sizeof(spcg.CgOpts) == 8 + 16 + 8 + 16 + 16
     assert ctypes.sizeof(spcg.CgResult) == 16 + 8 + 8 + 8
     o = spcg.CgOpts()

@@ -162,3 +162,65 @@ def test_status_codes():
     for small in (True, False):
         r = S.cg_solve(MD, to_dev(np.ones(3)), precond="none", small_path=small)
         assert r["status"] == S.NOT_SPD
+
+
+# ------------------------------------------- single reduction (Chronopoulos-Gear) --
+
+@pytest.mark.parametrize("case,precond", [("poisson2d", "none"), ("poisson2d", "jacobi"),
+                                           ("fv32", "jacobi"), ("banded", "none")])
+def test_single_reduction_matches_oracle(case, precond):
+    A = {"poisson2d": lambda: I.poisson2d(64), "fv32": lambda: I.fv_diffusion(32, 8)[0],
+         "banded": lambda: I.banded_spd(1024, 255)}[case]()
+    b = I.rhs_from_solution(A, I.uniform_vector(A.n_rows, 2))
+    ref = oracle.cg_single_reduction(A, b, tol=1e-10, maxit=5000, precond=precond)
+    std = oracle.pcg(A, b, tol=1e-10, maxit=5000, precond=precond)
+    g = solve(A, b, tol=1e-10, maxit=5000, precond=precond, variant="single_reduction")
+    assert g["status"] == 0 and ref["status"] == 0 and within(g["iters"], ref["iters"])
+    assert abs(g["iters"] - std["iters"]) <= 0.02 * std["iters"] + 2
+    assert oracle.true_relres(A, b, g["x"]) <= 1e-10
+    k = min(40, len(ref["hist"]), len(g["hist"]))
+    assert np.allclose(g["hist"][:k], ref["hist"][:k], rtol=1e-6)
+
+
+def test_single_reduction_full_size_poisson128():
+    A = I.poisson3d(128)
+    b = I.rhs_from_solution(A, I.uniform_vector(A.n_rows, 1))
+    g = solve(A, b, tol=1e-10, maxit=20000, precond="jacobi", variant="single_reduction")
+    assert g["status"] == 0 and within(g["iters"], 425)
+    assert oracle.true_relres(A, b, g["x"]) <= 1e-10
+
+
+def test_single_reduction_status_codes():
+    S = spcg()
+    A = I.poisson2d(16)
+    n = A.n_rows
+    M = S.CsrMatrix.from_host(A)
+    r = S.cg_solve(M, to_dev(np.zeros(n)), variant="single_reduction")
+    assert r["status"] == 0 and r["iters"] == 0
+    r = S.cg_solve(M, to_dev(np.ones(n)), maxit=3, variant="single_reduction")
+    assert r["status"] == S.NOT_CONVERGED and r["iters"] == 3
+    D = I.CSR(3, 3, np.array([0, 1, 2, 3], np.int32), np.array([0, 1, 2], np.int32),
+              np.array([1.0, -1.0, 2.0]))
+    r = S.cg_solve(S.CsrMatrix.from_host(D), to_dev(np.ones(3)), precond="none",
+                   variant="single_reduction")
+    assert r["status"] == S.NOT_SPD
+    # only FP64 with no or Jacobi preconditioning
+    with pytest.raises(S.SpcgError):
+        S.cg_solve(M, to_dev(np.ones(n)), precision="mixed", variant="single_reduction")
+    o = S.cg_opts()
+    o.variant = 7
+    with pytest.raises(S.SpcgError):
+        S.cg_solve(M, to_dev(np.ones(n)), opts=o)
+
+
+@pytest.mark.parametrize("every", [1, 8])
+def test_timing_mode_counts_sampled_launches(every):
+    # events bracket the SpMV of every `every`-th pass; the solve is unchanged
+    A, _, xs = I.fv_diffusion(24, 3)
+    b = I.rhs_from_solution(A, xs)
+    plain = solve(A, b, tol=1e-10, maxit=5000, precond="jacobi", small_path=False)
+    g = solve(A, b, tol=1e-10, maxit=5000, precond="jacobi", small_path=False, timing=every)
+    assert g["status"] == 0 and g["iters"] == plain["iters"]
+    assert np.array_equal(g["x"], plain["x"])
+    assert g["spmv_calls"] == (g["iters"] + every - 1) // every
+    assert g["spmv_ms"] > 0.0

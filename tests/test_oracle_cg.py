@@ -166,3 +166,54 @@ def test_mixed_reliable_update():
     assert m["n_updates"] >= 5
     # the kept direction keeps the inner count near the FP64 count
     assert m["iters"] <= 1.15 * j["iters"] + 5
+
+
+# ------------------------------------------- single-reduction (Chronopoulos-Gear) --
+
+@pytest.mark.parametrize("case,precond", [("poisson", "none"), ("poisson", "jacobi"),
+                                           ("fv", "jacobi"), ("fv", "none")])
+def test_single_reduction_matches_standard_cg(case, precond):
+    # same Krylov iterates in exact arithmetic: residual histories agree while
+    # rounding has not built up, and the pass counts match.  Plain CG on the
+    # high-contrast diffusion matrix (kappa ~ 1e6) is the exception that shows
+    # the rounding: both variants leave exact arithmetic after ~10 passes, so
+    # only the pass count (within 5 %) and the true residual are compared.
+    A = I.poisson2d(64) if case == "poisson" else I.fv_diffusion(12, 3, corr_len=2.0)[0]
+    b = I.rhs_from_solution(A, I.uniform_vector(A.n_rows, 0 if case == "poisson" else 1))
+    s = oracle.cg_single_reduction(A, b, tol=1e-10, maxit=5000, precond=precond)
+    c = oracle.pcg(A, b, tol=1e-10, maxit=5000, precond=precond)
+    assert s["status"] == 0 and c["status"] == 0 and s["true_relres"] <= 1e-10
+    if case == "fv" and precond == "none":
+        assert abs(s["iters"] - c["iters"]) <= 0.05 * c["iters"] + 2
+        assert np.allclose(s["hist"][:8], c["hist"][:8], rtol=1e-10, atol=0)
+        return
+    assert abs(s["iters"] - c["iters"]) <= 2
+    k = min(60, len(s["hist"]), len(c["hist"]))
+    assert np.allclose(s["hist"][:k], c["hist"][:k], rtol=1e-8, atol=0)
+
+
+def test_single_reduction_dense_solve_and_finite_termination():
+    rng = np.random.default_rng(11)
+    B = rng.standard_normal((30, 30))
+    M = B @ B.T + 30 * np.eye(30)
+    A = csr_from_dense(M)
+    b = rng.standard_normal(30)
+    s = oracle.cg_single_reduction(A, b, tol=1e-13, maxit=500, precond="jacobi")
+    assert s["status"] == 0
+    assert np.allclose(s["x"], np.linalg.solve(M, b), rtol=1e-10, atol=1e-12)
+    # 6 distinct eigenvalues -> at most 6 passes
+    D = csr_from_dense(np.diag(np.repeat([1.0, 2.0, 3.5, 5.0, 8.0, 13.0], 5)))
+    r = oracle.cg_single_reduction(D, np.ones(30), tol=1e-12, maxit=100, precond="none")
+    assert r["status"] == 0 and r["iters"] <= 6
+    # diagonal A with Jacobi: one pass
+    r = oracle.cg_single_reduction(D, np.arange(1.0, 31.0), tol=1e-12, maxit=100, precond="jacobi")
+    assert r["status"] == 0 and r["iters"] == 1
+
+
+def test_single_reduction_status_codes():
+    A = csr_from_dense(np.array([[1.0, 2.0], [2.0, 1.0]]))   # indefinite
+    r = oracle.cg_single_reduction(A, np.array([1.0, -0.5]), precond="none")
+    assert r["status"] == oracle.NOT_SPD
+    P = I.poisson2d(8)
+    r = oracle.cg_single_reduction(P, np.zeros(P.n_rows))
+    assert r["status"] == 0 and r["iters"] == 0 and not np.any(r["x"])
