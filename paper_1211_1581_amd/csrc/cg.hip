@@ -155,9 +155,9 @@ k_resid(CsrDev A, const double *__restrict__ vals, const double *__restrict__ x,
     int bs, be;
     const int slot = block_range(A.n_blocks, bs, be);
     EpiResid epi{b, r, r32, 0.0, 0.0};
-    for (int k = bs; k < be; ++k) spmv_block<double, double, double>(A, vals, x, k, sm, epi);
-    const double v[2] = {block_sum(epi.bb, sm.red), block_sum(epi.rr, sm.red)};
-    store_partials(part, slot, v);
+    for (int k = bs; k < be; ++k) spmv_block<double, double, double>(A, vals, x, k, sm, epi, k + 1 < be);
+    const double v[2] = {epi.bb, epi.rr};
+    store_block_partials(part, slot, v, sm.red);
 }
 
 __global__ void __launch_bounds__(kFinThreads)
@@ -192,7 +192,7 @@ template <int PRE>
 __global__ void __launch_bounds__(kBlock)
 k_start(int n, const double *__restrict__ r, const double *__restrict__ dinv,
         const double *__restrict__ zin, double *__restrict__ p, const CgState *st, double *part) {
-    __shared__ double red[4];
+    __shared__ double red[kWaves * 2];
     if (st->halt != RUN) return;
     double rz = 0.0, rr = 0.0;
     const int base = blockIdx.x * kVecBlock + threadIdx.x;
@@ -209,8 +209,8 @@ k_start(int n, const double *__restrict__ r, const double *__restrict__ dinv,
             rr += ri * ri;
         }
     }
-    const double v[2] = {block_sum(rz, red), block_sum(rr, red)};
-    store_partials(part, blockIdx.x, v);
+    const double v[2] = {rz, rr};
+    store_block_partials(part, blockIdx.x, v, red);
 }
 
 __global__ void __launch_bounds__(kFinThreads)
@@ -252,9 +252,9 @@ k_cg_q(CsrDev A, const TV *__restrict__ vals, const T *__restrict__ p, T *__rest
     int bs, be;
     const int slot = block_range(A.n_blocks, bs, be);
     EpiPQ<T> epi{q, p, T(0)};
-    for (int k = bs; k < be; ++k) spmv_block<TV, T, T>(A, vals, p, k, sm, epi);
-    const T v[1] = {block_sum(epi.acc, sm.red)};
-    store_partials(part, slot, v);
+    for (int k = bs; k < be; ++k) spmv_block<TV, T, T>(A, vals, p, k, sm, epi, k + 1 < be);
+    const T v[1] = {epi.acc};
+    store_block_partials(part, slot, v, sm.red);
 }
 
 // F1: sigma = p.q, alpha = rho / sigma
@@ -281,7 +281,7 @@ template <typename T, int PRE>
 __global__ void __launch_bounds__(kBlock)
 k_cg_xr(int n, int expect, T *__restrict__ x, T *__restrict__ r, const T *__restrict__ p,
         const T *__restrict__ q, const T *__restrict__ dinv, const CgState *st, T *part) {
-    __shared__ T red[4];
+    __shared__ T red[kWaves * 2];
     if (st->halt != RUN || st->k != expect) return;
     const T alpha = st_alpha<T>(st);
     T rz = T(0), rr = T(0);
@@ -298,8 +298,8 @@ k_cg_xr(int n, int expect, T *__restrict__ x, T *__restrict__ r, const T *__rest
         }
     }
     if constexpr (PRE == SPCG_PRECOND_NONE) rz = rr;
-    const T v[2] = {block_sum(rz, red), block_sum(rr, red)};
-    store_partials(part, blockIdx.x, v);
+    const T v[2] = {rz, rr};
+    store_block_partials(part, blockIdx.x, v, red);
 }
 
 // F2: pass count, history, stop decision, beta and rho
@@ -395,7 +395,7 @@ k_gt_apply(FactorDev GT, const double *__restrict__ r, double *__restrict__ t, c
             spmv_short<float, double, double>(GT.A.row_ptr, GT.A.col, GT.vals, r, GT.n, k, epi);
     } else {
         block_range(GT.A.n_blocks, bs, be);
-        for (int k = bs; k < be; ++k) spmv_block<float, double, double>(GT.A, GT.vals, r, k, sm, epi);
+        for (int k = bs; k < be; ++k) spmv_block<float, double, double>(GT.A, GT.vals, r, k, sm, epi, k + 1 < be);
     }
 }
 
@@ -426,10 +426,10 @@ k_g_apply(FactorDev G, const double *__restrict__ t, const double *__restrict__ 
             spmv_short<float, double, double>(G.A.row_ptr, G.A.col, G.vals, t, G.n, k, epi);
     } else {
         slot = block_range(G.A.n_blocks, bs, be);
-        for (int k = bs; k < be; ++k) spmv_block<float, double, double>(G.A, G.vals, t, k, sm, epi);
+        for (int k = bs; k < be; ++k) spmv_block<float, double, double>(G.A, G.vals, t, k, sm, epi, k + 1 < be);
     }
-    const double v[1] = {block_sum(epi.acc, sm.red)};
-    store_partials(part, slot, v);
+    const double v[1] = {epi.acc};
+    store_block_partials(part, slot, v, sm.red);
 }
 
 // End of a learned pass (one finalize for both reductions): ||r||^2 from the
@@ -543,9 +543,9 @@ k_sr_w(CsrDev A, const double *__restrict__ vals, const double *__restrict__ u,
     int bs, be;
     const int slot = block_range(A.n_blocks, bs, be);
     EpiSR epi{w, r, u, 0.0, 0.0, 0.0};
-    for (int k = bs; k < be; ++k) spmv_block<double, double, double>(A, vals, u, k, sm, epi);
-    const double v[3] = {block_sum(epi.g, sm.red), block_sum(epi.d, sm.red), block_sum(epi.rr, sm.red)};
-    store_partials(part, slot, v);
+    for (int k = bs; k < be; ++k) spmv_block<double, double, double>(A, vals, u, k, sm, epi, k + 1 < be);
+    const double v[3] = {epi.g, epi.d, epi.rr};
+    store_block_partials(part, slot, v, sm.red);
 }
 
 // F at a phase start: gamma, delta -> alpha, beta = 0, history entry
@@ -628,7 +628,7 @@ k_mp_fold(int n, double *__restrict__ x, float *__restrict__ x32, const CgState 
 __global__ void __launch_bounds__(kBlock)
 k_mp_rz(int n, const float *__restrict__ r32, const float *__restrict__ dinv32,
         float *__restrict__ p32, const CgState *st, float *part, int init) {
-    __shared__ float red[4];
+    __shared__ float red[kWaves];
     if (init ? st->halt != RUN : st->halt != H_REPLACE) return;
     float rz = 0.0f;
     const int base = blockIdx.x * kVecBlock + threadIdx.x;
@@ -642,8 +642,8 @@ k_mp_rz(int n, const float *__restrict__ r32, const float *__restrict__ dinv32,
             rz += ri * zi;
         }
     }
-    const float v[1] = {block_sum(rz, red)};
-    store_partials(part, blockIdx.x, v);
+    const float v[1] = {rz};
+    store_block_partials(part, blockIdx.x, v, red);
 }
 
 // Ends a replacement (or the start): converged, out of passes, or running.
@@ -774,6 +774,7 @@ static FactorDev factor_view(const spcg_csr *F) {
     return FactorDev{dev_view(F), (const float *)F->vals, F->n_rows};
 }
 
+// Partial-sum slots of the largest producing kernel (one per wavefront)
 static int64_t n_slots(const spcg_csr *A, const spcg_cg_opts *o) {
     int64_t s = std::max<int64_t>(spmv_grid(A->n_blocks), vec_blocks(A->n_rows));
     if (o->precond == SPCG_PRECOND_LEARNED) {

@@ -110,7 +110,7 @@ k_spmv(CsrDev A, const T *__restrict__ vals, const T *__restrict__ x, T *__restr
     int bs, be;
     block_range(A.n_blocks, bs, be);
     EpiStore<T> epi{y};
-    for (int b = bs; b < be; ++b) spmv_block<T, T, T>(A, vals, x, b, sm, epi);
+    for (int b = bs; b < be; ++b) spmv_block<T, T, T>(A, vals, x, b, sm, epi, b + 1 < be);
 }
 
 // y = A x for matrices whose rows have at most kShortLen entries

@@ -4,11 +4,12 @@
 //  * Rows are partitioned once per matrix into row blocks of bounded work:
 //    with the merge coordinate f(i) = row_ptr[i] + i (entries plus rows
 //    before row i), block b owns the rows with f(i) in [b*kChunk, (b+1)*kChunk).
-//    Every row but the last of a block has fewer than kChunk entries; a
-//    block's entries fit the LDS slab (kSlab) unless its last row is long,
-//    and then that row is reduced separately by the whole workgroup.
-//  * A 256-thread workgroup walks a contiguous range of row blocks (at most
-//    kMaxGrid workgroups, 8 resident per CU).  Phase 1 streams the block's
+//    The rows before a block's last one hold fewer than kChunk entries in
+//    all; the block's entries fit the LDS slab (kSlab) unless its last row is
+//    long, and then that row is reduced separately by the whole workgroup.
+//  * A 256-thread workgroup handles a contiguous range of row blocks (one
+//    block per workgroup up to kMaxGrid blocks; 7 resident per CU with the
+//    FP64 slab, 8 with FP32).  Phase 1 streams the block's
 //    contiguous values and column indices with coalesced non-temporal loads,
 //    gathers x and writes the products into LDS.  Phase 2 reduces each row
 //    from LDS with a group of L lanes (L ~ the block's mean row length) and a
@@ -47,9 +48,9 @@ struct spcg_csr {
 namespace spcg {
 
 constexpr int kBlock = 256;              // threads per workgroup of the streaming kernels
-constexpr int kChunk = 1024;             // merge-coordinate span of one row block
+constexpr int kChunk = 1536;             // merge-coordinate span of one row block
 constexpr int kSlab = 1792;              // LDS products per row block (>= kChunk; longer last rows go strided)
-constexpr int kMaxGrid = 8192;           // workgroups of a row-block kernel (each walks a range)
+constexpr int kMaxGrid = 16384;          // workgroups of a row-block kernel (each walks a range)
 
 // Row-block kernels run 8 waves per SIMD (8 workgroups of 256 per CU): the
 // register budget is capped at 64 VGPRs so latency hiding is not traded away.
@@ -124,6 +125,37 @@ __device__ __forceinline__ void store_partials(T *part, int slot, const T (&v)[N
     }
 }
 
+// Partial sums of one workgroup at its end: each wavefront reduces its
+// values with a butterfly and parks them in LDS, one barrier, then thread 0
+// adds the kWaves wavefront sums in order and writes slot `slot`.  Row-block
+// kernels skip the barrier that would otherwise follow their last block, so
+// the workgroup ends with a single barrier (a workgroup that stays resident
+// longer costs the streaming kernels several percent, and per-wavefront
+// partials would quadruple what the one-workgroup finalize has to read).
+constexpr int kWaves = kBlock / 64;
+
+template <typename T, int NV>
+__device__ __forceinline__ void store_block_partials(T *part, int slot, const T (&v)[NV],
+                                                     T *red /* LDS, kWaves * NV */) {
+    T s[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) s[j] = wave_sum(v[j]);
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) red[(threadIdx.x >> 6) * NV + j] = s[j];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            T t = red[j];
+#pragma unroll
+            for (int w = 1; w < kWaves; ++w) t += red[w * NV + j];
+            part[(size_t)slot * NV + j] = t;
+        }
+    }
+}
+
 // Fixed-order totals of two partial arrays at once: a (na >= 1 slots x NA
 // values) and b (nb >= 1 slots x NB values).  Call from all kFinThreads
 // threads of a one-workgroup kernel; every thread receives the totals.  The
@@ -133,7 +165,9 @@ template <typename T, int NA, int NB>
 __device__ __forceinline__ void finalize_sum2(const T *__restrict__ a, int na, T (&ta)[NA],
                                               const T *__restrict__ b, int nb, T *tb) {
     constexpr int NV = NA + NB;
-    constexpr int kFinPer = 8;
+    // slots per thread and round (24K single-value slots per round, without
+    // register spills)
+    constexpr int kFinPer = NV >= 3 ? 8 : 24 / NV;
     __shared__ T sh[kFinThreads / 64][NV];
     T acc[NV];
 #pragma unroll
@@ -200,7 +234,7 @@ template <typename TA>
 struct SpmvSmem {
     TA slab[kSlab];
     int32_t rp[kChunk + 1];
-    TA red[4];
+    TA red[kBlock / 64 * 3];  // block sums: up to 3 values per wavefront
     TA last;
 };
 
@@ -246,11 +280,13 @@ __device__ __forceinline__ int32_t load_uniform(const int32_t *p, int i) {
 // every row i of the block, by one thread, with consecutive threads on
 // consecutive rows; epi.load(i) (the epilogue's per-row operand, e.g. p_i for
 // p.q) is issued at the start of the block so its latency hides behind the
-// block's loads.  Must be called by all 256 threads.
+// block's loads.  Must be called by all 256 threads.  more = false (the
+// workgroup's last block) leaves out the closing barrier: the caller's
+// store_block_partials, or the end of the kernel, follows.
 template <typename TV, typename TX, typename TA, class Epi>
 __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict__ vals,
                                            const TX *__restrict__ x, int blk,
-                                           SpmvSmem<TA> &sm, Epi &epi) {
+                                           SpmvSmem<TA> &sm, Epi &epi, bool more = true) {
     const int tid = threadIdx.x;
     const int r0 = load_uniform(A.block_row, blk);
     const int r1 = load_uniform(A.block_row, blk + 1);
@@ -326,7 +362,7 @@ __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict
         else s = sm.rp[t + 1] > sm.rp[t] ? sm.slab[sm.rp[t]] : TA(0);
         epi.row(r0 + t, s, t == tid ? pre : epi.load(r0 + t));
     }
-    __syncthreads();  // the LDS slab is reused by the next row block
+    if (more) __syncthreads();  // the LDS slab is reused by the next row block
 }
 
 // ------------------------------------------------------- short rows --
