@@ -752,6 +752,151 @@ k_cg_small(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ co
     }
 }
 
+// Register-resident variant for n <= R * 1024 rows of at most ML entries: each
+// thread keeps its R rows (columns, values, x) in registers for the whole
+// solve, and p, r and D^-1 live in LDS, so a pass reads no global memory: the
+// SpMV gathers p from LDS, and the only synchronisation is the two workgroup
+// reductions and the barrier after the direction update.
+template <int PRE, int R, int ML>
+__global__ void __launch_bounds__(kSmallThreads)
+k_cg_regs(int n, int64_t nnz, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+          const double *__restrict__ vals, double *__restrict__ x, double *__restrict__ r,
+          const double *__restrict__ p_in, const double *__restrict__ dinv, CgState *st,
+          double *hist) {
+    constexpr int MP = (ML + 1) / 2;  // column indices (< 2^16) packed two per register
+    __shared__ double pl[R * kSmallThreads];
+    // this thread's own entries of r and D^-1 (only it reads them): LDS keeps
+    // the registers for the matrix
+    __shared__ double rl_[R * kSmallThreads], dl[R * kSmallThreads];
+    __shared__ double sh[2][kSmallThreads / 64];
+    if (st->halt != RUN) return;
+    const int tid = threadIdx.x;
+    uint32_t c[R][MP];
+    double v[R][ML], xr[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int i = tid + j * kSmallThreads;
+        const bool real = i < n;
+        const int lo = real ? rp[i] : 0;
+        const int len = real ? rp[i + 1] - lo : 0;
+#pragma unroll
+        for (int t = 0; t < MP; ++t) c[j][t] = 0u;
+#pragma unroll
+        for (int t = 0; t < ML; ++t) {
+            const int64_t e = min((int64_t)lo + t, nnz - 1);
+            const bool use = t < len;
+            const uint32_t cj = use ? (uint32_t)col[e] : 0u;
+            c[j][t / 2] |= (t & 1) ? (cj << 16) : cj;
+            v[j][t] = use ? vals[e] : 0.0;
+        }
+        xr[j] = real ? x[i] : 0.0;
+        rl_[i] = real ? r[i] : 0.0;
+        dl[i] = real && PRE == SPCG_PRECOND_JACOBI ? dinv[i] : 0.0;
+        pl[i] = real ? p_in[i] : 0.0;
+    }
+    __syncthreads();
+    double rho = st->rho;
+    const double thresh = st->thresh, nb = st->nb;
+    const int maxit = st->maxit;
+    int k = st->k;
+    int halt = RUN, status = SPCG_OK;
+    double rr = st->rr;
+    while (true) {
+        double q[R], pq = 0.0;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            double sj = 0.0;
+#pragma unroll
+            for (int t = 0; t < ML; ++t) {
+                const uint32_t cj = (t & 1) ? (c[j][t / 2] >> 16) : (c[j][t / 2] & 0xffffu);
+                sj += v[j][t] * pl[cj];
+            }
+            q[j] = sj;
+            pq += pl[tid + j * kSmallThreads] * sj;
+            // keep one row's LDS gathers in flight at a time (register pressure)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        pq = wave_sum(pq);
+        if ((tid & 63) == 0) sh[0][tid >> 6] = pq;
+        __syncthreads();
+        double sigma = 0.0;
+#pragma unroll
+        for (int w = 0; w < kSmallThreads / 64; ++w) sigma += sh[0][w];
+        if (!(sigma > 0.0) || !isfinite(sigma)) {
+            halt = H_BREAK;
+            status = isfinite(sigma) ? SPCG_NOT_SPD : SPCG_NON_FINITE;
+            break;
+        }
+        const double alpha = rho / sigma;
+        double rz = 0.0, rl = 0.0;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int i = tid + j * kSmallThreads;
+            xr[j] += alpha * pl[i];
+            const double ri = rl_[i] - alpha * q[j];
+            rl_[i] = ri;
+            const double zj = PRE == SPCG_PRECOND_JACOBI ? dl[i] * ri : ri;
+            rz += ri * zj;
+            rl += ri * ri;
+        }
+        rz = wave_sum(rz);
+        rl = wave_sum(rl);
+        if ((tid & 63) == 0) {
+            sh[1][tid >> 6] = rz;
+            sh[0][tid >> 6] = rl;  // every thread read sigma before the barrier above
+        }
+        __syncthreads();
+        double rzs = 0.0;
+        rr = 0.0;
+#pragma unroll
+        for (int w = 0; w < kSmallThreads / 64; ++w) {
+            rzs += sh[1][w];
+            rr += sh[0][w];
+        }
+        ++k;
+        const double est = sqrt(rr);
+        if (tid == 0) hist[k] = est / nb;
+        if (!isfinite(rzs) || !isfinite(rr)) {
+            halt = H_BREAK;
+            status = SPCG_NON_FINITE;
+            break;
+        }
+        if (rr > 0.0 && !(rzs > 0.0)) {
+            halt = H_BREAK;
+            status = SPCG_NOT_SPD;
+            break;
+        }
+        const double beta = rzs / rho;
+        rho = rzs;
+        if (est <= thresh) { halt = H_CONV; break; }
+        if (k >= maxit) { halt = H_MAXIT; break; }
+        // each thread updates only its own entries of p, which no other thread
+        // reads before the barrier
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int i = tid + j * kSmallThreads;
+            const double zj = PRE == SPCG_PRECOND_JACOBI ? dl[i] * rl_[i] : rl_[i];
+            pl[i] = zj + beta * pl[i];
+        }
+        __syncthreads();  // the new direction is complete before the next product reads it
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int i = tid + j * kSmallThreads;
+        if (i < n) {
+            x[i] = xr[j];
+            r[i] = rl_[i];
+        }
+    }
+    if (tid == 0) {
+        st->k = k;
+        st->rho = rho;
+        st->rr = rr;
+        st->halt = halt;
+        st->status = status;
+    }
+}
+
 // ----------------------------------------------------------- workspace --
 
 struct Work {
@@ -1128,6 +1273,42 @@ static int small_ok(const spcg_csr *A, const spcg_cg_opts *o) {
            o->variant == SPCG_CG_STANDARD && A->n_rows <= 16384 && A->nnz <= (int64_t)1 << 15;
 }
 
+// Shapes of the register-resident solver: rows per thread R and row length
+// bound ML with about R * (2.5 ML + 4) registers within the 128 a 1024-thread
+// workgroup allows, and 3 R * 8 KB of LDS (column indices need n < 2^16).
+static int regs_shape(const spcg_csr *A) {
+    const int64_t n = A->n_rows, ml = A->max_len;
+    if (n <= kSmallThreads && ml <= 16) return 1;
+    if (n <= 2 * kSmallThreads && ml <= 8) return 2;
+    if (n <= 4 * kSmallThreads && ml <= 5) return 4;
+    return 0;
+}
+
+static bool regs_ok(const spcg_csr *A) { return A->nnz > 0 && regs_shape(A) != 0; }
+
+static int launch_regs(Solver &S, int pre, double *d_x) {
+    const spcg_csr *A = S.A;
+    Work &w = S.w;
+    const int n = A->n_rows;
+#define SPCG_REGS(P, RR, MM)                                                                    \
+    hipLaunchKernelGGL((k_cg_regs<P, RR, MM>), dim3(1), dim3(kSmallThreads), 0, S.s, n, A->nnz, \
+                       A->row_ptr, A->col, (const double *)A->vals, d_x, w.r,                  \
+                       (const double *)w.p, (const double *)w.dinv, w.st, w.hist)
+    const int R = regs_shape(A);
+    if (pre == SPCG_PRECOND_JACOBI) {
+        if (R == 1) SPCG_REGS(SPCG_PRECOND_JACOBI, 1, 16);
+        else if (R == 2) SPCG_REGS(SPCG_PRECOND_JACOBI, 2, 8);
+        else SPCG_REGS(SPCG_PRECOND_JACOBI, 4, 5);
+    } else {
+        if (R == 1) SPCG_REGS(SPCG_PRECOND_NONE, 1, 16);
+        else if (R == 2) SPCG_REGS(SPCG_PRECOND_NONE, 2, 8);
+        else SPCG_REGS(SPCG_PRECOND_NONE, 4, 5);
+    }
+#undef SPCG_REGS
+    SPCG_LAUNCH_CHECK("k_cg_regs");
+    return SPCG_OK;
+}
+
 }  // namespace spcg
 
 using namespace spcg;
@@ -1241,7 +1422,10 @@ int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o
 
     for (;;) {
         if (h->halt == RUN) {
-            if (!mixed && !learned && small_ok(A, o)) {
+            if (!mixed && !learned && small_ok(A, o) && regs_ok(A)) {
+                if ((rc = launch_regs(S, pre, d_x))) return rc;
+                if ((rc = S.read_state())) return rc;
+            } else if (!mixed && !learned && small_ok(A, o)) {
                 if (pre == SPCG_PRECOND_JACOBI)
                     hipLaunchKernelGGL(k_cg_small<SPCG_PRECOND_JACOBI>, dim3(1),
                                        dim3(kSmallThreads), 0, s, n, A->row_ptr, A->col,

@@ -51,13 +51,24 @@ k_validate(int n, int ncols, int64_t nnz, const int32_t *__restrict__ rp,
         const int c = col[k];
         if (c < 0 || c >= ncols) err |= 8;
     }
-    // one atomic per wavefront
+    // one atomic per workgroup (atomics on one address serialise: one per
+    // wavefront of a full-size grid cost ~0.3 ms)
+    __shared__ int sh[2][kBlock / 64];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         err |= __shfl_xor(err, o, 64);
         mx = max(mx, __shfl_xor(mx, o, 64));
     }
     if ((threadIdx.x & 63) == 0) {
+        sh[0][threadIdx.x >> 6] = err;
+        sh[1][threadIdx.x >> 6] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; ++w) {
+            err |= sh[0][w];
+            mx = max(mx, sh[1][w]);
+        }
         if (err) atomicOr(&flags[0], err);
         if (mx) atomicMax(&flags[1], mx);
     }
@@ -230,7 +241,7 @@ int spcg_csr_create(spcg_csr_t *out, int32_t n_rows, int32_t n_cols, int64_t nnz
     CREATE_TRY(hipGetLastError());
     {
         const int64_t work = (int64_t)n_rows + 1 > nnz ? (int64_t)n_rows + 1 : nnz;
-        const unsigned grid = (unsigned)std::min<int64_t>((work + kBlock - 1) / kBlock, 8192);
+        const unsigned grid = (unsigned)std::min<int64_t>((work + kBlock - 1) / kBlock, 1024);
         hipLaunchKernelGGL(k_validate, dim3(grid > 0 ? grid : 1), dim3(kBlock), 0, stream, n_rows,
                            n_cols, nnz, d_row_ptr, d_col, h->flags);
         CREATE_TRY(hipGetLastError());

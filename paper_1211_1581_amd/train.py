@@ -93,8 +93,15 @@ def heldout_loss(data: Dataset, w, m=8, seed=12345):
     return tot / len(data.graphs)
 
 
+def lr_at(step, total, lr, lr_min):
+    """Cosine decay from lr to lr_min over `total` steps (lr_min = lr: constant)."""
+    if lr_min >= lr or total <= 1:
+        return lr
+    return lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * min(step, total) / total))
+
+
 def train(epochs=12, lr=1e-3, m=4, train_seeds=range(100, 356), val_seeds=range(356, 364),
-          N=48, init_seed=0, probe_seed=7, log=print):
+          N=48, init_seed=0, probe_seed=7, lr_min=None, log=print):
     t0 = time.perf_counter()
     data = Dataset(N, train_seeds)
     val = Dataset(N, val_seeds)
@@ -117,7 +124,8 @@ def train(epochs=12, lr=1e-3, m=4, train_seeds=range(100, 356), val_seeds=range(
             g = data.graphs[idx]
             step += 1
             g.loss_grad(w, probes_for(g.A.n_rows, m, gen), grad, want_loss=False)
-            spcg.adam_step(w, grad, m1, v1, step, lr=lr)
+            spcg.adam_step(w, grad, m1, v1, step,
+                           lr=lr_at(step - 1, epochs * len(order), lr, lr if lr_min is None else lr_min))
         torch.cuda.synchronize()
         vl = heldout_loss(val, w)
         history.append((ep, vl))
@@ -128,6 +136,7 @@ def train(epochs=12, lr=1e-3, m=4, train_seeds=range(100, 356), val_seeds=range(
     meta = {"N": N, "train_seeds": [min(train_seeds), max(train_seeds)],
             "val_seeds": [min(val_seeds), max(val_seeds)], "epochs": epochs, "lr": lr,
             "probes_per_step": m, "optimizer": "Adam(0.9, 0.999, 1e-8), FP32 master weights",
+            "lr_min": lr if lr_min is None else lr_min,
             "init_seed": init_seed, "probe_seed": probe_seed, "best_epoch": best[2],
             "heldout_loss": best[0], "heldout_loss_jacobi": history[0][1],
             "history": history, "train_seconds": time.perf_counter() - t0}
@@ -220,6 +229,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--epochs", type=int, default=12)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr-min", type=float, default=None,
+                    help="cosine decay of the learning rate down to this value")
     ap.add_argument("--probes", type=int, default=4)
     ap.add_argument("--n-train", type=int, default=256)
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
@@ -231,8 +242,12 @@ def main():
         res = evaluate(w, seeds=range(1000, 1000 + args.eval_seeds), log=lambda s: print(s, flush=True))
         print(json.dumps(res), flush=True)
         return
-    w, meta = train(epochs=args.epochs, lr=args.lr, m=args.probes,
+    w, meta = train(epochs=args.epochs, lr=args.lr, m=args.probes, lr_min=args.lr_min,
                     train_seeds=range(100, 100 + args.n_train), log=lambda s: print(s, flush=True))
+    # the pass budget of the fallback scales this held-out 48^3 mean
+    meta["mean_learned_passes_48"] = mean_learned_iters_48(
+        torch.tensor(w, dtype=torch.float32, device="cuda"))
+    print(f"mean learned passes at 48^3 (held-out): {meta['mean_learned_passes_48']:.1f}", flush=True)
     save_weights(args.out, w, meta)
     print(json.dumps({k: v for k, v in meta.items() if k != "history"}), flush=True)
 

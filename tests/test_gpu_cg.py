@@ -224,3 +224,20 @@ def test_timing_mode_counts_sampled_launches(every):
     assert np.array_equal(g["x"], plain["x"])
     assert g["spmv_calls"] == (g["iters"] + every - 1) // every
     assert g["spmv_ms"] > 0.0
+
+
+@pytest.mark.parametrize("case", ["band9", "poisson2d_40", "poisson2d_64", "band17_small"])
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
+def test_single_workgroup_solvers(case, precond):
+    # register-resident solver (rows of <= 16 / 8 / 5 entries for n <= 1024 / 2048 /
+    # 4096) and the general single-workgroup solver (longer rows), against the oracle
+    A = {"band9": lambda: I.banded_spd(1000, 9), "poisson2d_40": lambda: I.poisson2d(40),
+         "poisson2d_64": lambda: I.poisson2d(64),
+         "band17_small": lambda: I.banded_spd(900, 17)}[case]()
+    b = I.rhs_from_solution(A, I.uniform_vector(A.n_rows, 5))
+    ref = oracle.pcg(A, b, tol=1e-10, maxit=2000, precond=precond)
+    g = solve(A, b, tol=1e-10, maxit=2000, precond=precond, small_path=True)
+    assert g["status"] == 0 and within(g["iters"], ref["iters"])
+    assert oracle.true_relres(A, b, g["x"]) <= 1e-10
+    k = min(40, len(ref["hist"]), len(g["hist"]))
+    assert np.allclose(g["hist"][:k], ref["hist"][:k], rtol=1e-6)
