@@ -267,12 +267,34 @@ def main():
                      "launches": spmv_calls},
     }
     line["copy_gbs"] = copy_rate()
+    line["read_gbs"] = read_rate()
     if not args.no_forms:
         line["workloads"] = workloads(A, xs)
         line["forms"] = forms(args)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(A, b, args.cpu_seconds)
     print(json.dumps(line), flush=True)
+
+
+def read_rate():
+    """Streaming read of 1 GiB of FP64 (torch's sum; bytes read / time, median
+    of 10): the read ceiling for kernels that, like SpMV, mostly read."""
+    import numpy as np
+    import torch
+    a = torch.ones(2 ** 27, dtype=torch.float64, device="cuda")
+    out = torch.empty((), dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        torch.sum(a, dim=0, out=out)
+    ts = []
+    for _ in range(10):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.sum(a, dim=0, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    del a
+    return round(2 ** 30 / float(np.median(ts)) / 1e9, 1)
 
 
 def copy_rate():
