@@ -115,7 +115,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 // totals.  (A "last workgroup finishes" scheme inside the producer needs a
 // device-scope release/acquire per workgroup, which on CDNA writes back and
 // invalidates the XCD's L2 and costs far more than the extra launch.)
-constexpr int kFinThreads = 1024;
+constexpr int kFinThreads = 256;
 
 template <typename T, int NV>
 __device__ __forceinline__ void store_partials(T *part, int slot, const T (&v)[NV]) {
