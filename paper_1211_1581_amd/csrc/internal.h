@@ -50,7 +50,7 @@ namespace spcg {
 constexpr int kBlock = 256;              // threads per workgroup of the streaming kernels
 constexpr int kChunk = 1536;             // merge-coordinate span of one row block
 constexpr int kSlab = 1792;              // LDS products per row block (>= kChunk; longer last rows go strided)
-constexpr int kMaxGrid = 16384;          // workgroups of a row-block kernel (each walks a range)
+constexpr int kMaxGrid = 32768;          // workgroups of a row-block kernel (each walks a range)
 
 // Row-block kernels run 8 waves per SIMD (8 workgroups of 256 per CU): the
 // register budget is capped at 64 VGPRs so latency hiding is not traded away.
@@ -115,7 +115,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 // totals.  (A "last workgroup finishes" scheme inside the producer needs a
 // device-scope release/acquire per workgroup, which on CDNA writes back and
 // invalidates the XCD's L2 and costs far more than the extra launch.)
-constexpr int kFinThreads = 256;
+constexpr int kFinThreads = 512;
 
 template <typename T, int NV>
 __device__ __forceinline__ void store_partials(T *part, int slot, const T (&v)[NV]) {
@@ -165,9 +165,9 @@ template <typename T, int NA, int NB>
 __device__ __forceinline__ void finalize_sum2(const T *__restrict__ a, int na, T (&ta)[NA],
                                               const T *__restrict__ b, int nb, T *tb) {
     constexpr int NV = NA + NB;
-    // slots per thread and round (24K single-value slots per round, without
-    // register spills)
-    constexpr int kFinPer = NV >= 3 ? 8 : 24 / NV;
+    // slots per thread and round: two wavefronts per SIMD leave room for many
+    // loads in flight (16K single-value or 8K three-value slots per round)
+    constexpr int kFinPer = NV >= 3 ? 16 : 32 / NV;
     __shared__ T sh[kFinThreads / 64][NV];
     T acc[NV];
 #pragma unroll
