@@ -125,6 +125,36 @@ def test_full_size_poisson128():
     assert M.info()["n_blocks"] == (A.nnz + A.n_rows + 1535) // 1536  # 1536 merge items per row block
 
 
+def test_poisson256_several_blocks_per_workgroup():
+    # 87K row blocks: more than one launch's workgroups, so each workgroup walks
+    # a range of blocks (the LDS slab is reused between them)
+    A = I.poisson3d(256)
+    x = I.uniform_vector(A.n_rows, 3)
+    y, M = run(A, x)
+    assert M.info()["n_blocks"] > 32768
+    check_f64(y, oracle.spmv(A, x), A, x, "256^3")
+
+
+def test_many_empty_rows_several_blocks_per_workgroup():
+    # 48M rows, three in four empty, every 97th row with 6 entries (row-block
+    # kernel, not the short-row one), columns in a small range
+    n, nc = 48_000_000, 4096
+    rng = np.random.default_rng(8)
+    lens = np.zeros(n, np.int64)
+    lens[::4] = 1
+    lens[::97] = 6
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum(lens, out=rp[1:])
+    nnz = int(rp[-1])
+    col = rng.integers(0, nc, nnz).astype(np.int32)
+    vals = rng.integers(-4, 5, nnz).astype(np.float64)
+    A = I.CSR(n, nc, rp.astype(np.int32), col, vals)
+    x = rng.integers(-3, 4, nc).astype(np.float64)
+    y, M = run(A, x)
+    assert M.info()["n_blocks"] > 32768 and M.info()["max_row_len"] == 6
+    assert np.array_equal(y, oracle.spmv(A, x))
+
+
 @pytest.fixture(scope="module")
 def cfg3():
     return I.lognormal_irregular()
