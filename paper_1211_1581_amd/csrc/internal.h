@@ -49,11 +49,14 @@ namespace spcg {
 
 constexpr int kBlock = 256;              // threads per workgroup of the streaming kernels
 constexpr int kChunk = 1536;             // merge-coordinate span of one row block
-constexpr int kSlab = 1792;              // LDS products per row block (>= kChunk; longer last rows go strided)
+constexpr int kSlab = 1776;              // LDS products per row block (>= kChunk; longer last rows go strided)
 constexpr int kMaxGrid = 32768;          // workgroups of a row-block kernel (each walks a range)
 
-// Row-block kernels run 8 waves per SIMD (8 workgroups of 256 per CU): the
-// register budget is capped at 64 VGPRs so latency hiding is not traded away.
+// Row-block kernels run 8 workgroups of 256 per CU (8 waves per SIMD, the
+// most a SIMD holds): the FP64 slab, row pointers and block sums take 20464
+// bytes of LDS, just within a 160 KB / 8 share, and the kernels stay within
+// 64 VGPRs.  A slab of 1792 (20592 bytes) left room for only 7 and cost the
+// FP64 product 4-5 %.
 #define SPCG_ROWBLOCK_KERNEL __global__ void __launch_bounds__(256)
 
 void set_error(hipError_t e, const char *what);

@@ -221,3 +221,22 @@ def test_dot_deterministic_and_bounded():
         ref = oracle.dot(a, b)
         bound = 2 * gamma(max(n, 1), 2.0 ** -53) * np.sum(np.abs(a * b))
         assert abs(d1 - ref) <= bound + 1e-300
+
+
+@pytest.mark.parametrize("L", [1535, 1536, 1537, 1775, 1776, 1777, 1792, 1793])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_rows_at_the_lds_slab_size(L, dtype):
+    # each row of L entries opens its own row block: lengths around the
+    # merge-coordinate span (1536) and the LDS slab (1776), below and above,
+    # then short rows after them
+    lens = np.array([L, L, 3, L - 1, 0, 5] * 3, np.int64)
+    rp = np.zeros(len(lens) + 1, np.int64)
+    np.cumsum(lens, out=rp[1:])
+    rng = np.random.default_rng(L)
+    nc = 4000
+    col = np.concatenate([np.sort(rng.choice(nc, l, replace=False)) for l in lens]).astype(np.int32)
+    vals = rng.integers(-5, 6, rp[-1]).astype(np.float64)
+    A = I.CSR(len(lens), nc, rp.astype(np.int32), col, vals)
+    x = rng.integers(-3, 4, nc).astype(np.float64)
+    y, M = run(A, x, dtype)
+    assert np.array_equal(y.astype(np.float64), oracle.spmv(A, x))
