@@ -57,6 +57,9 @@ extern "C" {
 #define SPCG_CG_STANDARD 0          /* the loop of Sec. 3.4: two reductions per pass */
 #define SPCG_CG_SINGLE_REDUCTION 1  /* Chronopoulos-Gear: one joint reduction per pass */
 
+/* Largest row count, column count and nnz of a matrix handle. */
+#define SPCG_MAX_INDEX 2147418111
+
 typedef struct spcg_csr *spcg_csr_t;
 
 /* Human-readable name of a status code (static string). */
@@ -69,7 +72,9 @@ const char *spcg_last_error(void);
  * Create a matrix handle (Sec. 3.2: values, column of each value, position of
  * each row's first value; here with n_rows + 1 entries so the last row's end
  * is explicit).
- *   n_rows, n_cols  >= 0;   nnz = d_row_ptr[n_rows] < 2^31
+ *   0 <= n_rows, n_cols, nnz <= SPCG_MAX_INDEX (2^31 - 2^16 - 1), else
+ *   SPCG_INVALID_ARG: the kernels index with 32-bit integers and step up to a
+ *   few thousand entries past a position, so the top 2^16 values are kept free
  *   d_row_ptr int32[n_rows+1], d_col int32[nnz], d_vals (F64: double[nnz],
  *   F32: float[nnz]); all borrowed: they must stay alive and unchanged until
  *   spcg_csr_destroy.  Columns need not be sorted; duplicates are summed.

@@ -216,7 +216,9 @@ int spcg_csr_create(spcg_csr_t *out, int32_t n_rows, int32_t n_cols, int64_t nnz
                     int32_t dtype, hipStream_t stream) {
     if (!out) return SPCG_INVALID_ARG;
     *out = nullptr;
-    if (n_rows < 0 || n_cols < 0 || nnz < 0 || nnz >= (int64_t(1) << 31)) return SPCG_INVALID_ARG;
+    if (n_rows < 0 || n_cols < 0 || nnz < 0 || n_rows > SPCG_MAX_INDEX || n_cols > SPCG_MAX_INDEX ||
+        nnz > SPCG_MAX_INDEX)
+        return SPCG_INVALID_ARG;
     if (dtype != SPCG_F64 && dtype != SPCG_F32) return SPCG_INVALID_ARG;
     if (!d_row_ptr || (nnz > 0 && (!d_col || !d_vals))) return SPCG_INVALID_ARG;
     spcg_csr *h = new (std::nothrow) spcg_csr;

@@ -55,6 +55,12 @@ def test_invalid_args_rejected_on_host():
     # negative sizes and bad dtype are rejected before any device work
     assert L.spcg_csr_create(ctypes.byref(h), -1, 3, 0, None, None, None, 0, None) == spcg.INVALID_ARG
     assert L.spcg_csr_create(ctypes.byref(h), 3, 3, 0, None, None, None, 7, None) == spcg.INVALID_ARG
+    # sizes above SPCG_MAX_INDEX = 2^31 - 2^16 - 1 (32-bit indexing with headroom)
+    big = 2**31 - 2**16
+    fake = ctypes.c_void_p(1)  # never dereferenced: the size check comes first
+    assert L.spcg_csr_create(ctypes.byref(h), 3, 3, big, fake, fake, fake, 0, None) == spcg.INVALID_ARG
+    assert L.spcg_csr_create(ctypes.byref(h), big, 3, 0, fake, fake, fake, 0, None) == spcg.INVALID_ARG
+    assert L.spcg_csr_create(ctypes.byref(h), 3, big, 0, fake, fake, fake, 0, None) == spcg.INVALID_ARG
     assert L.spmv_csr(None, None, None, None) == spcg.INVALID_ARG
     res = spcg.CgResult()
     assert L.cg_solve(None, None, None, None, None, 0, ctypes.byref(res), None, None) == spcg.INVALID_ARG

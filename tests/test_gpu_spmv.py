@@ -240,3 +240,74 @@ def test_rows_at_the_lds_slab_size(L, dtype):
     x = rng.integers(-3, 4, nc).astype(np.float64)
     y, M = run(A, x, dtype)
     assert np.array_equal(y.astype(np.float64), oracle.spmv(A, x))
+
+
+def test_maximum_size():
+    # nnz = 2^31 - 2^16 - 8 (the handle's limit is 2^31 - 2^16 - 1): 268M rows
+    # of 8 entries and a last row of 6000 (reduced outside the LDS slab, at the
+    # top of the index range).  The inputs are made on the device from closed
+    # formulas; sampled rows are checked against the oracle, every row through
+    # two weighted sums taken by torch.  Integer values keep all of it exact.
+    S = spcg()
+    lim = 2**31 - 2**16 - 1
+    last = 6000
+    nr = (lim - last) // 8 + 1
+    nnz = 8 * (nr - 1) + last
+    nc = 1 << 20
+    dev = "cuda"
+    rp = torch.empty(nr + 1, dtype=torch.int32, device=dev)
+    rp[:nr] = (torch.arange(nr, device=dev, dtype=torch.int64) * 8).to(torch.int32)
+    rp[nr] = nnz
+    col = torch.empty(nnz, dtype=torch.int32, device=dev)
+    vals = torch.empty(nnz, dtype=torch.float64, device=dev)
+    ch = 1 << 28
+    for a in range(0, nnz, ch):
+        k = torch.arange(a, min(a + ch, nnz), device=dev, dtype=torch.int64)
+        col[a:a + k.numel()] = ((k * 2654435761) % nc).to(torch.int32)
+        vals[a:a + k.numel()] = (((k * 40503) >> 7) % 7 - 3).to(torch.float64)
+        del k
+    x = (torch.arange(nc, device=dev) % 5 - 2).to(torch.float64)
+
+    def host_rows(rows):
+        rows = np.asarray(rows, np.int64)
+        starts = 8 * rows
+        lens = np.where(rows == nr - 1, last, 8)
+        sub_rp = np.zeros(len(rows) + 1, np.int64)
+        np.cumsum(lens, out=sub_rp[1:])
+        k = np.concatenate([np.arange(s, s + l) for s, l in zip(starts, lens)])
+        c = ((k * 2654435761) % nc).astype(np.int32)
+        v = (((k * 40503) >> 7) % 7 - 3).astype(np.float64)
+        return I.CSR(len(rows), nc, sub_rp.astype(np.int32), c, v)
+
+    rng = np.random.default_rng(31)
+    rows = np.unique(np.concatenate([np.arange(10), nr - 1 - np.arange(10),
+                                     rng.integers(0, nr, 2000)]))
+    xh = (np.arange(nc) % 5 - 2).astype(np.float64)
+    ref = oracle.spmv(host_rows(rows), xh)
+
+    def weighted(w_of_row):
+        # sum over k of w(row(k)) vals[k] x[col[k]], chunked, exact in FP64
+        tot = 0.0
+        for a in range(0, nnz, ch):
+            k = torch.arange(a, min(a + ch, nnz), device=dev, dtype=torch.int64)
+            r = torch.clamp(k // 8, max=nr - 1)
+            t = w_of_row(r) * vals[a:a + k.numel()] * x[col[a:a + k.numel()].long()]
+            tot += float(t.sum())
+            del k, r, t
+        return tot
+
+    w1 = lambda r: (r % 7 + 1).to(torch.float64)
+    w2 = lambda r: ((r * 31) % 11 + 1).to(torch.float64)
+    s1, s2 = weighted(w1), weighted(w2)
+    ridx = torch.arange(nr, device=dev, dtype=torch.int64)
+    for dtype in (torch.float64, torch.float32):
+        M = S.CsrMatrix(rp, col, vals.to(dtype), n_cols=nc)
+        info = M.info()
+        assert info["max_row_len"] == last and info["n_long"] >= 1
+        y = S.spmv_csr(M, x.to(dtype))
+        torch.cuda.synchronize()
+        assert np.array_equal(y[torch.as_tensor(rows, device=dev)].double().cpu().numpy(), ref)
+        yd = y.double()
+        assert float((w1(ridx) * yd).sum()) == s1 and float((w2(ridx) * yd).sum()) == s2
+        M.close()
+        del y, yd, M
