@@ -218,6 +218,7 @@ def main():
     avg_us = spmv_ms * 1e3 / max(spmv_calls, 1)
     achieved = b_spmv / (avg_us * 1e-6) / 1e9
     traffic = measured_traffic("k_cg_q", "poisson128")
+    matrix_mb = (nnz * 12 + 4 * (n + 1)) / 1e6
 
     # standalone SpMV, cold: rotate over 3 copies (651 MB > the 256 MB MALL)
     copies = [M] + [spcg.CsrMatrix.from_host(A, device=dev) for _ in range(2)]
@@ -264,7 +265,11 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic, "kernel": "k_cg_q (SpMV q = A p with p.q partials)",
                      "bytes_per_launch": b_spmv, "avg_launch_us": round(avg_us, 2),
-                     "launches": spmv_calls},
+                     "launches": spmv_calls,
+                     "note": ("A's streams (%.1f MB) fit the cache-allocating limit (%d MiB), so A stays in "
+                              "the 256 MB MALL across passes; the cold HBM rate is spmv_cold_gbs"
+                              % (matrix_mb, spcg.keep_bytes() >> 20)) if matrix_mb * 1e6 <= spcg.keep_bytes()
+                             else "A streams from HBM with non-temporal loads"},
     }
     line["copy_gbs"] = copy_rate()
     line["read_gbs"] = read_rate()

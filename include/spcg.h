@@ -91,6 +91,20 @@ int spcg_csr_create(spcg_csr_t *out, int32_t n_rows, int32_t n_cols, int64_t nnz
 /* Release a handle's analysis arrays (synchronises the device first). */
 int spcg_csr_destroy(spcg_csr_t A);
 
+/*
+ * Load policy of the matrix streams, process-wide.  The MI355X holds a 256 MB
+ * memory-side cache in front of HBM.  A product, or a CG pass loop, whose
+ * matrices stream at most `bytes` per product or pass (col + vals + row_ptr;
+ * in the learned form A, G and G^T together, else G and G^T alone) reads them
+ * with cache-allocating loads, so repeated products find them in that cache;
+ * larger ones are read with non-temporal loads, which leave it to the rest.
+ * bytes >= 0 sets the limit (0: always non-temporal) and returns the previous
+ * one; bytes < 0 only returns the current one.  Default 192 MiB.  The policy
+ * changes speed only: results are bitwise identical either way.  Takes effect
+ * for calls made after it returns.
+ */
+int64_t spcg_keep_bytes(int64_t bytes);
+
 /* Analysis summary: row blocks, blocks ending in a long row, longest row. */
 int spcg_csr_info(spcg_csr_t A, int64_t *n_blocks, int64_t *n_long_rows, int64_t *max_row_len);
 

@@ -242,8 +242,8 @@ struct EpiPQ {
     }
 };
 
-// K1: q = A p; partial p.q
-template <typename TV, typename T>
+// K1: q = A p; partial p.q.  KEEP: load policy of A's streams (keep_bytes).
+template <typename TV, typename T, bool KEEP>
 SPCG_ROWBLOCK_KERNEL
 k_cg_q(CsrDev A, const TV *__restrict__ vals, const T *__restrict__ p, T *__restrict__ q,
        const CgState *st, T *part, int expect) {
@@ -252,7 +252,7 @@ k_cg_q(CsrDev A, const TV *__restrict__ vals, const T *__restrict__ p, T *__rest
     int bs, be;
     const int slot = block_range(A.n_blocks, bs, be);
     EpiPQ<T> epi{q, p, T(0)};
-    for (int k = bs; k < be; ++k) spmv_block<TV, T, T>(A, vals, p, k, sm, epi, k + 1 < be);
+    for (int k = bs; k < be; ++k) spmv_block<TV, T, T, KEEP>(A, vals, p, k, sm, epi, k + 1 < be);
     const T v[1] = {epi.acc};
     store_block_partials(part, slot, v, sm.red);
 }
@@ -380,8 +380,9 @@ struct FactorDev {
 };
 
 // t = G^T r.  kexp: pass number the state must be at, or -1 at a phase start.
-// SHORT: every row of G^T has at most kShortLen entries.
-template <bool SHORT>
+// SHORT: every row of G^T has at most kShortLen entries.  KEEP: load policy
+// of the factor's streams (keep_bytes).
+template <bool SHORT, bool KEEP>
 SPCG_ROWBLOCK_KERNEL
 k_gt_apply(FactorDev GT, const double *__restrict__ r, double *__restrict__ t, const CgState *st,
            int kexp) {
@@ -392,10 +393,10 @@ k_gt_apply(FactorDev GT, const double *__restrict__ r, double *__restrict__ t, c
     if constexpr (SHORT) {
         block_range((int)short_steps(GT.n), bs, be);
         for (int k = bs; k < be; ++k)
-            spmv_short<float, double, double>(GT.A.row_ptr, GT.A.col, GT.vals, r, GT.n, k, epi);
+            spmv_short<float, double, double, KEEP>(GT.A.row_ptr, GT.A.col, GT.vals, r, GT.n, k, epi);
     } else {
         block_range(GT.A.n_blocks, bs, be);
-        for (int k = bs; k < be; ++k) spmv_block<float, double, double>(GT.A, GT.vals, r, k, sm, epi, k + 1 < be);
+        for (int k = bs; k < be; ++k) spmv_block<float, double, double, KEEP>(GT.A, GT.vals, r, k, sm, epi, k + 1 < be);
     }
 }
 
@@ -411,7 +412,7 @@ struct EpiZ {
 };
 
 // z = G t; partial r.z
-template <bool SHORT>
+template <bool SHORT, bool KEEP>
 SPCG_ROWBLOCK_KERNEL
 k_g_apply(FactorDev G, const double *__restrict__ t, const double *__restrict__ r,
           double *__restrict__ z, const CgState *st, double *part, int kexp) {
@@ -423,10 +424,10 @@ k_g_apply(FactorDev G, const double *__restrict__ t, const double *__restrict__ 
     if constexpr (SHORT) {
         slot = block_range((int)short_steps(G.n), bs, be);
         for (int k = bs; k < be; ++k)
-            spmv_short<float, double, double>(G.A.row_ptr, G.A.col, G.vals, t, G.n, k, epi);
+            spmv_short<float, double, double, KEEP>(G.A.row_ptr, G.A.col, G.vals, t, G.n, k, epi);
     } else {
         slot = block_range(G.A.n_blocks, bs, be);
-        for (int k = bs; k < be; ++k) spmv_block<float, double, double>(G.A, G.vals, t, k, sm, epi, k + 1 < be);
+        for (int k = bs; k < be; ++k) spmv_block<float, double, double, KEEP>(G.A, G.vals, t, k, sm, epi, k + 1 < be);
     }
     const double v[1] = {epi.acc};
     store_block_partials(part, slot, v, sm.red);
@@ -534,6 +535,7 @@ struct EpiSR {
 };
 
 // K2: w = A u; partials (r.u, w.u, r.r).  kexp: pass number, or -1 at a phase start.
+template <bool KEEP>
 SPCG_ROWBLOCK_KERNEL
 k_sr_w(CsrDev A, const double *__restrict__ vals, const double *__restrict__ u,
        const double *__restrict__ r, double *__restrict__ w, const CgState *st, double *part,
@@ -543,7 +545,7 @@ k_sr_w(CsrDev A, const double *__restrict__ vals, const double *__restrict__ u,
     int bs, be;
     const int slot = block_range(A.n_blocks, bs, be);
     EpiSR epi{w, r, u, 0.0, 0.0, 0.0};
-    for (int k = bs; k < be; ++k) spmv_block<double, double, double>(A, vals, u, k, sm, epi, k + 1 < be);
+    for (int k = bs; k < be; ++k) spmv_block<double, double, double, KEEP>(A, vals, u, k, sm, epi, k + 1 < be);
     const double v[3] = {epi.g, epi.d, epi.rr};
     store_block_partials(part, slot, v, sm.red);
 }
@@ -985,6 +987,22 @@ struct Solver {
     bool timing = false;
     int timing_every = 1;
     bool timed(int e) const { return timing && e % timing_every == 0; }
+    // Ordinary (cache-allocating) loads for the matrices streamed every pass
+    // when they fit keep_bytes(): A (or its FP32 copy in the mixed inner loop);
+    // in the learned form A, G and G^T together, else the two factors alone
+    // (measured at 128^3: keeping the factors, 150 MB, beats keeping A).
+    bool keep = false, keep_g = false;
+    void set_keep() {
+        const bool mixed = o->precision == SPCG_PREC_MIXED;
+        const int64_t a = matrix_bytes(A->n_rows, A->nnz, mixed ? 4 : 8);
+        int64_t f = 0;
+        if (o->precond == SPCG_PRECOND_LEARNED)
+            for (const spcg_csr *F : {o->G, o->GT})
+                if (F) f += matrix_bytes(F->n_rows, F->nnz, F->dtype == SPCG_F32 ? 4 : 8);
+        const int64_t lim = keep_bytes();
+        keep = a + f <= lim;
+        keep_g = f > 0 && f <= lim;
+    }
     int n_timed = 0;
     int *timed_k = nullptr;
 
@@ -1046,18 +1064,15 @@ struct Solver {
 
     // z = G (G^T r); r.z partials of the G apply in w.partg
     void apply_factor(int kexp) {
-        if (uses_short_rows(o->GT))
-            hipLaunchKernelGGL(k_gt_apply<true>, dim3(factor_grid(o->GT)), dim3(kBlock), 0, s,
-                               factor_view(o->GT), (const double *)w.r, w.t, w.st, kexp);
-        else
-            hipLaunchKernelGGL(k_gt_apply<false>, dim3(factor_grid(o->GT)), dim3(kBlock), 0, s,
-                               factor_view(o->GT), (const double *)w.r, w.t, w.st, kexp);
-        if (uses_short_rows(o->G))
-            hipLaunchKernelGGL(k_g_apply<true>, dim3(gG()), dim3(kBlock), 0, s, factor_view(o->G),
-                               (const double *)w.t, (const double *)w.r, w.z, w.st, w.partg, kexp);
-        else
-            hipLaunchKernelGGL(k_g_apply<false>, dim3(gG()), dim3(kBlock), 0, s, factor_view(o->G),
-                               (const double *)w.t, (const double *)w.r, w.z, w.st, w.partg, kexp);
+        const bool sgt = uses_short_rows(o->GT), sg = uses_short_rows(o->G);
+        auto gt = sgt ? (keep_g ? k_gt_apply<true, true> : k_gt_apply<true, false>)
+                      : (keep_g ? k_gt_apply<false, true> : k_gt_apply<false, false>);
+        auto g = sg ? (keep_g ? k_g_apply<true, true> : k_g_apply<true, false>)
+                    : (keep_g ? k_g_apply<false, true> : k_g_apply<false, false>);
+        hipLaunchKernelGGL(gt, dim3(factor_grid(o->GT)), dim3(kBlock), 0, s, factor_view(o->GT),
+                           (const double *)w.r, w.t, w.st, kexp);
+        hipLaunchKernelGGL(g, dim3(gG()), dim3(kBlock), 0, s, factor_view(o->G),
+                           (const double *)w.t, (const double *)w.r, w.z, w.st, w.partg, kexp);
     }
 
     int resid(int mode, float *r32) {
@@ -1080,9 +1095,14 @@ struct Solver {
         else
             hipLaunchKernelGGL(k_sr_start<SPCG_PRECOND_NONE>, dim3(gv()), dim3(kBlock), 0, s, n,
                                (const double *)w.r, (const double *)w.dinv, w.z, w.p, w.q, w.st);
-        hipLaunchKernelGGL(k_sr_w, dim3(gA()), dim3(kBlock), 0, s, dev_view(A),
-                           (const double *)A->vals, (const double *)w.z, (const double *)w.r, w.t,
-                           w.st, w.partd, -1);
+        if (keep)
+            hipLaunchKernelGGL(k_sr_w<true>, dim3(gA()), dim3(kBlock), 0, s, dev_view(A),
+                               (const double *)A->vals, (const double *)w.z, (const double *)w.r,
+                               w.t, w.st, w.partd, -1);
+        else
+            hipLaunchKernelGGL(k_sr_w<false>, dim3(gA()), dim3(kBlock), 0, s, dev_view(A),
+                               (const double *)A->vals, (const double *)w.z, (const double *)w.r,
+                               w.t, w.st, w.partd, -1);
         hipLaunchKernelGGL(k_fin_sr_start, dim3(1), dim3(kFinThreads), 0, s, w.st,
                            (const double *)w.partd, (int)gA(), w.hist);
         SPCG_LAUNCH_CHECK("single-reduction start");
@@ -1099,16 +1119,19 @@ struct Solver {
             hipLaunchKernelGGL(k_sr_vec<SPCG_PRECOND_NONE>, dim3(gv()), dim3(kBlock), 0, s, n, e, x,
                                w.r, w.p, w.q, w.z, (const double *)w.t, (const double *)w.dinv,
                                w.st);
-        if (timed(e)) {
-            hipExtLaunchKernelGGL(k_sr_w, dim3(gA()), dim3(kBlock), 0, s, A->events[2 * n_timed],
-                                  A->events[2 * n_timed + 1], 0, dev_view(A),
+        {
+            auto kern = keep ? k_sr_w<true> : k_sr_w<false>;
+            if (timed(e)) {
+                hipExtLaunchKernelGGL(kern, dim3(gA()), dim3(kBlock), 0, s, A->events[2 * n_timed],
+                                      A->events[2 * n_timed + 1], 0, dev_view(A),
                                   (const double *)A->vals, (const double *)w.z,
                                   (const double *)w.r, w.t, w.st, w.partd, e);
-            timed_k[n_timed++] = e;
-        } else {
-            hipLaunchKernelGGL(k_sr_w, dim3(gA()), dim3(kBlock), 0, s, dev_view(A),
-                               (const double *)A->vals, (const double *)w.z, (const double *)w.r,
-                               w.t, w.st, w.partd, e);
+                timed_k[n_timed++] = e;
+            } else {
+                hipLaunchKernelGGL(kern, dim3(gA()), dim3(kBlock), 0, s, dev_view(A),
+                                  (const double *)A->vals, (const double *)w.z,
+                                  (const double *)w.r, w.t, w.st, w.partd, e);
+            }
         }
         hipLaunchKernelGGL(k_fin_sr, dim3(1), dim3(kFinThreads), 0, s, w.st,
                            (const double *)w.partd, (int)gA(), w.hist, e);
@@ -1140,16 +1163,19 @@ struct Solver {
     int pass64(int pre, int e) {
         const int n = A->n_rows;
         const double *pd = w.partd;
-        if (timed(e)) {
-            hipExtLaunchKernelGGL((k_cg_q<double, double>), dim3(gA()), dim3(kBlock), 0, s,
-                                  A->events[2 * n_timed], A->events[2 * n_timed + 1], 0,
-                                  dev_view(A), (const double *)A->vals, (const double *)w.p, w.q,
-                                  w.st, w.partd, e);
-            timed_k[n_timed++] = e;
-        } else {
-            hipLaunchKernelGGL((k_cg_q<double, double>), dim3(gA()), dim3(kBlock), 0, s,
-                               dev_view(A), (const double *)A->vals, (const double *)w.p, w.q,
-                               w.st, w.partd, e);
+        {
+            auto kern = keep ? k_cg_q<double, double, true> : k_cg_q<double, double, false>;
+            if (timed(e)) {
+                hipExtLaunchKernelGGL(kern, dim3(gA()), dim3(kBlock), 0, s, A->events[2 * n_timed],
+                                      A->events[2 * n_timed + 1], 0, dev_view(A),
+                                  (const double *)A->vals, (const double *)w.p, w.q, w.st,
+                                  w.partd, e);
+                timed_k[n_timed++] = e;
+            } else {
+                hipLaunchKernelGGL(kern, dim3(gA()), dim3(kBlock), 0, s, dev_view(A),
+                                  (const double *)A->vals, (const double *)w.p, w.q, w.st,
+                                  w.partd, e);
+            }
         }
         hipLaunchKernelGGL(k_fin_q<double>, dim3(1), dim3(kFinThreads), 0, s, w.st, pd, (int)gA(), e);
         if (pre == SPCG_PRECOND_JACOBI) {
@@ -1182,16 +1208,19 @@ struct Solver {
     int pass32(int e) {
         const int n = A->n_rows;
         const float *pf = w.partf;
-        if (timed(e)) {
-            hipExtLaunchKernelGGL((k_cg_q<float, float>), dim3(gA()), dim3(kBlock), 0, s,
-                                  A->events[2 * n_timed], A->events[2 * n_timed + 1], 0,
-                                  dev_view(A), (const float *)w.vals32, (const float *)w.p32,
-                                  w.q32, w.st, w.partf, e);
-            timed_k[n_timed++] = e;
-        } else {
-            hipLaunchKernelGGL((k_cg_q<float, float>), dim3(gA()), dim3(kBlock), 0, s,
-                               dev_view(A), (const float *)w.vals32, (const float *)w.p32, w.q32,
-                               w.st, w.partf, e);
+        {
+            auto kern = keep ? k_cg_q<float, float, true> : k_cg_q<float, float, false>;
+            if (timed(e)) {
+                hipExtLaunchKernelGGL(kern, dim3(gA()), dim3(kBlock), 0, s, A->events[2 * n_timed],
+                                      A->events[2 * n_timed + 1], 0, dev_view(A),
+                                  (const float *)w.vals32, (const float *)w.p32, w.q32, w.st,
+                                  w.partf, e);
+                timed_k[n_timed++] = e;
+            } else {
+                hipLaunchKernelGGL(kern, dim3(gA()), dim3(kBlock), 0, s, dev_view(A),
+                                  (const float *)w.vals32, (const float *)w.p32, w.q32, w.st,
+                                  w.partf, e);
+            }
         }
         hipLaunchKernelGGL(k_fin_q<float>, dim3(1), dim3(kFinThreads), 0, s, w.st, pf, (int)gA(), e);
         hipLaunchKernelGGL((k_cg_xr<float, SPCG_PRECOND_JACOBI>), dim3(gv()), dim3(kBlock), 0, s,
@@ -1370,6 +1399,7 @@ int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o
     S.s = s;
     S.x = d_x;
     S.b = d_b;
+    S.set_keep();
     S.h = (CgState *)A->h_pinned;
     S.timing = o->timing > 0;
     S.timing_every = o->timing > 0 ? o->timing : 1;

@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <atomic>
 #include <new>
 
 #include "internal.h"
@@ -11,6 +12,10 @@
 namespace spcg {
 
 static thread_local char g_err[512] = "";
+
+static std::atomic<int64_t> g_keep_bytes{kKeepBytes};
+
+int64_t keep_bytes() { return g_keep_bytes.load(std::memory_order_relaxed); }
 
 void set_error(hipError_t e, const char *what) {
     snprintf(g_err, sizeof g_err, "%s: %s", what, hipGetErrorString(e));
@@ -114,14 +119,14 @@ struct EpiStore {
     __device__ __forceinline__ void row(int i, T s, NoOperand) { y[i] = s; }
 };
 
-template <typename T>
+template <typename T, bool KEEP>
 SPCG_ROWBLOCK_KERNEL
 k_spmv(CsrDev A, const T *__restrict__ vals, const T *__restrict__ x, T *__restrict__ y) {
     __shared__ SpmvSmem<T> sm;
     int bs, be;
     block_range(A.n_blocks, bs, be);
     EpiStore<T> epi{y};
-    for (int b = bs; b < be; ++b) spmv_block<T, T, T>(A, vals, x, b, sm, epi, b + 1 < be);
+    for (int b = bs; b < be; ++b) spmv_block<T, T, T, KEEP>(A, vals, x, b, sm, epi, b + 1 < be);
 }
 
 // y = A x for matrices whose rows have at most kShortLen entries
@@ -144,8 +149,12 @@ int launch_spmv(const spcg_csr *A, const T *x, T *y, hipStream_t s) {
         SPCG_LAUNCH_CHECK("k_spmv_short");
         return SPCG_OK;
     }
-    hipLaunchKernelGGL(k_spmv<T>, dim3(spmv_grid(A->n_blocks)), dim3(kBlock), 0, s, dev_view(A),
-                       (const T *)A->vals, x, y);
+    if (matrix_bytes(A->n_rows, A->nnz, sizeof(T)) <= keep_bytes())
+        hipLaunchKernelGGL((k_spmv<T, true>), dim3(spmv_grid(A->n_blocks)), dim3(kBlock), 0, s,
+                           dev_view(A), (const T *)A->vals, x, y);
+    else
+        hipLaunchKernelGGL((k_spmv<T, false>), dim3(spmv_grid(A->n_blocks)), dim3(kBlock), 0, s,
+                           dev_view(A), (const T *)A->vals, x, y);
     SPCG_LAUNCH_CHECK("k_spmv");
     return SPCG_OK;
 }
@@ -199,6 +208,10 @@ const char *spcg_status_str(int status) {
 }
 
 const char *spcg_last_error(void) { return g_err; }
+
+int64_t spcg_keep_bytes(int64_t bytes) {
+    return bytes >= 0 ? g_keep_bytes.exchange(bytes) : g_keep_bytes.load();
+}
 
 static void release(spcg_csr *h) {
     if (!h) return;

@@ -52,6 +52,23 @@ constexpr int kChunk = 1536;             // merge-coordinate span of one row blo
 constexpr int kSlab = 1776;              // LDS products per row block (>= kChunk; longer last rows go strided)
 constexpr int kMaxGrid = 32768;          // workgroups of a row-block kernel (each walks a range)
 
+// Load policy of the matrix streams (col, vals).  The MI355X keeps a 256 MB
+// memory-side cache (MALL) in front of HBM; ordinary loads allocate in it,
+// non-temporal loads do not.  A matrix whose streamed bytes per product are at
+// most keep_bytes() (default kKeepBytes, set by spcg_keep_bytes) is read with
+// ordinary loads, so repeated products (a CG pass loop) find it there: 128^3
+// 7-point Poisson in FP64 (183.5 MB) runs its CG product in ~41 instead of
+// ~50 us.  Larger matrices stream non-temporally: with ordinary loads the
+// 160^3 systems (358 MB FP64, 244 MB FP32) thrash the cache and run 3-5 %
+// slower.  Both policies give bitwise-identical results.
+constexpr int64_t kKeepBytes = int64_t(192) << 20;
+int64_t keep_bytes();
+
+// Bytes one product streams from the matrix: col, vals and row_ptr.
+inline int64_t matrix_bytes(int64_t n_rows, int64_t nnz, int val_bytes) {
+    return nnz * (4 + val_bytes) + 4 * (n_rows + 1);
+}
+
 // Row-block kernels run 8 workgroups of 256 per CU (8 waves per SIMD, the
 // most a SIMD holds): the FP64 slab, row pointers and block sums take 20464
 // bytes of LDS, just within a 160 KB / 8 share, and the kernels stay within
@@ -242,8 +259,9 @@ struct SpmvSmem {
 };
 
 // Products of NU rounds of kBlock entries starting at k0 (cnt >= 1 entries
-// are real; the clamped tail re-reads the last one and is not stored).
-template <int NU, typename TV, typename TX, typename TA>
+// are real; the clamped tail re-reads the last one and is not stored).  KEEP:
+// ordinary loads of col/vals (see keep_bytes), else non-temporal ones.
+template <int NU, bool KEEP, typename TV, typename TX, typename TA>
 __device__ __forceinline__ void block_products(const CsrDev &A, const TV *__restrict__ vals,
                                                const TX *__restrict__ x, int k0, int cnt,
                                                TA *__restrict__ slab) {
@@ -254,8 +272,13 @@ __device__ __forceinline__ void block_products(const CsrDev &A, const TV *__rest
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
         const int t = min(tid + u * kBlock, cnt - 1);
-        c[u] = __builtin_nontemporal_load(A.col + k0 + t);
-        v[u] = __builtin_nontemporal_load(vals + k0 + t);
+        if constexpr (KEEP) {
+            c[u] = A.col[k0 + t];
+            v[u] = vals[k0 + t];
+        } else {
+            c[u] = __builtin_nontemporal_load(A.col + k0 + t);
+            v[u] = __builtin_nontemporal_load(vals + k0 + t);
+        }
     }
 #pragma unroll
     for (int u = 0; u < NU; ++u) xv[u] = x[c[u]];
@@ -285,8 +308,9 @@ __device__ __forceinline__ int32_t load_uniform(const int32_t *p, int i) {
 // p.q) is issued at the start of the block so its latency hides behind the
 // block's loads.  Must be called by all 256 threads.  more = false (the
 // workgroup's last block) leaves out the closing barrier: the caller's
-// store_block_partials, or the end of the kernel, follows.
-template <typename TV, typename TX, typename TA, class Epi>
+// store_block_partials, or the end of the kernel, follows.  KEEP selects the
+// load policy of the matrix streams (keep_bytes).
+template <typename TV, typename TX, typename TA, bool KEEP = false, class Epi>
 __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict__ vals,
                                            const TX *__restrict__ x, int blk,
                                            SpmvSmem<TA> &sm, Epi &epi, bool more = true) {
@@ -309,13 +333,13 @@ __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict
     const int rv = A.row_ptr[r0 + min(tid, nr)];
     const auto pre = epi.load(r0 + min(tid, nr - 1));  // the epilogue's operand of row r0 + tid
     switch ((cnt + kBlock - 1) / kBlock) {
-        case 1: block_products<1>(A, vals, x, k0, cnt, sm.slab); break;
-        case 2: block_products<2>(A, vals, x, k0, cnt, sm.slab); break;
-        case 3: block_products<3>(A, vals, x, k0, cnt, sm.slab); break;
-        case 4: block_products<4>(A, vals, x, k0, cnt, sm.slab); break;
-        case 5: block_products<5>(A, vals, x, k0, cnt, sm.slab); break;
-        case 6: block_products<6>(A, vals, x, k0, cnt, sm.slab); break;
-        case 7: block_products<7>(A, vals, x, k0, cnt, sm.slab); break;
+        case 1: block_products<1, KEEP>(A, vals, x, k0, cnt, sm.slab); break;
+        case 2: block_products<2, KEEP>(A, vals, x, k0, cnt, sm.slab); break;
+        case 3: block_products<3, KEEP>(A, vals, x, k0, cnt, sm.slab); break;
+        case 4: block_products<4, KEEP>(A, vals, x, k0, cnt, sm.slab); break;
+        case 5: block_products<5, KEEP>(A, vals, x, k0, cnt, sm.slab); break;
+        case 6: block_products<6, KEEP>(A, vals, x, k0, cnt, sm.slab); break;
+        case 7: block_products<7, KEEP>(A, vals, x, k0, cnt, sm.slab); break;
         default: break;  // only empty rows
     }
     static_assert(kSlab <= 7 * kBlock, "block_products covers at most 7 rounds");
@@ -388,7 +412,8 @@ inline unsigned short_grid(int64_t n_rows) { return spmv_grid(short_steps(n_rows
 // Rows [b * kShortRows, (b + 1) * kShortRows) of an n-row matrix with nnz >= 1
 // and every row at most kShortLen long.  epi.row(i, s, epi.load(i)) is called
 // once per row, by the group's first lane (the loads are issued up front).
-template <typename TV, typename TX, typename TA, class Epi>
+// KEEP selects the load policy of col/vals (keep_bytes).
+template <typename TV, typename TX, typename TA, bool KEEP = false, class Epi>
 __device__ __forceinline__ void spmv_short(const int32_t *__restrict__ rp,
                                            const int32_t *__restrict__ col,
                                            const TV *__restrict__ vals, const TX *__restrict__ x,
@@ -412,8 +437,13 @@ __device__ __forceinline__ void spmv_short(const int32_t *__restrict__ rp,
     for (int u = 0; u < kShortRounds; ++u) {
         const int k = a[u] + lane;
         const int kc = k < e[u] ? k : max(e[u] - 1, 0);
-        c[u] = __builtin_nontemporal_load(col + kc);
-        v[u] = __builtin_nontemporal_load(vals + kc);
+        if constexpr (KEEP) {
+            c[u] = col[kc];
+            v[u] = vals[kc];
+        } else {
+            c[u] = __builtin_nontemporal_load(col + kc);
+            v[u] = __builtin_nontemporal_load(vals + kc);
+        }
     }
 #pragma unroll
     for (int u = 0; u < kShortRounds; ++u) {

@@ -61,6 +61,8 @@ def lib():
         L.spcg_last_error.argtypes = []
         L.spcg_last_error.restype = ctypes.c_char_p
         L.spcg_csr_create.argtypes = [ctypes.POINTER(P), i32, i32, i64, P, P, P, i32, P]
+        L.spcg_keep_bytes.argtypes = [i64]
+        L.spcg_keep_bytes.restype = i64
         L.spcg_csr_destroy.argtypes = [P]
         L.spcg_csr_info.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                     ctypes.POINTER(i64)]
@@ -80,6 +82,12 @@ def lib():
 
 def status_str(st: int) -> str:
     return lib().spcg_status_str(st).decode()
+
+
+def keep_bytes(value=None) -> int:
+    """Matrix-stream load policy (spcg_keep_bytes): with value, set the limit
+    in bytes and return the previous one; without, return the current one."""
+    return int(lib().spcg_keep_bytes(-1 if value is None else int(value)))
 
 
 def last_error() -> str:

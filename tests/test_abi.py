@@ -80,3 +80,12 @@ def test_weight_layout_matches_oracle():
     assert spcg.MPNN_PARAMS == mpnn.n_params()
     src = open(os.path.join(ROOT, "include", "spcg.h")).read()
     assert "#define SPCG_MPNN_PARAMS 29442" in src
+
+
+def test_keep_bytes_setting_round_trips():
+    # process-wide load policy of the matrix streams: no device work involved
+    from paper_1211_1581_amd import spcg
+    d = spcg.keep_bytes()
+    assert d == 192 << 20
+    assert spcg.keep_bytes(0) == d and spcg.keep_bytes() == 0
+    assert spcg.keep_bytes(d) == 0 and spcg.keep_bytes() == d
