@@ -8,10 +8,10 @@
 //    all; the block's entries fit the LDS slab (kSlab) unless its last row is
 //    long, and then that row is reduced separately by the whole workgroup.
 //  * A 256-thread workgroup handles a contiguous range of row blocks (one
-//    block per workgroup up to kMaxGrid blocks; 7 resident per CU with the
-//    FP64 slab, 8 with FP32).  Phase 1 streams the block's
-//    contiguous values and column indices with coalesced non-temporal loads,
-//    gathers x and writes the products into LDS.  Phase 2 reduces each row
+//    block per workgroup up to kMaxGrid blocks; 8 resident per CU).  Phase 1
+//    streams the block's contiguous values and column indices with coalesced
+//    loads (cache-allocating or non-temporal, see keep_bytes), gathers x and
+//    writes the products into LDS.  Phase 2 reduces each row
 //    from LDS with a group of L lanes (L ~ the block's mean row length) and a
 //    wavefront butterfly.  The summation order depends only on the matrix,
 //    so results are bitwise reproducible.
