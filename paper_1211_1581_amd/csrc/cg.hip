@@ -44,7 +44,7 @@ enum Halt : int {
 struct CgState {
     double rho, alpha, beta, rr, nb, thresh, rlast, delta, true_rr, r2_64;
     float rho32, alpha32, beta32, rr32;
-    int k, maxit, halt, status, budget, n_updates, bad_diag, pad;
+    int k, maxit, halt, status, budget, n_updates, bad_diag, c16_bad;
 };
 
 constexpr int kVecPer = 4;
@@ -242,8 +242,9 @@ struct EpiPQ {
     }
 };
 
-// K1: q = A p; partial p.q.  KEEP: load policy of A's streams (keep_bytes).
-template <typename TV, typename T, bool KEEP>
+// K1: q = A p; partial p.q.  KEEP: load policy of A's streams (keep_bytes);
+// C16: compact columns (A.off16).
+template <typename TV, typename T, bool KEEP, bool C16 = false>
 SPCG_ROWBLOCK_KERNEL
 k_cg_q(CsrDev A, const TV *__restrict__ vals, const T *__restrict__ p, T *__restrict__ q,
        const CgState *st, T *part, int expect) {
@@ -252,7 +253,7 @@ k_cg_q(CsrDev A, const TV *__restrict__ vals, const T *__restrict__ p, T *__rest
     int bs, be;
     const int slot = block_range(A.n_blocks, bs, be);
     EpiPQ<T> epi{q, p, T(0)};
-    for (int k = bs; k < be; ++k) spmv_block<TV, T, T, KEEP>(A, vals, p, k, sm, epi, k + 1 < be);
+    for (int k = bs; k < be; ++k) spmv_block<TV, T, T, KEEP, C16>(A, vals, p, k, sm, epi, k + 1 < be);
     const T v[1] = {epi.acc};
     store_block_partials(part, slot, v, sm.red);
 }
@@ -611,6 +612,23 @@ k_fin_sr(CgState *st, const double *part, int nslots, double *hist, int expect) 
 
 // ------------------------------------------------------------ mixed --
 
+// Compact columns of the FP32 inner matrix: off16[k] = col[k] - block_row[b]
+// for the entries k of row block b (2 instead of 4 bytes per entry); c16_bad
+// is set when an offset does not fit int16, and the inner loop then reads col.
+__global__ void __launch_bounds__(kBlock)
+k_make_off16(CsrDev A, int16_t *__restrict__ off16, CgState *st) {
+    int bad = 0;
+    for (int b = blockIdx.x; b < A.n_blocks; b += gridDim.x) {
+        const int r0 = A.block_row[b], k1 = A.block_k[b + 1];
+        for (int k = A.block_k[b] + threadIdx.x; k < k1; k += kBlock) {
+            const int d = A.col[k] - r0;
+            bad |= d < -32768 || d > 32767;
+            off16[k] = (int16_t)d;
+        }
+    }
+    if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(&st->c16_bad, 1);
+}
+
 // x64 += x32, x32 = 0  (replacement or final fold)
 __global__ void __launch_bounds__(kBlock)
 k_mp_fold(int n, double *__restrict__ x, float *__restrict__ x32, const CgState *st, int always) {
@@ -906,6 +924,7 @@ struct Work {
     double *hist;
     double *r, *p, *q, *dinv, *z, *t, *x0;
     float *r32, *p32, *q32, *x32, *dinv32, *vals32;
+    int16_t *off16;  // mixed: compact columns of the FP32 inner matrix
     double *partd;  // [nslots * 2]
     double *partg;  // [nslots]  (learned: r.z partials of the G apply)
     float *partf;   // [nslots * 2]
@@ -964,6 +983,7 @@ static size_t carve(const spcg_csr *A, const spcg_cg_opts *o, char *base, Work *
         W.x32 = (float *)take(sizeof(float) * n);
         W.dinv32 = (float *)take(sizeof(float) * n);
         W.vals32 = (float *)take(sizeof(float) * (size_t)A->nnz);
+        W.off16 = (int16_t *)take(sizeof(int16_t) * (size_t)A->nnz);
     }
     W.partd = (double *)take(sizeof(double) * 2 * W.nslots);
     if (learned) W.partg = (double *)take(sizeof(double) * W.nslots);
@@ -988,13 +1008,15 @@ struct Solver {
     int timing_every = 1;
     bool timed(int e) const { return timing && e % timing_every == 0; }
     // Ordinary (cache-allocating) loads for the matrices streamed every pass
-    // when they fit keep_bytes(): A (or its FP32 copy in the mixed inner loop);
-    // in the learned form A, G and G^T together, else the two factors alone
-    // (measured at 128^3: keeping the factors, 150 MB, beats keeping A).
-    bool keep = false, keep_g = false;
+    // when they fit keep_bytes(): A (or its FP32 copy in the mixed inner loop,
+    // with 2-byte columns when c16); in the learned form A, G and G^T
+    // together, else the two factors alone (measured at 128^3: keeping the
+    // factors, 150 MB, beats keeping A).
+    bool keep = false, keep_g = false, c16 = false;
     void set_keep() {
         const bool mixed = o->precision == SPCG_PREC_MIXED;
-        const int64_t a = matrix_bytes(A->n_rows, A->nnz, mixed ? 4 : 8);
+        const int64_t a = mixed ? A->nnz * (c16 ? 6 : 8) + 4 * (int64_t)(A->n_rows + 1)
+                                : matrix_bytes(A->n_rows, A->nnz, 8);
         int64_t f = 0;
         if (o->precond == SPCG_PRECOND_LEARNED)
             for (const spcg_csr *F : {o->G, o->GT})
@@ -1209,17 +1231,18 @@ struct Solver {
         const int n = A->n_rows;
         const float *pf = w.partf;
         {
-            auto kern = keep ? k_cg_q<float, float, true> : k_cg_q<float, float, false>;
+            auto kern = keep ? (c16 ? k_cg_q<float, float, true, true> : k_cg_q<float, float, true, false>)
+                             : (c16 ? k_cg_q<float, float, false, true> : k_cg_q<float, float, false, false>);
+            CsrDev d = dev_view(A);
+            if (c16) d.off16 = w.off16;
             if (timed(e)) {
                 hipExtLaunchKernelGGL(kern, dim3(gA()), dim3(kBlock), 0, s, A->events[2 * n_timed],
-                                      A->events[2 * n_timed + 1], 0, dev_view(A),
-                                  (const float *)w.vals32, (const float *)w.p32, w.q32, w.st,
-                                  w.partf, e);
+                                      A->events[2 * n_timed + 1], 0, d, (const float *)w.vals32,
+                                      (const float *)w.p32, w.q32, w.st, w.partf, e);
                 timed_k[n_timed++] = e;
             } else {
-                hipLaunchKernelGGL(kern, dim3(gA()), dim3(kBlock), 0, s, dev_view(A),
-                                  (const float *)w.vals32, (const float *)w.p32, w.q32, w.st,
-                                  w.partf, e);
+                hipLaunchKernelGGL(kern, dim3(gA()), dim3(kBlock), 0, s, d, (const float *)w.vals32,
+                                   (const float *)w.p32, w.q32, w.st, w.partf, e);
             }
         }
         hipLaunchKernelGGL(k_fin_q<float>, dim3(1), dim3(kFinThreads), 0, s, w.st, pf, (int)gA(), e);
@@ -1421,6 +1444,9 @@ int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o
                            A->nnz, (const double *)A->vals, w.vals32);
         hipLaunchKernelGGL(k_fill<float>, dim3(grid_of(n, kBlock * 8)), dim3(kBlock), 0, s,
                            (int64_t)n, w.x32, 0.0f);
+        if (A->n_blocks > 0)
+            hipLaunchKernelGGL(k_make_off16, dim3((unsigned)std::min<int64_t>(A->n_blocks, 4096)),
+                               dim3(kBlock), 0, s, dev_view(A), w.off16, w.st);
         SPCG_LAUNCH_CHECK("mixed set-up");
     }
     if (learned) {
@@ -1431,6 +1457,10 @@ int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o
     if ((rc = S.resid(R_INIT, mixed ? w.r32 : nullptr))) return rc;
     if ((rc = S.read_state())) return rc;
     CgState *h = S.h;
+    if (mixed && A->n_blocks > 0 && !h->c16_bad) {
+        S.c16 = true;
+        S.set_keep();
+    }
     if (h->bad_diag) return (h->bad_diag & 2) ? SPCG_NON_FINITE : SPCG_NOT_SPD;
     if (h->halt == H_ZERO) {
         hipLaunchKernelGGL(k_fill<double>, dim3(grid_of(n, kBlock * 8)), dim3(kBlock), 0, s,

@@ -248,6 +248,10 @@ struct CsrDev {
     const int32_t *__restrict__ block_row;  // first row of each row block  [n_blocks + 1]
     const int32_t *__restrict__ block_k;    // row_ptr[block_row[b]]        [n_blocks + 1]
     int n_blocks;
+    // optional compact columns: col[k] - block_row[b] as int16 for every
+    // entry k of row block b (the kernels instantiated with C16 read these
+    // instead of col)
+    const int16_t *__restrict__ off16;
 };
 
 template <typename TA>
@@ -260,10 +264,11 @@ struct SpmvSmem {
 
 // Products of NU rounds of kBlock entries starting at k0 (cnt >= 1 entries
 // are real; the clamped tail re-reads the last one and is not stored).  KEEP:
-// ordinary loads of col/vals (see keep_bytes), else non-temporal ones.
-template <int NU, bool KEEP, typename TV, typename TX, typename TA>
+// ordinary loads of col/vals (see keep_bytes), else non-temporal ones.  C16:
+// columns from A.off16 relative to the block's first row r0.
+template <int NU, bool KEEP, bool C16, typename TV, typename TX, typename TA>
 __device__ __forceinline__ void block_products(const CsrDev &A, const TV *__restrict__ vals,
-                                               const TX *__restrict__ x, int k0, int cnt,
+                                               const TX *__restrict__ x, int k0, int cnt, int r0,
                                                TA *__restrict__ slab) {
     const int tid = threadIdx.x;
     int c[NU];
@@ -272,13 +277,12 @@ __device__ __forceinline__ void block_products(const CsrDev &A, const TV *__rest
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
         const int t = min(tid + u * kBlock, cnt - 1);
-        if constexpr (KEEP) {
-            c[u] = A.col[k0 + t];
-            v[u] = vals[k0 + t];
+        if constexpr (C16) {
+            c[u] = r0 + (KEEP ? A.off16[k0 + t] : __builtin_nontemporal_load(A.off16 + k0 + t));
         } else {
-            c[u] = __builtin_nontemporal_load(A.col + k0 + t);
-            v[u] = __builtin_nontemporal_load(vals + k0 + t);
+            c[u] = KEEP ? A.col[k0 + t] : __builtin_nontemporal_load(A.col + k0 + t);
         }
+        v[u] = KEEP ? vals[k0 + t] : __builtin_nontemporal_load(vals + k0 + t);
     }
 #pragma unroll
     for (int u = 0; u < NU; ++u) xv[u] = x[c[u]];
@@ -309,8 +313,9 @@ __device__ __forceinline__ int32_t load_uniform(const int32_t *p, int i) {
 // block's loads.  Must be called by all 256 threads.  more = false (the
 // workgroup's last block) leaves out the closing barrier: the caller's
 // store_block_partials, or the end of the kernel, follows.  KEEP selects the
-// load policy of the matrix streams (keep_bytes).
-template <typename TV, typename TX, typename TA, bool KEEP = false, class Epi>
+// load policy of the matrix streams (keep_bytes); C16 reads the compact
+// columns A.off16.
+template <typename TV, typename TX, typename TA, bool KEEP = false, bool C16 = false, class Epi>
 __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict__ vals,
                                            const TX *__restrict__ x, int blk,
                                            SpmvSmem<TA> &sm, Epi &epi, bool more = true) {
@@ -333,13 +338,13 @@ __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict
     const int rv = A.row_ptr[r0 + min(tid, nr)];
     const auto pre = epi.load(r0 + min(tid, nr - 1));  // the epilogue's operand of row r0 + tid
     switch ((cnt + kBlock - 1) / kBlock) {
-        case 1: block_products<1, KEEP>(A, vals, x, k0, cnt, sm.slab); break;
-        case 2: block_products<2, KEEP>(A, vals, x, k0, cnt, sm.slab); break;
-        case 3: block_products<3, KEEP>(A, vals, x, k0, cnt, sm.slab); break;
-        case 4: block_products<4, KEEP>(A, vals, x, k0, cnt, sm.slab); break;
-        case 5: block_products<5, KEEP>(A, vals, x, k0, cnt, sm.slab); break;
-        case 6: block_products<6, KEEP>(A, vals, x, k0, cnt, sm.slab); break;
-        case 7: block_products<7, KEEP>(A, vals, x, k0, cnt, sm.slab); break;
+        case 1: block_products<1, KEEP, C16>(A, vals, x, k0, cnt, r0, sm.slab); break;
+        case 2: block_products<2, KEEP, C16>(A, vals, x, k0, cnt, r0, sm.slab); break;
+        case 3: block_products<3, KEEP, C16>(A, vals, x, k0, cnt, r0, sm.slab); break;
+        case 4: block_products<4, KEEP, C16>(A, vals, x, k0, cnt, r0, sm.slab); break;
+        case 5: block_products<5, KEEP, C16>(A, vals, x, k0, cnt, r0, sm.slab); break;
+        case 6: block_products<6, KEEP, C16>(A, vals, x, k0, cnt, r0, sm.slab); break;
+        case 7: block_products<7, KEEP, C16>(A, vals, x, k0, cnt, r0, sm.slab); break;
         default: break;  // only empty rows
     }
     static_assert(kSlab <= 7 * kBlock, "block_products covers at most 7 rounds");
@@ -367,16 +372,17 @@ __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict
     }
     if (long_last) {
         // the long last row: whole workgroup, strided over global memory
+        auto col_at = [&](int k) { return C16 ? r0 + A.off16[k] : A.col[k]; };
         const int klast = k0 + sm.rp[nr - 1];
         TA s0 = TA(0), s1 = TA(0), s2 = TA(0), s3 = TA(0);
         int k = klast + tid;
         for (; k + 3 * kBlock < kend; k += 4 * kBlock) {
-            s0 += TA(vals[k]) * TA(x[A.col[k]]);
-            s1 += TA(vals[k + kBlock]) * TA(x[A.col[k + kBlock]]);
-            s2 += TA(vals[k + 2 * kBlock]) * TA(x[A.col[k + 2 * kBlock]]);
-            s3 += TA(vals[k + 3 * kBlock]) * TA(x[A.col[k + 3 * kBlock]]);
+            s0 += TA(vals[k]) * TA(x[col_at(k)]);
+            s1 += TA(vals[k + kBlock]) * TA(x[col_at(k + kBlock)]);
+            s2 += TA(vals[k + 2 * kBlock]) * TA(x[col_at(k + 2 * kBlock)]);
+            s3 += TA(vals[k + 3 * kBlock]) * TA(x[col_at(k + 3 * kBlock)]);
         }
-        for (; k < kend; k += kBlock) s0 += TA(vals[k]) * TA(x[A.col[k]]);
+        for (; k < kend; k += kBlock) s0 += TA(vals[k]) * TA(x[col_at(k)]);
         TA s = block_sum((s0 + s1) + (s2 + s3), sm.red);
         if (tid == 0) sm.last = s;
     }
@@ -478,7 +484,7 @@ inline bool uses_short_rows(const spcg_csr *A) {
 }
 
 inline CsrDev dev_view(const spcg_csr *A) {
-    return CsrDev{A->row_ptr, A->col, A->block_row, A->block_k, (int)A->n_blocks};
+    return CsrDev{A->row_ptr, A->col, A->block_row, A->block_k, (int)A->n_blocks, nullptr};
 }
 
 }  // namespace spcg

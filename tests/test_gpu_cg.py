@@ -302,3 +302,46 @@ def test_nonzero_initial_guess(form):
         assert g["iters"] <= 1.15 * j["iters"] + 5 and abs(g["n_updates"] - ref["n_updates"]) <= 2
     else:
         assert within(g["iters"], ref["iters"], 0.05, 3)
+
+
+def _sym_csr(n, diag, pairs):
+    """Symmetric CSR with `diag` on the diagonal and value v at (i, j) and
+    (j, i) for each (i, j, v) array triple in `pairs`."""
+    import scipy.sparse as sp
+    r = [np.arange(n)]
+    c = [np.arange(n)]
+    v = [np.full(n, diag)]
+    for i, j, w in pairs:
+        r += [i, j]
+        c += [j, i]
+        v += [w, w]
+    M = sp.coo_matrix((np.concatenate(v), (np.concatenate(r), np.concatenate(c))), shape=(n, n)).tocsr()
+    M.sort_indices()
+    return I.CSR(n, n, M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data.astype(np.float64))
+
+
+@pytest.mark.parametrize("case", ["far_columns", "long_row"])
+def test_mixed_precision_column_layouts(case):
+    # The FP32 inner loop reads 16-bit column offsets from each row block's
+    # first row when they fit.  far_columns: couplings 40000 apart do not fit,
+    # so it reads the int32 columns; long_row: a 3001-entry row (reduced
+    # outside the LDS slab) within reach of the offsets.  Both strictly
+    # diagonally dominant (SPD, well conditioned).
+    n = 90000 if case == "far_columns" else 20000
+    i = np.arange(n - 1)
+    pairs = [(i, i + 1, np.full(n - 1, -1.0))]
+    if case == "far_columns":
+        k = np.arange(n - 40000)
+        pairs.append((k, k + 40000, np.full(k.size, -0.25)))
+    else:
+        j = np.arange(2, 3001)
+        pairs.append((np.zeros(j.size, np.int64), j, np.full(j.size, -0.001)))
+    A = _sym_csr(n, 4.0, pairs)
+    b = I.rhs_from_solution(A, I.uniform_vector(n, 6))
+    ref = oracle.cg_mixed(A, b, tol=1e-10, maxit=5000, delta=0.1)
+    j64 = oracle.pcg(A, b, tol=1e-10, maxit=5000, precond="jacobi")
+    g = solve(A, b, tol=1e-10, maxit=5000, precond="jacobi", precision="mixed")
+    assert g["status"] == 0 and ref["status"] == 0
+    assert oracle.true_relres(A, b, g["x"]) <= 1e-10
+    assert within(g["iters"], ref["iters"], 0.05, 3) or g["iters"] <= 1.15 * j64["iters"] + 5
+    assert np.allclose(g["hist"][:5], ref["hist"][:5], rtol=1e-4)
