@@ -5,8 +5,9 @@
 //   K1  q = A p            SpMV with p.q folded into the row epilogue
 //   F1  sigma = sum of K1's partials, alpha = rho / sigma   (one workgroup)
 //   K2  x += alpha p, r -= alpha q, z = D^-1 r   (z not stored); partials r.z, r.r
-//   F2  rho', ||r||^2 -> beta, history entry, stop decision  (one workgroup)
-//   K3  p = D^-1 r + beta p
+//   K3F every workgroup sums K2's partials (rho', ||r||^2 -> beta, stop
+//       decision) and updates p = D^-1 r + beta p; workgroup 0 records the
+//       pass (history entry, state)
 // Every kernel carries the pass number it belongs to and does nothing unless
 // the device state is at that pass and running, so the host can enqueue a
 // batch of passes and read one status word per batch.
@@ -45,6 +46,12 @@ struct CgState {
     double rho, alpha, beta, rr, nb, thresh, rlast, delta, true_rr, r2_64;
     float rho32, alpha32, beta32, rr32;
     int k, maxit, halt, status, budget, n_updates, bad_diag, c16_bad;
+    // folded pass end (K3F): rho by pass parity, so that the workgroup that
+    // records pass e + 1 never writes what the others of pass e still read;
+    // kq = the last pass whose F1 ran (K3F's gate)
+    double rho_pp[2];
+    float rho32_pp[2];
+    int kq, pad;
 };
 
 constexpr int kVecPer = 4;
@@ -77,6 +84,7 @@ __global__ void k_init_state(CgState *st, int maxit, double delta, int budget) {
         s.maxit = maxit;
         s.delta = delta;
         s.budget = budget;
+        s.kq = -1;
         *st = s;
     }
 }
@@ -86,6 +94,7 @@ __global__ void k_phase_state(CgState *st) {
     if (threadIdx.x == 0) {
         st->halt = RUN;
         st->status = SPCG_OK;
+        st->kq = -1;
     }
 }
 
@@ -220,6 +229,7 @@ k_fin_start(CgState *st, const double *part, int nslots, double *hist) {
     finalize_sum(part, nslots, t);
     if (threadIdx.x != 0) return;
     st->rho = t[0];
+    st->rho_pp[st->k & 1] = t[0];
     st->rr = t[1];
     hist[st->k] = sqrt(t[1]) / st->nb;
     if (!finite_d(t[0]) || !finite_d(t[1])) set_break(st, NAN);
@@ -258,8 +268,9 @@ k_cg_q(CsrDev A, const TV *__restrict__ vals, const T *__restrict__ p, T *__rest
     store_block_partials(part, slot, v, sm.red);
 }
 
-// F1: sigma = p.q, alpha = rho / sigma
-template <typename T>
+// F1: sigma = p.q, alpha = rho / sigma.  PP: rho by pass parity, and kq set
+// for the folded pass end (K3F).
+template <typename T, bool PP = false>
 __global__ void __launch_bounds__(kFinThreads)
 k_fin_q(CgState *st, const T *part, int nslots, int expect) {
     if (st->halt != RUN || st->k != expect) return;
@@ -269,11 +280,14 @@ k_fin_q(CgState *st, const T *part, int nslots, int expect) {
     const T sigma = t[0];
     if (!(sigma > T(0)) || !finite_d((double)sigma)) {
         set_break(st, (double)sigma);
-    } else if constexpr (sizeof(T) == 8) {
-        st->alpha = st->rho / sigma;
-    } else {
-        st->alpha32 = st->rho32 / sigma;
+        return;
     }
+    if constexpr (sizeof(T) == 8) {
+        st->alpha = (PP ? st->rho_pp[expect & 1] : st->rho) / sigma;
+    } else {
+        st->alpha32 = (PP ? st->rho32_pp[expect & 1] : st->rho32) / sigma;
+    }
+    if (PP) st->kq = expect;
 }
 
 // K2: x += alpha p, r -= alpha q, z = M^-1 r; partials (r.z, r.r).
@@ -286,16 +300,18 @@ k_cg_xr(int n, int expect, T *__restrict__ x, T *__restrict__ r, const T *__rest
     if (st->halt != RUN || st->k != expect) return;
     const T alpha = st_alpha<T>(st);
     T rz = T(0), rr = T(0);
-    const int base = blockIdx.x * kVecBlock + threadIdx.x;
+    for (int tile = blockIdx.x; tile * kVecBlock < n; tile += gridDim.x) {
+        const int base = tile * kVecBlock + threadIdx.x;
 #pragma unroll
-    for (int u = 0; u < kVecPer; ++u) {
-        const int i = base + u * kBlock;
-        if (i < n) {
-            x[i] += alpha * p[i];
-            const T ri = r[i] - alpha * q[i];
-            r[i] = ri;
-            if constexpr (PRE == SPCG_PRECOND_JACOBI) rz += ri * (dinv[i] * ri);
-            rr += ri * ri;
+        for (int u = 0; u < kVecPer; ++u) {
+            const int i = base + u * kBlock;
+            if (i < n) {
+                x[i] += alpha * p[i];
+                const T ri = r[i] - alpha * q[i];
+                r[i] = ri;
+                if constexpr (PRE == SPCG_PRECOND_JACOBI) rz += ri * (dinv[i] * ri);
+                rr += ri * ri;
+            }
         }
     }
     if constexpr (PRE == SPCG_PRECOND_NONE) rz = rr;
@@ -303,44 +319,117 @@ k_cg_xr(int n, int expect, T *__restrict__ x, T *__restrict__ r, const T *__rest
     store_block_partials(part, blockIdx.x, v, red);
 }
 
-// F2: pass count, history, stop decision, beta and rho
+// Update kernels of the folded pass end run with at most kXrGrid workgroups
+// (each walks a range of tiles), so K3F sums at most 2 kXrGrid partials.
+constexpr int kXrGrid = 1024;
+
+// K3F: the end-of-pass finalize folded into p = z + beta p.  Every workgroup
+// sums K2's partials itself, in the same fixed order, so all of them get the
+// same rho' and ||r||^2 and take the same stop decision; unless the pass ends
+// the loop (converged, out of passes, breakdown) they update p.  Workgroup 0
+// records the pass: count, history, rho' (into the other parity slot), beta,
+// decision.  The gate is kq (F1 of this pass ran), which those writes do not
+// touch.  T = float: the mixed inner loop (replacement instead of stop).
 template <typename T, int PRE, bool MIXED>
-__global__ void __launch_bounds__(kFinThreads)
-k_fin_xr(CgState *st, const T *part, int nslots, double *hist, int expect) {
-    if (st->halt != RUN || st->k != expect) return;
-    T t[2];
-    finalize_sum(part, nslots, t);
-    if (threadIdx.x != 0) return;
+__global__ void __launch_bounds__(kBlock)
+k_cg_pf(int n, int expect, const T *__restrict__ r, const T *__restrict__ dinv,
+        T *__restrict__ p, CgState *st, const T *__restrict__ part, int nslots,
+        double *__restrict__ hist) {
+    __shared__ T sh[kWaves * 2];
+    if (st->kq != expect) return;
+    // the first tile's operands are requested before the partials are summed
+    const int tid = threadIdx.x;
+    int tile = blockIdx.x;
+    T rv[kVecPer], dv[kVecPer], pv[kVecPer];
+#pragma unroll
+    for (int u = 0; u < kVecPer; ++u) {
+        const int i = min(tile * kVecBlock + tid + u * kBlock, n - 1);
+        rv[u] = r[i];
+        dv[u] = PRE == SPCG_PRECOND_JACOBI ? dinv[i] : T(1);
+        pv[u] = p[i];
+    }
+    T a0 = T(0), a1 = T(0);
+    for (int j = tid; j < nslots; j += kBlock) {
+        a0 += part[2 * j];
+        a1 += part[2 * j + 1];
+    }
+    a0 = wave_sum(a0);
+    a1 = wave_sum(a1);
+    if ((tid & 63) == 0) {
+        sh[2 * (tid >> 6)] = a0;
+        sh[2 * (tid >> 6) + 1] = a1;
+    }
+    __syncthreads();
+    T t0 = T(0), t1 = T(0);
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        t0 += sh[2 * w];
+        t1 += sh[2 * w + 1];
+    }
+    // the decision of the former end-of-pass finalize, in every workgroup
     const int k = expect + 1;
-    st->k = k;
-    const double rrd = (double)t[1];
+    const double rrd = (double)t1;
     const double est = sqrt(rrd);
-    hist[k] = est / st->nb;
-    if (!finite_d((double)t[0]) || !finite_d(rrd)) {
-        set_break(st, NAN);
-        return;
+    bool brk = false;
+    double brk_v = 0.0;
+    if (!finite_d((double)t0) || !finite_d(rrd)) {
+        brk = true;
+        brk_v = NAN;
+    } else if (rrd > 0.0 && !(t0 > T(0))) {
+        brk = true;
+        brk_v = (double)t0;
     }
-    if constexpr (PRE != SPCG_PRECOND_LEARNED) {
-        if (rrd > 0.0 && !(t[0] > T(0))) {
-            set_break(st, (double)t[0]);
-            return;
+    int halt = RUN;
+    T beta = T(0);
+    if (!brk) {
+        if constexpr (MIXED) {
+            beta = t0 / st->rho32_pp[expect & 1];
+            if (est < st->delta * st->rlast || est <= st->thresh || k >= st->maxit) halt = H_REPLACE;
+        } else {
+            beta = T((double)t0 / st->rho_pp[expect & 1]);
+            if (est <= st->thresh) halt = H_CONV;
+            else if (k >= st->maxit) halt = H_MAXIT;
         }
     }
-    if constexpr (MIXED) {
-        st->beta32 = t[0] / st->rho32;
-        st->rho32 = t[0];
-        st->rr32 = t[1];
-        if (est < st->delta * st->rlast || est <= st->thresh || k >= st->maxit)
-            st->halt = H_REPLACE;
-    } else {
-        st->rr = rrd;
-        if constexpr (PRE != SPCG_PRECOND_LEARNED) {
-            st->beta = (double)t[0] / st->rho;
-            st->rho = (double)t[0];
+    if (blockIdx.x == 0 && tid == 0) {
+        st->k = k;
+        hist[k] = est / st->nb;
+        if (brk) {
+            set_break(st, brk_v);
+        } else {
+            if constexpr (MIXED) {
+                st->beta32 = beta;
+                st->rho32 = t0;
+                st->rho32_pp[k & 1] = t0;
+                st->rr32 = t1;
+            } else {
+                st->beta = (double)beta;
+                st->rho = (double)t0;
+                st->rho_pp[k & 1] = (double)t0;
+                st->rr = rrd;
+            }
+            if (halt != RUN) st->halt = halt;
         }
-        if (est <= st->thresh) st->halt = H_CONV;
-        else if (k >= st->maxit) st->halt = H_MAXIT;
-        else if (PRE == SPCG_PRECOND_LEARNED && k >= st->budget) st->halt = H_BUDGET;
+    }
+    if (brk || (halt != RUN && halt != H_REPLACE)) return;
+    for (;;) {
+#pragma unroll
+        for (int u = 0; u < kVecPer; ++u) {
+            const int i = tile * kVecBlock + tid + u * kBlock;
+            if (i < n) {
+                const T zi = PRE == SPCG_PRECOND_JACOBI ? dv[u] * rv[u] : rv[u];
+                p[i] = zi + beta * pv[u];
+            }
+        }
+        tile += gridDim.x;
+        if (tile * kVecBlock >= n) break;
+#pragma unroll
+        for (int u = 0; u < kVecPer; ++u) {
+            const int i = min(tile * kVecBlock + tid + u * kBlock, n - 1);
+            rv[u] = r[i];
+            dv[u] = PRE == SPCG_PRECOND_JACOBI ? dinv[i] : T(1);
+            pv[u] = p[i];
+        }
     }
 }
 
@@ -674,6 +763,7 @@ k_fin_mprz(CgState *st, const float *part, int nslots, double *hist, int init) {
     finalize_sum(part, nslots, t);
     if (threadIdx.x != 0) return;
     st->rho32 = t[0];
+    st->rho32_pp[st->k & 1] = t[0];
     if (init) hist[st->k] = st->rlast / st->nb;
     if (!finite_d((double)t[0]) || !finite_d(st->rlast)) set_break(st, NAN);
     else if (st->rlast <= st->thresh) st->halt = H_CONV;
@@ -1081,6 +1171,7 @@ struct Solver {
         return SPCG_OK;
     }
     unsigned gv() const { return grid_of(A->n_rows, kVecBlock); }
+    unsigned gxr() const { return std::min<unsigned>(gv(), kXrGrid); }
     unsigned gA() const { return spmv_grid(A->n_blocks); }
     unsigned gG() const { return factor_grid(o->G); }
 
@@ -1199,22 +1290,26 @@ struct Solver {
                                   w.partd, e);
             }
         }
-        hipLaunchKernelGGL(k_fin_q<double>, dim3(1), dim3(kFinThreads), 0, s, w.st, pd, (int)gA(), e);
-        if (pre == SPCG_PRECOND_JACOBI) {
-            hipLaunchKernelGGL((k_cg_xr<double, SPCG_PRECOND_JACOBI>), dim3(gv()), dim3(kBlock), 0,
-                               s, n, e, x, w.r, w.p, w.q, w.dinv, w.st, w.partd);
-            hipLaunchKernelGGL((k_fin_xr<double, SPCG_PRECOND_JACOBI, false>), dim3(1),
-                               dim3(kFinThreads), 0, s, w.st, pd, (int)gv(), w.hist, e);
-            hipLaunchKernelGGL((k_cg_p<double, SPCG_PRECOND_JACOBI>), dim3(gv()), dim3(kBlock), 0,
-                               s, n, e, w.r, w.dinv, w.z, w.p, w.st);
-        } else if (pre == SPCG_PRECOND_NONE) {
-            hipLaunchKernelGGL((k_cg_xr<double, SPCG_PRECOND_NONE>), dim3(gv()), dim3(kBlock), 0, s,
-                               n, e, x, w.r, w.p, w.q, w.dinv, w.st, w.partd);
-            hipLaunchKernelGGL((k_fin_xr<double, SPCG_PRECOND_NONE, false>), dim3(1),
-                               dim3(kFinThreads), 0, s, w.st, pd, (int)gv(), w.hist, e);
-            hipLaunchKernelGGL((k_cg_p<double, SPCG_PRECOND_NONE>), dim3(gv()), dim3(kBlock), 0, s,
-                               n, e, w.r, w.dinv, w.z, w.p, w.st);
+        if (pre != SPCG_PRECOND_LEARNED) {
+            // F1, K2 on at most kXrGrid workgroups, K3F (pass end folded in)
+            const unsigned gx = gxr();
+            hipLaunchKernelGGL((k_fin_q<double, true>), dim3(1), dim3(kFinThreads), 0, s, w.st, pd,
+                               (int)gA(), e);
+            if (pre == SPCG_PRECOND_JACOBI) {
+                hipLaunchKernelGGL((k_cg_xr<double, SPCG_PRECOND_JACOBI>), dim3(gx), dim3(kBlock), 0,
+                                   s, n, e, x, w.r, w.p, w.q, w.dinv, w.st, w.partd);
+                hipLaunchKernelGGL((k_cg_pf<double, SPCG_PRECOND_JACOBI, false>), dim3(gx),
+                                   dim3(kBlock), 0, s, n, e, (const double *)w.r,
+                                   (const double *)w.dinv, w.p, w.st, pd, (int)gx, w.hist);
+            } else {
+                hipLaunchKernelGGL((k_cg_xr<double, SPCG_PRECOND_NONE>), dim3(gx), dim3(kBlock), 0,
+                                   s, n, e, x, w.r, w.p, w.q, w.dinv, w.st, w.partd);
+                hipLaunchKernelGGL((k_cg_pf<double, SPCG_PRECOND_NONE, false>), dim3(gx),
+                                   dim3(kBlock), 0, s, n, e, (const double *)w.r,
+                                   (const double *)w.dinv, w.p, w.st, pd, (int)gx, w.hist);
+            }
         } else {
+            hipLaunchKernelGGL(k_fin_q<double>, dim3(1), dim3(kFinThreads), 0, s, w.st, pd, (int)gA(), e);
             hipLaunchKernelGGL((k_cg_xr<double, SPCG_PRECOND_LEARNED>), dim3(gv()), dim3(kBlock),
                                0, s, n, e, x, w.r, w.p, w.q, w.dinv, w.st, w.partd);
             apply_factor(e);
@@ -1245,13 +1340,14 @@ struct Solver {
                                    (const float *)w.p32, w.q32, w.st, w.partf, e);
             }
         }
-        hipLaunchKernelGGL(k_fin_q<float>, dim3(1), dim3(kFinThreads), 0, s, w.st, pf, (int)gA(), e);
-        hipLaunchKernelGGL((k_cg_xr<float, SPCG_PRECOND_JACOBI>), dim3(gv()), dim3(kBlock), 0, s,
+        const unsigned gx = gxr();
+        hipLaunchKernelGGL((k_fin_q<float, true>), dim3(1), dim3(kFinThreads), 0, s, w.st, pf,
+                           (int)gA(), e);
+        hipLaunchKernelGGL((k_cg_xr<float, SPCG_PRECOND_JACOBI>), dim3(gx), dim3(kBlock), 0, s,
                            n, e, w.x32, w.r32, w.p32, w.q32, w.dinv32, w.st, w.partf);
-        hipLaunchKernelGGL((k_fin_xr<float, SPCG_PRECOND_JACOBI, true>), dim3(1),
-                           dim3(kFinThreads), 0, s, w.st, pf, (int)gv(), w.hist, e);
-        hipLaunchKernelGGL((k_cg_p<float, SPCG_PRECOND_JACOBI>), dim3(gv()), dim3(kBlock), 0, s, n,
-                           e, w.r32, w.dinv32, (const float *)nullptr, w.p32, w.st);
+        hipLaunchKernelGGL((k_cg_pf<float, SPCG_PRECOND_JACOBI, true>), dim3(gx), dim3(kBlock), 0,
+                           s, n, e, (const float *)w.r32, (const float *)w.dinv32, w.p32, w.st, pf,
+                           (int)gx, w.hist);
         SPCG_LAUNCH_CHECK("mixed pass");
         return SPCG_OK;
     }
