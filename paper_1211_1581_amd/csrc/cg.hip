@@ -63,9 +63,6 @@ inline int64_t vec_blocks(int64_t n) { return (n + kVecBlock - 1) / kVecBlock; }
 template <typename T> __device__ __forceinline__ T st_alpha(const CgState *s);
 template <> __device__ __forceinline__ double st_alpha<double>(const CgState *s) { return s->alpha; }
 template <> __device__ __forceinline__ float st_alpha<float>(const CgState *s) { return s->alpha32; }
-template <typename T> __device__ __forceinline__ T st_beta(const CgState *s);
-template <> __device__ __forceinline__ double st_beta<double>(const CgState *s) { return s->beta; }
-template <> __device__ __forceinline__ float st_beta<float>(const CgState *s) { return s->beta32; }
 
 __device__ __forceinline__ bool finite_d(double v) { return isfinite(v); }
 
@@ -319,9 +316,55 @@ k_cg_xr(int n, int expect, T *__restrict__ x, T *__restrict__ r, const T *__rest
     store_block_partials(part, blockIdx.x, v, red);
 }
 
+// Fixed-order totals of a[j * SA + OA] (j < na) and b[j * SB + OB] (j < nb)
+// in every thread of a kBlock workgroup (na, nb >= 1).  Loads go in batches of
+// 8 per thread at clamped, in-bounds indices, all in flight together; the
+// order of the sums depends only on na and nb, so every workgroup that calls
+// this on the same partials gets the same totals.
+template <int SA, int OA, int SB, int OB, typename T>
+__device__ __forceinline__ void wg_totals(const T *__restrict__ a, int na, const T *__restrict__ b,
+                                          int nb, T &ta, T &tb, T *sh /* kWaves * 2 */) {
+    constexpr int kPer = 8;
+    const int tid = threadIdx.x;
+    T acc_a = T(0), acc_b = T(0);
+    const int nmax = na > nb ? na : nb;
+    for (int base = 0; base < nmax; base += kBlock * kPer) {
+        T va[kPer], vb[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int j = base + tid + u * kBlock;
+            va[u] = a[(size_t)min(j, na - 1) * SA + OA];
+            vb[u] = b[(size_t)min(j, nb - 1) * SB + OB];
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int j = base + tid + u * kBlock;
+            acc_a += j < na ? va[u] : T(0);
+            acc_b += j < nb ? vb[u] : T(0);
+        }
+    }
+    acc_a = wave_sum(acc_a);
+    acc_b = wave_sum(acc_b);
+    if ((tid & 63) == 0) {
+        sh[2 * (tid >> 6)] = acc_a;
+        sh[2 * (tid >> 6) + 1] = acc_b;
+    }
+    __syncthreads();
+    ta = T(0);
+    tb = T(0);
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        ta += sh[2 * w];
+        tb += sh[2 * w + 1];
+    }
+}
+
 // Update kernels of the folded pass end run with at most kXrGrid workgroups
 // (each walks a range of tiles), so K3F sums at most 2 kXrGrid partials.
 constexpr int kXrGrid = 1024;
+// Workgroups of the learned form's z = G t (each walks a range of row blocks
+// or short-row steps): K3L sums one partial per workgroup.
+constexpr int kApplyGrid = 4096;
 
 // K3F: the end-of-pass finalize folded into p = z + beta p.  Every workgroup
 // sums K2's partials itself, in the same fixed order, so all of them get the
@@ -348,24 +391,8 @@ k_cg_pf(int n, int expect, const T *__restrict__ r, const T *__restrict__ dinv,
         dv[u] = PRE == SPCG_PRECOND_JACOBI ? dinv[i] : T(1);
         pv[u] = p[i];
     }
-    T a0 = T(0), a1 = T(0);
-    for (int j = tid; j < nslots; j += kBlock) {
-        a0 += part[2 * j];
-        a1 += part[2 * j + 1];
-    }
-    a0 = wave_sum(a0);
-    a1 = wave_sum(a1);
-    if ((tid & 63) == 0) {
-        sh[2 * (tid >> 6)] = a0;
-        sh[2 * (tid >> 6) + 1] = a1;
-    }
-    __syncthreads();
-    T t0 = T(0), t1 = T(0);
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
-        t0 += sh[2 * w];
-        t1 += sh[2 * w + 1];
-    }
+    T t0, t1;
+    wg_totals<2, 0, 2, 1>(part, nslots, part, nslots, t0, t1, sh);
     // the decision of the former end-of-pass finalize, in every workgroup
     const int k = expect + 1;
     const double rrd = (double)t1;
@@ -429,27 +456,6 @@ k_cg_pf(int n, int expect, const T *__restrict__ r, const T *__restrict__ dinv,
             rv[u] = r[i];
             dv[u] = PRE == SPCG_PRECOND_JACOBI ? dinv[i] : T(1);
             pv[u] = p[i];
-        }
-    }
-}
-
-// K3: p = z + beta p  (z = D^-1 r, r, or the stored z)
-template <typename T, int PRE>
-__global__ void __launch_bounds__(kBlock)
-k_cg_p(int n, int expect, const T *__restrict__ r, const T *__restrict__ dinv,
-       const T *__restrict__ z, T *__restrict__ p, const CgState *st) {
-    const int h = st->halt;
-    if (st->k != expect + 1 || (h != RUN && h != H_REPLACE)) return;
-    const T beta = st_beta<T>(st);
-    const int base = blockIdx.x * kVecBlock + threadIdx.x;
-#pragma unroll
-    for (int u = 0; u < kVecPer; ++u) {
-        const int i = base + u * kBlock;
-        if (i < n) {
-            const T zi = PRE == SPCG_PRECOND_JACOBI ? dinv[i] * r[i]
-                         : PRE == SPCG_PRECOND_NONE ? r[i]
-                                                    : z[i];
-            p[i] = zi + beta * p[i];
         }
     }
 }
@@ -523,34 +529,79 @@ k_g_apply(FactorDev G, const double *__restrict__ t, const double *__restrict__ 
     store_block_partials(part, slot, v, sm.red);
 }
 
-// End of a learned pass (one finalize for both reductions): ||r||^2 from the
-// update kernel's partials and r.z from the G-apply partials -> pass count,
-// history, stop decision, beta and rho.  z of the last pass is computed even
-// when the pass converges; it is not used.
-__global__ void __launch_bounds__(kFinThreads)
-k_fin_learned(CgState *st, const double *part_xr, int n_xr, const double *part_g, int n_g,
-              double *hist, int expect) {
-    if (st->halt != RUN || st->k != expect) return;
-    double t[2], g[1];
-    finalize_sum2<double, 2, 1>(part_xr, n_xr, t, part_g, n_g, g);
-    if (threadIdx.x != 0) return;
-    const int k = expect + 1;
-    st->k = k;
-    const double rr = t[1], rho = g[0];
-    const double est = sqrt(rr);
-    hist[k] = est / st->nb;
-    if (!finite_d(rr) || !finite_d(rho)) {
-        set_break(st, NAN);
-        return;
+// K3L: the learned pass's end folded into p = z + beta p, as K3F: every
+// workgroup sums ||r||^2 from K2's partials (second value of each slot) and
+// r.z from the G apply's partials in one fixed order, takes the decision of a
+// learned pass (converged, out of passes, budget used up, breakdown) and
+// updates p unless the pass ends the loop; workgroup 0 records the pass.
+__global__ void __launch_bounds__(kBlock)
+k_cg_pl(int n, int expect, const double *__restrict__ z, double *__restrict__ p, CgState *st,
+        const double *__restrict__ part_xr, int n_xr, const double *__restrict__ part_g, int n_g,
+        double *__restrict__ hist) {
+    __shared__ double sh[kWaves * 2];
+    if (st->kq != expect) return;
+    const int tid = threadIdx.x;
+    int tile = blockIdx.x;
+    double zv[kVecPer], pv[kVecPer];
+#pragma unroll
+    for (int u = 0; u < kVecPer; ++u) {
+        const int i = min(tile * kVecBlock + tid + u * kBlock, n - 1);
+        zv[u] = z[i];
+        pv[u] = p[i];
     }
-    st->rr = rr;
-    if (est <= st->thresh) st->halt = H_CONV;
-    else if (k >= st->maxit) st->halt = H_MAXIT;
-    else if (k >= st->budget) st->halt = H_BUDGET;
-    else if (rr > 0.0 && !(rho > 0.0)) set_break(st, rho);
-    else {
-        st->beta = rho / st->rho;
-        st->rho = rho;
+    double rr, rho;
+    wg_totals<2, 1, 1, 0>(part_xr, n_xr, part_g, n_g, rr, rho, sh);
+    const int k = expect + 1;
+    const double est = sqrt(rr);
+    bool brk = false;
+    double brk_v = NAN;
+    int halt = RUN;
+    double beta = 0.0;
+    if (!finite_d(rr) || !finite_d(rho)) {
+        brk = true;
+    } else if (est <= st->thresh) {
+        halt = H_CONV;
+    } else if (k >= st->maxit) {
+        halt = H_MAXIT;
+    } else if (k >= st->budget) {
+        halt = H_BUDGET;
+    } else if (rr > 0.0 && !(rho > 0.0)) {
+        brk = true;
+        brk_v = rho;
+    } else {
+        beta = rho / st->rho_pp[expect & 1];
+    }
+    if (blockIdx.x == 0 && tid == 0) {
+        st->k = k;
+        hist[k] = est / st->nb;
+        if (brk) {
+            set_break(st, brk_v);
+        } else {
+            st->rr = rr;
+            if (halt != RUN) {
+                st->halt = halt;
+            } else {
+                st->beta = beta;
+                st->rho = rho;
+                st->rho_pp[k & 1] = rho;
+            }
+        }
+    }
+    if (brk || halt != RUN) return;
+    for (;;) {
+#pragma unroll
+        for (int u = 0; u < kVecPer; ++u) {
+            const int i = tile * kVecBlock + tid + u * kBlock;
+            if (i < n) p[i] = zv[u] + beta * pv[u];
+        }
+        tile += gridDim.x;
+        if (tile * kVecBlock >= n) break;
+#pragma unroll
+        for (int u = 0; u < kVecPer; ++u) {
+            const int i = min(tile * kVecBlock + tid + u * kBlock, n - 1);
+            zv[u] = z[i];
+            pv[u] = p[i];
+        }
     }
 }
 
@@ -1173,7 +1224,8 @@ struct Solver {
     unsigned gv() const { return grid_of(A->n_rows, kVecBlock); }
     unsigned gxr() const { return std::min<unsigned>(gv(), kXrGrid); }
     unsigned gA() const { return spmv_grid(A->n_blocks); }
-    unsigned gG() const { return factor_grid(o->G); }
+    // the G apply's workgroups (and r.z partials, which every workgroup of K3L sums)
+    unsigned gG() const { return std::min<unsigned>(factor_grid(o->G), kApplyGrid); }
 
     // z = G (G^T r); r.z partials of the G apply in w.partg
     void apply_factor(int kexp) {
@@ -1309,14 +1361,15 @@ struct Solver {
                                    (const double *)w.dinv, w.p, w.st, pd, (int)gx, w.hist);
             }
         } else {
-            hipLaunchKernelGGL(k_fin_q<double>, dim3(1), dim3(kFinThreads), 0, s, w.st, pd, (int)gA(), e);
-            hipLaunchKernelGGL((k_cg_xr<double, SPCG_PRECOND_LEARNED>), dim3(gv()), dim3(kBlock),
+            // F1, K2 (r.r), z = G (G^T r) with r.z, K3L (pass end folded in)
+            const unsigned gx = gxr();
+            hipLaunchKernelGGL((k_fin_q<double, true>), dim3(1), dim3(kFinThreads), 0, s, w.st, pd,
+                               (int)gA(), e);
+            hipLaunchKernelGGL((k_cg_xr<double, SPCG_PRECOND_LEARNED>), dim3(gx), dim3(kBlock),
                                0, s, n, e, x, w.r, w.p, w.q, w.dinv, w.st, w.partd);
             apply_factor(e);
-            hipLaunchKernelGGL(k_fin_learned, dim3(1), dim3(kFinThreads), 0, s, w.st, pd, (int)gv(),
-                               (const double *)w.partg, (int)gG(), w.hist, e);
-            hipLaunchKernelGGL((k_cg_p<double, SPCG_PRECOND_LEARNED>), dim3(gv()), dim3(kBlock),
-                               0, s, n, e, w.r, w.dinv, w.z, w.p, w.st);
+            hipLaunchKernelGGL(k_cg_pl, dim3(gx), dim3(kBlock), 0, s, n, e, (const double *)w.z, w.p,
+                               w.st, pd, (int)gx, (const double *)w.partg, (int)gG(), w.hist);
         }
         SPCG_LAUNCH_CHECK("cg pass");
         return SPCG_OK;
