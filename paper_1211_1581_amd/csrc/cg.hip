@@ -303,8 +303,11 @@ k_cg_xr(int n, int expect, T *__restrict__ x, T *__restrict__ r, const T *__rest
         for (int u = 0; u < kVecPer; ++u) {
             const int i = base + u * kBlock;
             if (i < n) {
-                x[i] += alpha * p[i];
-                const T ri = r[i] - alpha * q[i];
+                // x and q are not read again before they are next written:
+                // non-temporal accesses leave the MALL to the matrix and to
+                // the vectors that are
+                __builtin_nontemporal_store(__builtin_nontemporal_load(x + i) + alpha * p[i], x + i);
+                const T ri = r[i] - alpha * __builtin_nontemporal_load(q + i);
                 r[i] = ri;
                 if constexpr (PRE == SPCG_PRECOND_JACOBI) rz += ri * (dinv[i] * ri);
                 rr += ri * ri;
