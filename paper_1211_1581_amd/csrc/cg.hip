@@ -532,6 +532,118 @@ k_g_apply(FactorDev G, const double *__restrict__ t, const double *__restrict__ 
     store_block_partials(part, slot, v, sm.red);
 }
 
+// ----------------------------------- learned: factors as padded ELL --
+//
+// A factor whose rows hold at most kEllMax entries (the triangles of a
+// 7-point stencil hold 4) is copied at the start of a solve into the
+// workspace as W column-major planes, col[w * n + i] and val[w * n + i] for
+// the w-th entry of row i (padding: column i, value 0).  One thread per row
+// then loads its W columns and values with coalesced loads that depend on
+// nothing, gathers, and sums in the row's order: one round trip fewer than
+// the CSR kernels, which must read row_ptr first.
+constexpr int kEllMax = 8;
+constexpr int kEllGrid = 2048;  // workgroups of an ELL apply (each walks a range of rows)
+
+inline int ell_width(const spcg_csr *F) {
+    return !F || F->max_len > kEllMax ? 0 : (F->max_len <= 4 ? 4 : kEllMax);
+}
+
+template <int W>
+__global__ void __launch_bounds__(kBlock)
+k_to_ell(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+         const float *__restrict__ vals, int32_t *__restrict__ ec, float *__restrict__ ev) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const int a = rp[i], e = rp[i + 1];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const bool in = a + w < e;
+            ec[(size_t)w * n + i] = in ? col[a + w] : i;
+            ev[(size_t)w * n + i] = in ? vals[a + w] : 0.0f;
+        }
+    }
+}
+
+struct EllDev {
+    const int32_t *__restrict__ col;
+    const float *__restrict__ val;
+    int n;
+};
+
+// Rows per thread of an ELL apply: every thread loads the columns and values
+// of R rows at once (clamped, in-bounds indices), then gathers, so a batch
+// costs two round trips to memory however many rows it holds.
+template <int W> constexpr int ell_rows() { return W <= 4 ? 4 : 2; }
+
+// Rows base + u kBlock + threadIdx.x (u < R) of an ELL factor times x, each
+// in its row's order (FP32 values, FP64 sums); rows past n are clamped to
+// n - 1 (the caller drops them).
+template <int W, int R, bool KEEP>
+__device__ __forceinline__ void ell_rows_times(const EllDev &F, const double *__restrict__ x,
+                                               int base, double (&s)[R]) {
+    int c[R][W];
+    float v[R][W];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+        const int i = min(base + u * kBlock + (int)threadIdx.x, F.n - 1);
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const size_t o = (size_t)w * F.n + i;
+            c[u][w] = KEEP ? F.col[o] : __builtin_nontemporal_load(F.col + o);
+            v[u][w] = KEEP ? F.val[o] : __builtin_nontemporal_load(F.val + o);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+        double a = 0.0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) a += (double)v[u][w] * x[c[u][w]];
+        s[u] = a;
+    }
+}
+
+// t = G^T r  (ELL).  kexp: pass number, or -1 at a phase start.
+template <int W, bool KEEP>
+__global__ void __launch_bounds__(kBlock)
+k_gt_ell(EllDev GT, const double *__restrict__ r, double *__restrict__ t, const CgState *st,
+         int kexp) {
+    constexpr int R = ell_rows<W>();
+    if (st->halt != RUN || (kexp >= 0 && st->k != kexp)) return;
+    for (int base = blockIdx.x * kBlock * R; base < GT.n; base += gridDim.x * kBlock * R) {
+        double sv[R];
+        ell_rows_times<W, R, KEEP>(GT, r, base, sv);
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int i = base + u * kBlock + threadIdx.x;
+            if (i < GT.n) t[i] = sv[u];
+        }
+    }
+}
+
+// z = G t (ELL); partial r.z per workgroup
+template <int W, bool KEEP>
+__global__ void __launch_bounds__(kBlock)
+k_g_ell(EllDev G, const double *__restrict__ t, const double *__restrict__ r,
+        double *__restrict__ z, const CgState *st, double *part, int kexp) {
+    constexpr int R = ell_rows<W>();
+    __shared__ double red[kWaves];
+    if (st->halt != RUN || (kexp >= 0 && st->k != kexp)) return;
+    double acc = 0.0;
+    for (int base = blockIdx.x * kBlock * R; base < G.n; base += gridDim.x * kBlock * R) {
+        double sv[R];
+        ell_rows_times<W, R, KEEP>(G, t, base, sv);
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int i = base + u * kBlock + threadIdx.x;
+            if (i < G.n) {
+                z[i] = sv[u];
+                acc += r[i] * sv[u];
+            }
+        }
+    }
+    const double v[1] = {acc};
+    store_block_partials(part, blockIdx.x, v, red);
+}
+
 // K3L: the learned pass's end folded into p = z + beta p, as K3F: every
 // workgroup sums ||r||^2 from K2's partials (second value of each slot) and
 // r.z from the G apply's partials in one fixed order, takes the decision of a
@@ -1069,6 +1181,9 @@ struct Work {
     double *r, *p, *q, *dinv, *z, *t, *x0;
     float *r32, *p32, *q32, *x32, *dinv32, *vals32;
     int16_t *off16;  // mixed: compact columns of the FP32 inner matrix
+    int32_t *g_col, *gt_col;  // learned: ELL copies of G and G^T (w_g, w_gt planes)
+    float *g_val, *gt_val;
+    int w_g, w_gt;
     double *partd;  // [nslots * 2]
     double *partg;  // [nslots]  (learned: r.z partials of the G apply)
     float *partf;   // [nslots * 2]
@@ -1090,6 +1205,7 @@ static int64_t n_slots(const spcg_csr *A, const spcg_cg_opts *o) {
     if (o->precond == SPCG_PRECOND_LEARNED) {
         for (const spcg_csr *F : {o->G, o->GT})
             if (F) s = std::max<int64_t>(s, factor_grid(F));
+        s = std::max<int64_t>(s, std::min<int64_t>((A->n_rows + kBlock - 1) / kBlock, kEllGrid));  // ELL apply
     }
     return std::max<int64_t>(s, 1);
 }
@@ -1120,6 +1236,14 @@ static size_t carve(const spcg_csr *A, const spcg_cg_opts *o, char *base, Work *
         W.t = (double *)take(sizeof(double) * n);  // learned: t;  single reduction: w = A u
     }
     if (learned) W.x0 = (double *)take(sizeof(double) * n);
+    if (learned && ell_width(o->G) && ell_width(o->GT)) {
+        W.w_g = ell_width(o->G);
+        W.w_gt = ell_width(o->GT);
+        W.g_col = (int32_t *)take(sizeof(int32_t) * (size_t)W.w_g * n);
+        W.g_val = (float *)take(sizeof(float) * (size_t)W.w_g * n);
+        W.gt_col = (int32_t *)take(sizeof(int32_t) * (size_t)W.w_gt * n);
+        W.gt_val = (float *)take(sizeof(float) * (size_t)W.w_gt * n);
+    }
     if (mixed) {
         W.r32 = (float *)take(sizeof(float) * n);
         W.p32 = (float *)take(sizeof(float) * n);
@@ -1162,9 +1286,13 @@ struct Solver {
         const int64_t a = mixed ? A->nnz * (c16 ? 6 : 8) + 4 * (int64_t)(A->n_rows + 1)
                                 : matrix_bytes(A->n_rows, A->nnz, 8);
         int64_t f = 0;
-        if (o->precond == SPCG_PRECOND_LEARNED)
-            for (const spcg_csr *F : {o->G, o->GT})
-                if (F) f += matrix_bytes(F->n_rows, F->nnz, F->dtype == SPCG_F32 ? 4 : 8);
+        if (o->precond == SPCG_PRECOND_LEARNED) {
+            if (ell_width(o->G) && ell_width(o->GT))  // the ELL copies (8 bytes per slot)
+                f = (int64_t)(ell_width(o->G) + ell_width(o->GT)) * A->n_rows * 8;
+            else
+                for (const spcg_csr *F : {o->G, o->GT})
+                    if (F) f += matrix_bytes(F->n_rows, F->nnz, F->dtype == SPCG_F32 ? 4 : 8);
+        }
         const int64_t lim = keep_bytes();
         keep = a + f <= lim;
         keep_g = f > 0 && f <= lim;
@@ -1228,10 +1356,33 @@ struct Solver {
     unsigned gxr() const { return std::min<unsigned>(gv(), kXrGrid); }
     unsigned gA() const { return spmv_grid(A->n_blocks); }
     // the G apply's workgroups (and r.z partials, which every workgroup of K3L sums)
-    unsigned gG() const { return std::min<unsigned>(factor_grid(o->G), kApplyGrid); }
+    unsigned gG() const {
+        return w.w_g ? ell_grid() : std::min<unsigned>(factor_grid(o->G), kApplyGrid);
+    }
 
     // z = G (G^T r); r.z partials of the G apply in w.partg
+    unsigned ell_grid() const { return std::min<unsigned>(grid_of(A->n_rows, kBlock), kEllGrid); }
+
+    template <int WG, int WT, bool KEEP>
+    void apply_ell(int kexp) {
+        const EllDev gt{w.gt_col, w.gt_val, A->n_rows}, g{w.g_col, w.g_val, A->n_rows};
+        hipLaunchKernelGGL((k_gt_ell<WT, KEEP>), dim3(ell_grid()), dim3(kBlock), 0, s, gt,
+                           (const double *)w.r, w.t, w.st, kexp);
+        hipLaunchKernelGGL((k_g_ell<WG, KEEP>), dim3(ell_grid()), dim3(kBlock), 0, s, g,
+                           (const double *)w.t, (const double *)w.r, w.z, w.st, w.partg, kexp);
+    }
+
     void apply_factor(int kexp) {
+        if (w.w_g) {
+#define SPCG_ELL(WG, WT)                                        \
+    if (w.w_g == WG && w.w_gt == WT) {                          \
+        if (keep_g) apply_ell<WG, WT, true>(kexp);              \
+        else apply_ell<WG, WT, false>(kexp);                    \
+        return;                                                 \
+    }
+            SPCG_ELL(4, 4) SPCG_ELL(4, 8) SPCG_ELL(8, 4) SPCG_ELL(8, 8)
+#undef SPCG_ELL
+        }
         const bool sgt = uses_short_rows(o->GT), sg = uses_short_rows(o->G);
         auto gt = sgt ? (keep_g ? k_gt_apply<true, true> : k_gt_apply<true, false>)
                       : (keep_g ? k_gt_apply<false, true> : k_gt_apply<false, false>);
@@ -1605,6 +1756,16 @@ int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o
         hipLaunchKernelGGL(k_copy, dim3(grid_of(n, kBlock * 8)), dim3(kBlock), 0, s, (int64_t)n,
                            (const double *)d_x, w.x0);
         SPCG_LAUNCH_CHECK("k_copy");
+        for (int f = 0; f < 2 && w.w_g; ++f) {
+            const spcg_csr *F = f ? o->GT : o->G;
+            const int wd = f ? w.w_gt : w.w_g;
+            int32_t *ec = f ? w.gt_col : w.g_col;
+            float *ev = f ? w.gt_val : w.g_val;
+            auto kern = wd == 4 ? k_to_ell<4> : k_to_ell<kEllMax>;
+            hipLaunchKernelGGL(kern, dim3(std::min<unsigned>(grid_of(n, kBlock), 4096)), dim3(kBlock),
+                               0, s, n, F->row_ptr, F->col, (const float *)F->vals, ec, ev);
+            SPCG_LAUNCH_CHECK("k_to_ell");
+        }
     }
     if ((rc = S.resid(R_INIT, mixed ? w.r32 : nullptr))) return rc;
     if ((rc = S.read_state())) return rc;

@@ -115,11 +115,13 @@ def test_learned_form_with_jacobi_factor():
     assert fo["status"] == oracle.FELL_BACK and within(f["iters_fallback"], fo["iters_fallback"])
 
 
-@pytest.mark.parametrize("case", ["banded", "poisson2d"])
+@pytest.mark.parametrize("case", ["banded", "poisson2d", "wide"])
 def test_learned_form_general_factor(case):
-    # a factor with off-diagonal values: rows of up to 5 entries (row-block
-    # apply kernels) or at most 3 (short-row apply kernels)
-    A = I.banded_spd(3000, 9) if case == "banded" else I.poisson2d(60)
+    # a factor with off-diagonal values: rows of up to 5 entries (ELL copies
+    # padded to 8), at most 3 (padded to 4), or 10 (more than the ELL copies
+    # take: the CSR row-block apply kernels)
+    A = {"banded": lambda: I.banded_spd(3000, 9), "poisson2d": lambda: I.poisson2d(60),
+         "wide": lambda: I.banded_spd(3000, 19)}[case]()
     b = I.rhs_from_solution(A, I.uniform_vector(A.n_rows, 4))
     Lh, _ = lower_upper(A)
     rng = np.random.default_rng(9)
@@ -131,7 +133,7 @@ def test_learned_form_general_factor(case):
     S = spcg()
     G = S.CsrMatrix.from_host(Lh2, dtype=torch.float32)
     GT = S.CsrMatrix.from_host(Uh2, dtype=torch.float32)
-    assert (G.info()["max_row_len"] > 4) == (case == "banded")
+    assert G.info()["max_row_len"] == {"banded": 5, "poisson2d": 3, "wide": 10}[case]
     M = S.CsrMatrix.from_host(A)
     ref = oracle.pcg(A, b, tol=1e-10, maxit=5000, precond="g", G=Lh2)
     g = S.cg_solve(M, to_dev(b), tol=1e-10, maxit=5000, precond="learned", G=G, GT=GT)
