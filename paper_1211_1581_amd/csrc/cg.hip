@@ -1199,7 +1199,7 @@ static FactorDev factor_view(const spcg_csr *F) {
     return FactorDev{dev_view(F), (const float *)F->vals, F->n_rows};
 }
 
-// Partial-sum slots of the largest producing kernel (one per wavefront)
+// Partial-sum slots of the largest producing kernel (one per workgroup)
 static int64_t n_slots(const spcg_csr *A, const spcg_cg_opts *o) {
     int64_t s = std::max<int64_t>(spmv_grid(A->n_blocks), vec_blocks(A->n_rows));
     if (o->precond == SPCG_PRECOND_LEARNED) {

@@ -18,7 +18,9 @@
 //  * Workgroup indices are remapped so that each XCD walks one contiguous
 //    range of row blocks: x reuse of stencil matrices stays in that XCD's L2.
 //  * Scalar reductions (inner products) are deterministic: per-workgroup
-//    partials in fixed slots, summed in fixed order by a finalize kernel.
+//    partials in fixed slots, summed in fixed order by a one-workgroup
+//    finalize kernel or, at the end of a CG pass, by every workgroup of the
+//    next kernel.
 #pragma once
 
 #include <hip/hip_runtime.h>
