@@ -381,11 +381,21 @@ __global__ void __launch_bounds__(256) k_edge_fwd(int E, const int32_t *__restri
 #pragma unroll
         for (int c = 0; c < 2; ++c) m = mfma32(frag(T, 40, c), w2[c], m);
         wave_lds_sync();
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int r = tile * 32 + acc_row(q, lane);
-            if (r < E) eout[(size_t)r * H + (lane & 31)] = (__bf16)m[q];
+        // the message tile goes out through LDS: each lane stores 16
+        // consecutive BF16 of one row with two 16-byte stores
+        acc_to_lds(m, T, 40, false);
+        wave_lds_sync();
+        {
+            const int rr = lane >> 1, half = lane & 1;
+            const int r = tile * 32 + rr;
+            if (r < E) {
+                const bf16x8 *src = reinterpret_cast<const bf16x8 *>(T + rr * 40 + 16 * half);
+                bf16x8 *dst = reinterpret_cast<bf16x8 *>(eout + (size_t)r * H + 16 * half);
+                dst[0] = src[0];
+                dst[1] = src[1];
+            }
         }
+        wave_lds_sync();
     }
 }
 
