@@ -49,12 +49,20 @@ def jpcg_pass_bytes(n, nnz):
     return spmv_bytes(n, nnz) + 88 * n
 
 
-def kernel_source_hash():
-    """Hash of the HIP sources with comments and blank space removed, so that a
-    comment edit does not retire the counter summaries taken on the same code."""
+# sources of the CG pass kernels (k_cg_q and the kernels around it)
+CG_SOURCES = ("internal.h", "cg.hip")
+
+
+def kernel_source_hash(files=None):
+    """Hash of the HIP sources (all of them, or the named files of csrc/) with
+    comments and blank space removed, so that a comment edit does not retire
+    the counter summaries taken on the same code."""
     import re
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1211_1581_amd", "csrc", "*"))):
+    csrc = os.path.join(ROOT, "paper_1211_1581_amd", "csrc")
+    paths = sorted(glob.glob(os.path.join(csrc, "*"))) if files is None else \
+        [os.path.join(csrc, f) for f in files]
+    for f in paths:
         with open(f, encoding="utf-8") as fh:
             text = fh.read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
@@ -71,7 +79,7 @@ def measured_traffic(kernel, workload):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("source_hash") != kernel_source_hash():
+    if d.get("source_hash") != kernel_source_hash(CG_SOURCES):
         return None
     return d.get("bytes_per_launch")
 
