@@ -103,12 +103,71 @@ inline unsigned spmv_grid(int64_t nb) {
 
 // ------------------------------------------------------------ reductions --
 
+// Cross-lane moves inside rows of 16 lanes by DPP (v_mov_b32_dpp: a VALU
+// operand modifier, no LDS round trip; a 64-lane shuffle goes through the LDS
+// crossbar as ds_bpermute).  The source lanes are those of the caller's group,
+// which must be active.
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]: lane l <- l ^ 1
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]: lane l <- l ^ 2
+constexpr int kDppHalfMirror = 0x141;  // lane l <- 7 - l within each group of 8
+constexpr int kDppMirror = 0x140;      // lane l <- 15 - l within each row of 16
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_mov(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ int lane_value(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+
+__device__ __forceinline__ float lane_value(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over groups of L aligned lanes (L a power of two <= 64, uniform over
+// the wavefront): every lane of a group ends with its group's sum.  Within a
+// row of 16 the pairs are formed by mirrors and quad permutations, which
+// cover each group exactly like an xor butterfly.
+template <typename T>
+__device__ __forceinline__ T group_sum(T s, int L) {
+    if (L >= 64) s += __shfl_xor(s, 32, 64);
+    if (L >= 32) s += __shfl_xor(s, 16, 64);
+    if (L >= 16) s += dpp_mov<kDppMirror>(s);
+    if (L >= 8) s += dpp_mov<kDppHalfMirror>(s);
+    if (L >= 4) s += dpp_mov<kDppXor2>(s);
+    if (L >= 2) s += dpp_mov<kDppXor1>(s);
+    return s;
+}
+
+// Sum over a whole wavefront (all lanes active): rows of 16 by DPP, then the
+// four row sums read from lanes 0, 16, 32, 48 and added in a fixed order, so
+// every lane gets the same value.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
-    // butterfly: every lane ends with the same, order-fixed sum
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_mov<kDppXor1>(v);
+    v += dpp_mov<kDppXor2>(v);
+    v += dpp_mov<kDppHalfMirror>(v);
+    v += dpp_mov<kDppMirror>(v);
+    return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 
 // Sum over a 256-thread workgroup; every thread receives the result.
@@ -368,7 +427,7 @@ __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict
             const int a = sm.rp[r], e = sm.rp[r + 1];
             TA s = TA(0);
             for (int t = a + lane; t < e; t += L) s += sm.slab[t];
-            for (int o = L >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+            s = group_sum(s, L);
             if (lane == 0 && e > a) sm.slab[a] = s;
         }
     }
@@ -460,8 +519,8 @@ __device__ __forceinline__ void spmv_short(const int32_t *__restrict__ rp,
     }
 #pragma unroll
     for (int u = 0; u < kShortRounds; ++u) {
-        s[u] += __shfl_xor(s[u], 1, 64);
-        s[u] += __shfl_xor(s[u], 2, 64);
+        s[u] += dpp_mov<kDppXor1>(s[u]);
+        s[u] += dpp_mov<kDppXor2>(s[u]);
     }
 #pragma unroll
     for (int u = 0; u < kShortRounds; ++u) {
