@@ -163,7 +163,11 @@ typedef struct {
  * standard variant. */
 void spcg_cg_default_opts(spcg_cg_opts *opts);
 
-/* Bytes of device workspace cg_solve needs for A and opts (256-byte aligned pointer). */
+/* Bytes of device workspace cg_solve needs for A and opts (256-byte aligned pointer).  Besides the
+ * vectors and partial sums it holds the solver's own copies: for precision MIXED the FP32 values of A
+ * and 2-byte column offsets; for precond LEARNED with factors of at most 8 entries per row, G and G^T
+ * as padded column-major planes (8 bytes per slot).  So the size depends on opts->precision,
+ * opts->precond and the factor handles. */
 size_t spcg_cg_workspace_bytes(spcg_csr_t A, const spcg_cg_opts *opts);
 
 /*
