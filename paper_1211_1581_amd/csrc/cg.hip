@@ -955,10 +955,12 @@ __device__ __forceinline__ T wg_sum(T v, T *sh16) {
 
 // The whole loop in one 1024-thread workgroup (vectors stay in L2); the
 // state was prepared by k_resid / k_start.  Exits at convergence, maxit or
-// breakdown: every thread evaluates the same stop test on the same sums.
+// breakdown: every thread evaluates the same stop test on the same sums.  The
+// product gives each row a group of L lanes (L a power of two <= 16 near the
+// mean row length) that stride over its entries and add up by group_sum.
 template <int PRE>
 __global__ void __launch_bounds__(kSmallThreads)
-k_cg_small(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+k_cg_small(int n, int L, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
            const double *__restrict__ vals, double *__restrict__ x, double *__restrict__ r,
            double *__restrict__ p, double *__restrict__ q, const double *__restrict__ dinv,
            CgState *st, double *hist) {
@@ -970,14 +972,21 @@ k_cg_small(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ co
     int k = st->k;
     int halt = RUN, status = SPCG_OK;
     double rr = st->rr, alpha = 0.0, beta = 0.0;
+    const int lane = threadIdx.x & (L - 1);
     while (true) {
         double pq = 0.0;
-        for (int i = threadIdx.x; i < n; i += kSmallThreads) {
+        // the row loop's bound is uniform over each group of L lanes
+        for (int i = threadIdx.x / L; i < n; i += kSmallThreads / L) {
             double s = 0.0;
-            for (int e = rp[i]; e < rp[i + 1]; ++e) s += vals[e] * p[col[e]];
-            q[i] = s;
-            pq += p[i] * s;
+            for (int e = rp[i] + lane; e < rp[i + 1]; e += L) s += vals[e] * p[col[e]];
+            s = group_sum(s, L);
+            if (lane == 0) {
+                q[i] = s;
+                pq += p[i] * s;
+            }
         }
+        // wg_sum's barrier also completes q before the update loop reads it
+        // through another thread-to-row mapping
         const double sigma = wg_sum(pq, sh);
         if (!(sigma > 0.0) || !isfinite(sigma)) {
             halt = H_BREAK;
@@ -1799,14 +1808,17 @@ int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o
                 if ((rc = launch_regs(S, pre, d_x))) return rc;
                 if ((rc = S.read_state())) return rc;
             } else if (!mixed && !learned && small_ok(A, o)) {
+                // lanes per row: power-of-two floor of the mean row length, 1..16
+                int L = 1;
+                while (2 * L <= 16 && (int64_t)2 * L * n <= A->nnz) L *= 2;
                 if (pre == SPCG_PRECOND_JACOBI)
                     hipLaunchKernelGGL(k_cg_small<SPCG_PRECOND_JACOBI>, dim3(1),
-                                       dim3(kSmallThreads), 0, s, n, A->row_ptr, A->col,
+                                       dim3(kSmallThreads), 0, s, n, L, A->row_ptr, A->col,
                                        (const double *)A->vals, d_x, w.r, w.p, w.q, w.dinv, w.st,
                                        w.hist);
                 else
                     hipLaunchKernelGGL(k_cg_small<SPCG_PRECOND_NONE>, dim3(1), dim3(kSmallThreads),
-                                       0, s, n, A->row_ptr, A->col, (const double *)A->vals, d_x,
+                                       0, s, n, L, A->row_ptr, A->col, (const double *)A->vals, d_x,
                                        w.r, w.p, w.q, w.dinv, w.st, w.hist);
                 SPCG_LAUNCH_CHECK("k_cg_small");
                 if ((rc = S.read_state())) return rc;
