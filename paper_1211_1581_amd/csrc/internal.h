@@ -413,11 +413,52 @@ __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict
     for (int t = tid + kBlock; t <= nr; t += kBlock) sm.rp[t] = A.row_ptr[r0 + t] - k0;
     __syncthreads();
 
-    // phase 2: L lanes per row, L = pow2 floor of the mean row length (<= 64);
-    // each row's sum is parked in LDS on its first product slot
     const int nrs = long_last ? nr - 1 : nr;        // rows reduced from LDS
     const int cnts = long_last ? sm.rp[nr - 1] : cnt;  // their entries
-    if (nrs > 0) {
+    auto col_at = [&](int k) { return C16 ? r0 + A.off16[k] : A.col[k]; };
+    // the long last row: whole workgroup, strided over global memory; every
+    // thread receives the sum
+    auto long_row = [&]() {
+        const int klast = k0 + sm.rp[nr - 1];
+        TA s0 = TA(0), s1 = TA(0), s2 = TA(0), s3 = TA(0);
+        int k = klast + tid;
+        for (; k + 3 * kBlock < kend; k += 4 * kBlock) {
+            s0 += TA(vals[k]) * TA(x[col_at(k)]);
+            s1 += TA(vals[k + kBlock]) * TA(x[col_at(k + kBlock)]);
+            s2 += TA(vals[k + 2 * kBlock]) * TA(x[col_at(k + 2 * kBlock)]);
+            s3 += TA(vals[k + 3 * kBlock]) * TA(x[col_at(k + 3 * kBlock)]);
+        }
+        for (; k < kend; k += kBlock) s0 += TA(vals[k]) * TA(x[col_at(k)]);
+        return block_sum((s0 + s1) + (s2 + s3), sm.red);
+    };
+    if (nrs == 0 || cnts < 8 * nrs) {
+        // rows of fewer than 8 entries on average: each epilogue thread adds
+        // its row's products straight from the slab (8 independent LDS reads
+        // at clamped indices, then a tail for longer rows), with no separate
+        // row pass and no second barrier
+        const TA slast = long_last ? long_row() : TA(0);
+        for (int t = tid; t < nr; t += kBlock) {
+            TA s = TA(0);
+            if (long_last && t == nr - 1) {
+                s = slast;
+            } else {
+                const int a = sm.rp[t], b = sm.rp[t + 1];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const TA v = sm.slab[max(min(a + j, b - 1), 0)];
+                    s += a + j < b ? v : TA(0);
+                }
+                for (int e = a + 8; e < b; ++e) s += sm.slab[e];
+            }
+            epi.row(r0 + t, s, t == tid ? pre : epi.load(r0 + t));
+        }
+        if (more) __syncthreads();  // the LDS slab is reused by the next row block
+        return;
+    }
+
+    // phase 2: L lanes per row, L = pow2 floor of the mean row length (<= 64);
+    // each row's sum is parked in LDS on its first product slot
+    {
         const int avg = cnts / nrs;
         const int L = avg >= 64 ? 64 : (avg <= 1 ? 1 : (1 << (31 - __clz(avg))));
         const int lane = tid & (L - 1);
@@ -432,19 +473,7 @@ __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict
         }
     }
     if (long_last) {
-        // the long last row: whole workgroup, strided over global memory
-        auto col_at = [&](int k) { return C16 ? r0 + A.off16[k] : A.col[k]; };
-        const int klast = k0 + sm.rp[nr - 1];
-        TA s0 = TA(0), s1 = TA(0), s2 = TA(0), s3 = TA(0);
-        int k = klast + tid;
-        for (; k + 3 * kBlock < kend; k += 4 * kBlock) {
-            s0 += TA(vals[k]) * TA(x[col_at(k)]);
-            s1 += TA(vals[k + kBlock]) * TA(x[col_at(k + kBlock)]);
-            s2 += TA(vals[k + 2 * kBlock]) * TA(x[col_at(k + 2 * kBlock)]);
-            s3 += TA(vals[k + 3 * kBlock]) * TA(x[col_at(k + 3 * kBlock)]);
-        }
-        for (; k < kend; k += kBlock) s0 += TA(vals[k]) * TA(x[col_at(k)]);
-        TA s = block_sum((s0 + s1) + (s2 + s3), sm.red);
+        const TA s = long_row();
         if (tid == 0) sm.last = s;
     }
     __syncthreads();
