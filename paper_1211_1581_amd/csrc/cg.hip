@@ -52,6 +52,11 @@ struct CgState {
     double rho_pp[2];
     float rho32_pp[2];
     int kq, pad;
+    // learned form: constant-offset (DIA) check of G (0) and G^T (1): the
+    // offsets col - row of a probe row, their count, and whether some entry
+    // has another offset
+    int dia_off[2][8];
+    int dia_w[2], dia_bad[2], dia_probe[2];
 };
 
 constexpr int kVecPer = 4;
@@ -82,6 +87,7 @@ __global__ void k_init_state(CgState *st, int maxit, double delta, int budget) {
         s.delta = delta;
         s.budget = budget;
         s.kq = -1;
+        s.dia_probe[0] = s.dia_probe[1] = INT32_MAX;
         *st = s;
     }
 }
@@ -631,6 +637,165 @@ k_g_ell(EllDev G, const double *__restrict__ t, const double *__restrict__ r,
     for (int base = blockIdx.x * kBlock * R; base < G.n; base += gridDim.x * kBlock * R) {
         double sv[R];
         ell_rows_times<W, R, KEEP>(G, t, base, sv);
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int i = base + u * kBlock + threadIdx.x;
+            if (i < G.n) {
+                z[i] = sv[u];
+                acc += r[i] * sv[u];
+            }
+        }
+    }
+    const double v[1] = {acc};
+    store_block_partials(part, blockIdx.x, v, red);
+}
+
+// ------------------------------------- learned: factors as DIA planes --
+//
+// When every entry of a factor lies on one of at most kEllMax diagonals
+// (col - row in a fixed set: the triangles of a stencil matrix), the solve's
+// copy keeps only values, one plane per diagonal in ascending offset order
+// (val[w * n + i] for column i + off[w]; 0 where row i has no such entry).
+// An apply then needs no column loads: each thread requests its rows' values
+// and the gathered x at known addresses together, one round trip per batch.
+struct DiaOff {
+    int o[kEllMax];
+};
+
+// The first row of the longest length becomes the probe row (its offsets are
+// the candidates).  f: 0 for G, 1 for G^T.
+__global__ void __launch_bounds__(kBlock)
+k_dia_probe(int n, const int32_t *__restrict__ rp, int max_len, CgState *st, int f) {
+    __shared__ int first;
+    if (threadIdx.x == 0) first = INT32_MAX;
+    __syncthreads();
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+        if (rp[i + 1] - rp[i] == max_len) {
+            atomicMin(&first, i);
+            break;
+        }
+    __syncthreads();
+    if (threadIdx.x == 0 && first < INT32_MAX) atomicMin(&st->dia_probe[f], first);
+}
+
+// Read the probe row's offsets, then check every entry against them
+__global__ void __launch_bounds__(kBlock)
+k_dia_check(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col, CgState *st,
+            int f) {
+    const int m = min(max(st->dia_probe[f], 0), n - 1);
+    const int a = rp[m], len = rp[m + 1] - a;
+    if (len < 1 || len > kEllMax) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->dia_bad[f] = 1;
+        return;
+    }
+    int off[kEllMax];
+#pragma unroll
+    for (int w = 0; w < kEllMax; ++w) off[w] = w < len ? col[a + w] - m : 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int w = 0; w < len; ++w) st->dia_off[f][w] = off[w];
+        st->dia_w[f] = len;
+    }
+    int bad = 0;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        for (int k = rp[i]; k < rp[i + 1]; ++k) {
+            const int d = col[k] - i;
+            bool found = false;
+#pragma unroll
+            for (int w = 0; w < kEllMax; ++w) found |= w < len && d == off[w];
+            bad |= !found;
+        }
+    }
+    if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(&st->dia_bad[f], 1);
+}
+
+// DIA planes of a factor whose entries all lie on the diagonals off[0..cnt);
+// planes cnt..W are padding (offset 0, value 0)
+template <int W>
+__global__ void __launch_bounds__(kBlock)
+k_to_dia(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+         const float *__restrict__ vals, DiaOff off, int cnt, float *__restrict__ ev) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        float v[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) v[w] = 0.0f;
+        for (int k = rp[i]; k < rp[i + 1]; ++k) {
+            const int d = col[k] - i;
+            bool done = false;  // the first plane with this offset takes the entry
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                if (!done && w < cnt && d == off.o[w]) {
+                    v[w] += vals[k];
+                    done = true;
+                }
+            }
+        }
+#pragma unroll
+        for (int w = 0; w < W; ++w) ev[(size_t)w * n + i] = v[w];
+    }
+}
+
+struct DiaDev {
+    const float *__restrict__ val;
+    DiaOff off;
+    int n;
+};
+
+// Rows base + u kBlock + threadIdx.x (u < R) of a DIA factor times x, each in
+// ascending offset order (FP32 values, FP64 sums); rows past n are clamped
+template <int W, int R, bool KEEP>
+__device__ __forceinline__ void dia_rows_times(const DiaDev &F, const double *__restrict__ x,
+                                               int base, double (&s)[R]) {
+    float v[R][W];
+    double xv[R][W];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+        const int i = min(base + u * kBlock + (int)threadIdx.x, F.n - 1);
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const size_t o = (size_t)w * F.n + i;
+            v[u][w] = KEEP ? F.val[o] : __builtin_nontemporal_load(F.val + o);
+            xv[u][w] = x[min(max(i + F.off.o[w], 0), F.n - 1)];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+        double a = 0.0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) a += (double)v[u][w] * xv[u][w];
+        s[u] = a;
+    }
+}
+
+// t = G^T r  (DIA)
+template <int W, bool KEEP>
+__global__ void __launch_bounds__(kBlock)
+k_gt_dia(DiaDev GT, const double *__restrict__ r, double *__restrict__ t, const CgState *st,
+         int kexp) {
+    constexpr int R = ell_rows<W>();
+    if (st->halt != RUN || (kexp >= 0 && st->k != kexp)) return;
+    for (int base = blockIdx.x * kBlock * R; base < GT.n; base += gridDim.x * kBlock * R) {
+        double sv[R];
+        dia_rows_times<W, R, KEEP>(GT, r, base, sv);
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int i = base + u * kBlock + threadIdx.x;
+            if (i < GT.n) t[i] = sv[u];
+        }
+    }
+}
+
+// z = G t (DIA); partial r.z per workgroup
+template <int W, bool KEEP>
+__global__ void __launch_bounds__(kBlock)
+k_g_dia(DiaDev G, const double *__restrict__ t, const double *__restrict__ r,
+        double *__restrict__ z, const CgState *st, double *part, int kexp) {
+    constexpr int R = ell_rows<W>();
+    __shared__ double red[kWaves];
+    if (st->halt != RUN || (kexp >= 0 && st->k != kexp)) return;
+    double acc = 0.0;
+    for (int base = blockIdx.x * kBlock * R; base < G.n; base += gridDim.x * kBlock * R) {
+        double sv[R];
+        dia_rows_times<W, R, KEEP>(G, t, base, sv);
 #pragma unroll
         for (int u = 0; u < R; ++u) {
             const int i = base + u * kBlock + threadIdx.x;
@@ -1290,13 +1455,19 @@ struct Solver {
     // together, else the two factors alone (measured at 128^3: keeping the
     // factors, 150 MB, beats keeping A).
     bool keep = false, keep_g = false, c16 = false;
+    // learned form: factors as DIA planes (dia) with their offsets and widths
+    bool dia = false;
+    DiaOff dia_g{}, dia_gt{};
+    int wd_g = 0, wd_gt = 0;
     void set_keep() {
         const bool mixed = o->precision == SPCG_PREC_MIXED;
         const int64_t a = mixed ? A->nnz * (c16 ? 6 : 8) + 4 * (int64_t)(A->n_rows + 1)
                                 : matrix_bytes(A->n_rows, A->nnz, 8);
         int64_t f = 0;
         if (o->precond == SPCG_PRECOND_LEARNED) {
-            if (ell_width(o->G) && ell_width(o->GT))  // the ELL copies (8 bytes per slot)
+            if (dia)  // the DIA planes (4 bytes per slot)
+                f = (int64_t)(wd_g + wd_gt) * A->n_rows * 4;
+            else if (ell_width(o->G) && ell_width(o->GT))  // the ELL copies (8 bytes per slot)
                 f = (int64_t)(ell_width(o->G) + ell_width(o->GT)) * A->n_rows * 8;
             else
                 for (const spcg_csr *F : {o->G, o->GT})
@@ -1305,6 +1476,11 @@ struct Solver {
         const int64_t lim = keep_bytes();
         keep = a + f <= lim;
         keep_g = f > 0 && f <= lim;
+        if (dia && !keep && a <= lim) {
+            // DIA applies stream their planes well: keep A instead of them
+            keep = true;
+            keep_g = false;
+        }
     }
     int n_timed = 0;
     int *timed_k = nullptr;
@@ -1381,7 +1557,26 @@ struct Solver {
                            (const double *)w.t, (const double *)w.r, w.z, w.st, w.partg, kexp);
     }
 
+    template <int WG, int WT, bool KEEP>
+    void apply_dia(int kexp) {
+        const DiaDev gt{w.gt_val, dia_gt, A->n_rows}, g{w.g_val, dia_g, A->n_rows};
+        hipLaunchKernelGGL((k_gt_dia<WT, KEEP>), dim3(ell_grid()), dim3(kBlock), 0, s, gt,
+                           (const double *)w.r, w.t, w.st, kexp);
+        hipLaunchKernelGGL((k_g_dia<WG, KEEP>), dim3(ell_grid()), dim3(kBlock), 0, s, g,
+                           (const double *)w.t, (const double *)w.r, w.z, w.st, w.partg, kexp);
+    }
+
     void apply_factor(int kexp) {
+        if (dia) {
+#define SPCG_DIA(WG, WT)                                        \
+    if (wd_g == WG && wd_gt == WT) {                            \
+        if (keep_g) apply_dia<WG, WT, true>(kexp);              \
+        else apply_dia<WG, WT, false>(kexp);                    \
+        return;                                                 \
+    }
+            SPCG_DIA(4, 4) SPCG_DIA(4, 8) SPCG_DIA(8, 4) SPCG_DIA(8, 8)
+#undef SPCG_DIA
+        }
         if (w.w_g) {
 #define SPCG_ELL(WG, WT)                                        \
     if (w.w_g == WG && w.w_gt == WT) {                          \
@@ -1767,13 +1962,12 @@ int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o
         SPCG_LAUNCH_CHECK("k_copy");
         for (int f = 0; f < 2 && w.w_g; ++f) {
             const spcg_csr *F = f ? o->GT : o->G;
-            const int wd = f ? w.w_gt : w.w_g;
-            int32_t *ec = f ? w.gt_col : w.g_col;
-            float *ev = f ? w.gt_val : w.g_val;
-            auto kern = wd == 4 ? k_to_ell<4> : k_to_ell<kEllMax>;
-            hipLaunchKernelGGL(kern, dim3(std::min<unsigned>(grid_of(n, kBlock), 4096)), dim3(kBlock),
-                               0, s, n, F->row_ptr, F->col, (const float *)F->vals, ec, ev);
-            SPCG_LAUNCH_CHECK("k_to_ell");
+            const unsigned grid = std::min<unsigned>(grid_of(n, kBlock), 4096);
+            hipLaunchKernelGGL(k_dia_probe, dim3(grid), dim3(kBlock), 0, s, n, F->row_ptr,
+                               (int)F->max_len, w.st, f);
+            hipLaunchKernelGGL(k_dia_check, dim3(grid), dim3(kBlock), 0, s, n, F->row_ptr, F->col,
+                               w.st, f);
+            SPCG_LAUNCH_CHECK("k_dia_check");
         }
     }
     if ((rc = S.resid(R_INIT, mixed ? w.r32 : nullptr))) return rc;
@@ -1781,6 +1975,36 @@ int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o
     CgState *h = S.h;
     if (mixed && A->n_blocks > 0 && !h->c16_bad) {
         S.c16 = true;
+        S.set_keep();
+    }
+    if (learned && w.w_g) {
+        // the solve's copies of G and G^T: DIA planes when both lie on a few
+        // diagonals, else padded ELL planes
+        S.dia = !h->dia_bad[0] && !h->dia_bad[1];
+        for (int f = 0; f < 2; ++f) {
+            const spcg_csr *F = f ? o->GT : o->G;
+            float *ev = f ? w.gt_val : w.g_val;
+            const unsigned grid = std::min<unsigned>(grid_of(n, kBlock), 4096);
+            if (S.dia) {
+                DiaOff off{};
+                const int cnt = h->dia_w[f];
+                for (int j = 0; j < cnt; ++j) off.o[j] = h->dia_off[f][j];
+                const int wd = cnt <= 4 ? 4 : kEllMax;
+                (f ? S.dia_gt : S.dia_g) = off;
+                (f ? S.wd_gt : S.wd_g) = wd;
+                auto kern = wd == 4 ? k_to_dia<4> : k_to_dia<kEllMax>;
+                hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, n, F->row_ptr, F->col,
+                                   (const float *)F->vals, off, cnt, ev);
+                SPCG_LAUNCH_CHECK("k_to_dia");
+            } else {
+                const int wd = f ? w.w_gt : w.w_g;
+                int32_t *ec = f ? w.gt_col : w.g_col;
+                auto kern = wd == 4 ? k_to_ell<4> : k_to_ell<kEllMax>;
+                hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, n, F->row_ptr, F->col,
+                                   (const float *)F->vals, ec, ev);
+                SPCG_LAUNCH_CHECK("k_to_ell");
+            }
+        }
         S.set_keep();
     }
     if (h->bad_diag) return (h->bad_diag & 2) ? SPCG_NON_FINITE : SPCG_NOT_SPD;

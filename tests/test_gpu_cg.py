@@ -115,13 +115,33 @@ def test_learned_form_with_jacobi_factor():
     assert fo["status"] == oracle.FELL_BACK and within(f["iters_fallback"], fo["iters_fallback"])
 
 
-@pytest.mark.parametrize("case", ["banded", "poisson2d", "wide"])
+def _irregular_spd(n, seed):
+    # each row i couples to 3 distinct random earlier rows (so tril rows hold at
+    # most 4 entries on no fixed set of diagonals); strictly diagonally dominant
+    rng = np.random.default_rng(seed)
+    pairs = []
+    for i in range(1, n):
+        js = rng.choice(i, size=min(3, i), replace=False)
+        pairs += [(i, j) for j in js]
+    i_, j_ = np.array(pairs).T
+    w = -rng.uniform(0.1, 1.0, len(pairs))
+    import scipy.sparse as sp
+    B = sp.coo_matrix((w, (i_, j_)), shape=(n, n))
+    M = (B + B.T).tocsr()
+    d = np.asarray(abs(M).sum(axis=1)).ravel() + 1.0
+    M = (M + sp.diags(d)).tocsr()
+    M.sort_indices()
+    return I.CSR(n, n, M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data.astype(np.float64))
+
+
+@pytest.mark.parametrize("case", ["banded", "poisson2d", "wide", "irregular"])
 def test_learned_form_general_factor(case):
-    # a factor with off-diagonal values: rows of up to 5 entries (ELL copies
-    # padded to 8), at most 3 (padded to 4), or 10 (more than the ELL copies
-    # take: the CSR row-block apply kernels)
+    # a factor with off-diagonal values: on 5 diagonals (DIA planes padded to
+    # 8), on 3 diagonals (DIA, 4), rows of 10 entries (more than the solve's
+    # copies take: the CSR row-block apply kernels), or at most 4 entries on
+    # no fixed diagonals (padded ELL planes)
     A = {"banded": lambda: I.banded_spd(3000, 9), "poisson2d": lambda: I.poisson2d(60),
-         "wide": lambda: I.banded_spd(3000, 19)}[case]()
+         "wide": lambda: I.banded_spd(3000, 19), "irregular": lambda: _irregular_spd(3000, 5)}[case]()
     b = I.rhs_from_solution(A, I.uniform_vector(A.n_rows, 4))
     Lh, _ = lower_upper(A)
     rng = np.random.default_rng(9)
@@ -133,7 +153,7 @@ def test_learned_form_general_factor(case):
     S = spcg()
     G = S.CsrMatrix.from_host(Lh2, dtype=torch.float32)
     GT = S.CsrMatrix.from_host(Uh2, dtype=torch.float32)
-    assert G.info()["max_row_len"] == {"banded": 5, "poisson2d": 3, "wide": 10}[case]
+    assert G.info()["max_row_len"] == {"banded": 5, "poisson2d": 3, "wide": 10, "irregular": 4}[case]
     M = S.CsrMatrix.from_host(A)
     ref = oracle.pcg(A, b, tol=1e-10, maxit=5000, precond="g", G=Lh2)
     g = S.cg_solve(M, to_dev(b), tol=1e-10, maxit=5000, precond="learned", G=G, GT=GT)
