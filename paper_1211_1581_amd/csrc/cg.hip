@@ -666,16 +666,30 @@ struct DiaOff {
 // the candidates).  f: 0 for G, 1 for G^T.
 __global__ void __launch_bounds__(kBlock)
 k_dia_probe(int n, const int32_t *__restrict__ rp, int max_len, CgState *st, int f) {
-    __shared__ int first;
-    if (threadIdx.x == 0) first = INT32_MAX;
-    __syncthreads();
+    __shared__ int wmin[kWaves];
+    int first = INT32_MAX;  // this thread's first row of the longest length
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
         if (rp[i + 1] - rp[i] == max_len) {
-            atomicMin(&first, i);
+            first = i;
             break;
         }
+    // workgroup minimum: DPP inside rows of 16, then the row minima
+    first = min(first, dpp_mov<kDppXor1>(first));
+    first = min(first, dpp_mov<kDppXor2>(first));
+    first = min(first, dpp_mov<kDppHalfMirror>(first));
+    first = min(first, dpp_mov<kDppMirror>(first));
+    first = min(min(lane_value(first, 0), lane_value(first, 16)),
+                min(lane_value(first, 32), lane_value(first, 48)));
+    if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = first;
     __syncthreads();
-    if (threadIdx.x == 0 && first < INT32_MAX) atomicMin(&st->dia_probe[f], first);
+    if (threadIdx.x == 0) {
+        int m = wmin[0];
+        for (int w = 1; w < kWaves; ++w) m = min(m, wmin[w]);
+        // most workgroups hold no smaller row than one already recorded: a
+        // plain read first keeps the atomics (which serialise) few
+        const int cur = __hip_atomic_load(&st->dia_probe[f], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (m < cur) atomicMin(&st->dia_probe[f], m);
+    }
 }
 
 // Read the probe row's offsets, then check every entry against them
