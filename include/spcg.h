@@ -7,8 +7,9 @@
  *   - the conjugate-gradient solver for SPD systems (Sec. 3.4, Fig. 6 and the
  *     loop that follows it: one SpMV, two inner products, three vector updates
  *     per pass).
- * Beyond the paper: Jacobi and learned (M^-1 = G G^T) preconditioning, and an
- * FP32-inner / FP64-outer mixed-precision solver.
+ * Beyond the paper: Jacobi, learned (M^-1 = G G^T, the network that predicts
+ * G) and FSAI preconditioning, an FP32-inner / FP64-outer mixed-precision
+ * solver, and the single-reduction (Chronopoulos-Gear) form of the loop.
  *
  * Conventions for every call:
  *   - Pointers prefixed d_ are device pointers (HBM of the current device),
