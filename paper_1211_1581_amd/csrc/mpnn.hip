@@ -407,6 +407,7 @@ __global__ void __launch_bounds__(256) k_node_fwd(int n, const int32_t *__restri
                                                   const LayerBf *__restrict__ B,
                                                   const float *__restrict__ Lw) {
     __shared__ __bf16 lds[kWavesPerWg][32 * 40];
+    __shared__ float Dl[kWavesPerWg][32 * 33];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     __bf16 *T = lds[wv];
     bf16x8 w1[4], w2[2];
@@ -444,15 +445,31 @@ __global__ void __launch_bounds__(256) k_node_fwd(int n, const int32_t *__restri
         f32x16 d = splat16(b2);
 #pragma unroll
         for (int c = 0; c < 2; ++c) d = mfma32(frag(T, 40, c), w2[c], d);
-        wave_lds_sync();
+        // the update goes out through LDS (FP32, so the residual sum is the
+        // same): each lane adds 16 consecutive values of one row to h and
+        // writes them with two 16-byte stores
+        float *D = Dl[wv];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int r = tile * 32 + acc_row(q, lane);
+        for (int q = 0; q < 16; ++q) D[acc_row(q, lane) * 33 + (lane & 31)] = d[q];
+        wave_lds_sync();
+        {
+            const int rr = lane >> 1, half = lane & 1;
+            const int r = tile * 32 + rr;
             if (r < n) {
-                const size_t o = (size_t)r * H + (lane & 31);
-                hout[o] = (__bf16)((float)hin[o] + d[q]);
+                const size_t o = (size_t)r * H + 16 * half;
+                const bf16x8 h0 = *reinterpret_cast<const bf16x8 *>(hin + o);
+                const bf16x8 h1 = *reinterpret_cast<const bf16x8 *>(hin + o + 8);
+                bf16x8 u0, u1;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    u0[k] = (__bf16)((float)h0[k] + D[rr * 33 + 16 * half + k]);
+                    u1[k] = (__bf16)((float)h1[k] + D[rr * 33 + 16 * half + 8 + k]);
+                }
+                *reinterpret_cast<bf16x8 *>(hout + o) = u0;
+                *reinterpret_cast<bf16x8 *>(hout + o + 8) = u1;
             }
         }
+        wave_lds_sync();
     }
 }
 
