@@ -27,7 +27,7 @@ def within(k_gpu, k_or, frac=0.02, extra=2):
 
 
 @pytest.mark.parametrize("small", [True, False])
-def test_cfg1_plain_cg(small):
+def test_poisson2d_64_plain_cg(small):
     A = I.poisson2d(64)
     xs = I.uniform_vector(A.n_rows, 0)
     b = I.rhs_from_solution(A, xs)
@@ -54,7 +54,7 @@ def test_jacobi_pcg_fv(N, seed):
         assert np.allclose(g["hist"][:40], ref["hist"][:40], rtol=1e-6)
 
 
-def test_cfg2_full_size_jpcg():
+def test_poisson3d_128_full_size_jpcg():
     A = I.poisson3d(128)
     xs = I.uniform_vector(A.n_rows, 1)
     b = I.rhs_from_solution(A, xs)

@@ -156,20 +156,20 @@ def test_many_empty_rows_several_blocks_per_workgroup():
 
 
 @pytest.fixture(scope="module")
-def cfg3():
+def lognormal_200k():
     return I.lognormal_irregular()
 
 
-def test_full_size_lognormal_f64(cfg3):
-    A, x = cfg3
+def test_full_size_lognormal_f64(lognormal_200k):
+    A, x = lognormal_200k
     assert A.nnz == 15_788_355
     y, M = run(A, x)
     check_f64(y, oracle.spmv(A, x), A, x, "lognormal f64")
     assert M.info()["max_row_len"] == 4096
 
 
-def test_full_size_lognormal_f32(cfg3):
-    A, x = cfg3
+def test_full_size_lognormal_f32(lognormal_200k):
+    A, x = lognormal_200k
     y, _ = run(A, x, torch.float32)
     ref = f32_check(A, x, y)
     # report-only: error against the FP64 product of the unrounded inputs

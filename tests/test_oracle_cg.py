@@ -45,7 +45,7 @@ def test_tiny_spd_vs_direct(precond, seed):
     assert r["true_relres"] <= 1e-13
 
 
-def test_cfg1_poisson2d_manufactured():
+def test_poisson2d_64_manufactured():
     A = I.poisson2d(64)
     xs = I.uniform_vector(A.n_rows, 0)
     b = I.rhs_from_solution(A, xs)
