@@ -363,16 +363,41 @@ __global__ void __launch_bounds__(256) k_edge_fwd(int E, const int32_t *__restri
     const float b1 = Lw[E1B + (lane & 31)], b2 = Lw[E2B + (lane & 31)];
     const int ntiles = (E + 31) / 32;
     const int hh = lane >> 5;
-    for (int tile = blockIdx.x * kWavesPerWg + wv; tile < ntiles; tile += gridDim.x * kWavesPerWg) {
-        const int e = min(tile * 32 + (lane & 31), E - 1);
-        const int i = erow[e], j = ecol[e];
+    const int stride = gridDim.x * kWavesPerWg;
+    // Software pipeline, one tile deep: each pass issues the next tile's
+    // input gathers and the endpoints of the tile after it, then runs this
+    // tile's products on inputs gathered one pass earlier.
+    auto ends = [&](int t, int &i, int &j) {
+        const int e = min(t * 32 + (lane & 31), E - 1);
+        i = erow[e];
+        j = ecol[e];
+    };
+    auto gather = [&](int t, int i, int j, bf16x8 (&a)[6]) {
+        const int e = min(t * 32 + (lane & 31), E - 1);
         const __bf16 *src[3] = {hin + (size_t)i * H, hin + (size_t)j * H, ein + (size_t)e * H};
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+            a[c] = *reinterpret_cast<const bf16x8 *>(src[c >> 1] + 16 * (c & 1) + 8 * hh);
+    };
+    int tile = blockIdx.x * kWavesPerWg + wv;
+    bf16x8 a[6];
+    int i_nx = 0, j_nx = 0;
+    if (tile < ntiles) {
+        int i0, j0;
+        ends(tile, i0, j0);
+        gather(tile, i0, j0, a);
+        if (tile + stride < ntiles) ends(tile + stride, i_nx, j_nx);
+    }
+    for (; tile < ntiles; tile += stride) {
+        bf16x8 a_nx[6];
+        const int t1 = tile + stride;
+        if (t1 < ntiles) {
+            gather(t1, i_nx, j_nx, a_nx);
+            if (t1 + stride < ntiles) ends(t1 + stride, i_nx, j_nx);
+        }
         f32x16 z = splat16(b1);
 #pragma unroll
-        for (int c = 0; c < 6; ++c) {
-            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(src[c >> 1] + 16 * (c & 1) + 8 * hh);
-            z = mfma32(a, w1[c], z);
-        }
+        for (int c = 0; c < 6; ++c) z = mfma32(a[c], w1[c], z);
 #pragma unroll
         for (int q = 0; q < 16; ++q) z[q] = silu(z[q]);
         acc_to_lds(z, T, 40, false);
@@ -396,6 +421,8 @@ __global__ void __launch_bounds__(256) k_edge_fwd(int E, const int32_t *__restri
             }
         }
         wave_lds_sync();
+#pragma unroll
+        for (int c = 0; c < 6; ++c) a[c] = a_nx[c];
     }
 }
 
@@ -972,7 +999,7 @@ unsigned tile_wgs(int64_t items, int cap) {
     const int64_t tiles = (items + 31) / 32;
     return (unsigned)std::max<int64_t>(std::min<int64_t>((tiles + kWavesPerWg - 1) / kWavesPerWg, cap), 1);
 }
-constexpr int kFwdCap = 2048, kBwdCap = 256, kSmallCap = 512, kMaxProbes = 64;
+constexpr int kFwdCap = 2048, kEdgeCap = 768, kBwdCap = 256, kSmallCap = 512, kMaxProbes = 64;
 
 __bf16 *hbuf(const spcg_mpnn_ws *w, int l) { return w->train ? w->h[l] : w->h[l & 1]; }
 __bf16 *ebuf(const spcg_mpnn_ws *w, int l) { return w->train ? w->e[l] : w->e[l & 1]; }
@@ -988,7 +1015,7 @@ int forward(spcg_mpnn *g, spcg_mpnn_ws *ws, const float *w, hipStream_t s) {
     for (int l = 1; l <= NL; ++l) {
         const float *Lw = w + L0 + (l - 1) * LSZ;
         if (g->E > 0)
-            hipLaunchKernelGGL(k_edge_fwd, dim3(tile_wgs(g->E, kFwdCap)), dim3(256), 0, s, g->E,
+            hipLaunchKernelGGL(k_edge_fwd, dim3(tile_wgs(g->E, kEdgeCap)), dim3(256), 0, s, g->E,
                                g->erow, g->ecol, hbuf(ws, l - 1), ebuf(ws, l - 1), ebuf(ws, l),
                                ws->wbf + (l - 1), Lw);
         hipLaunchKernelGGL(k_node_fwd, dim3(tile_wgs(g->n, kFwdCap)), dim3(256), 0, s, g->n,
