@@ -994,7 +994,10 @@ int release_ws(spcg_mpnn_ws *w) {
 
 unsigned g1(int64_t n, int per = 256) { return (unsigned)std::max<int64_t>((n + per - 1) / per, 1); }
 
-// workgroups of the tile kernels: forward, and backward (bounded: per-wave partials)
+// workgroups of the tile kernels: forward, and backward (bounded: per-wave partials).
+// The edge forward kernel holds 148 registers per lane (3 wavefronts per SIMD),
+// so 768 = 256 CUs x 3 workgroups of 4 wavefronts is the resident grid: one
+// generation of workgroups, no tail.
 unsigned tile_wgs(int64_t items, int cap) {
     const int64_t tiles = (items + 31) / 32;
     return (unsigned)std::max<int64_t>(std::min<int64_t>((tiles + kWavesPerWg - 1) / kWavesPerWg, cap), 1);
