@@ -327,6 +327,13 @@ __global__ void k_prep_weights(const float *__restrict__ w, LayerBf *wb) {
 
 // ---------------------------------------------------------- encoders --
 
+// encoded edge state, one output: the 2 -> 32 linear map of the edge features,
+// rounded once to BF16 (the encoder and the fused first edge layer both use it,
+// so the two round identically)
+__device__ __forceinline__ __bf16 edge_code(float wg0, float wg1, float b, float g0, float g1) {
+    return (__bf16)__fmaf_rn(wg1, g1, __fmaf_rn(wg0, g0, b));
+}
+
 __global__ void k_encode(int n, int E, const float *__restrict__ w, const float *__restrict__ fe,
                          const float *__restrict__ ge, __bf16 *h0, __bf16 *e0) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -338,21 +345,34 @@ __global__ void k_encode(int n, int E, const float *__restrict__ w, const float 
     if (t < E) {
         const float g0 = ge[2 * t], g1 = ge[2 * t + 1];
         for (int o = 0; o < H; ++o)
-            e0[(size_t)t * H + o] = (__bf16)(w[EEW + 2 * o] * g0 + w[EEW + 2 * o + 1] * g1 + w[EEB + o]);
+            e0[(size_t)t * H + o] = edge_code(w[EEW + 2 * o], w[EEW + 2 * o + 1], w[EEB + o], g0, g1);
     }
 }
 
 // ----------------------------------------------------- layer forward --
 
-// Edge MLP of one layer: m = W2e silu(W1e [h_i; h_j; e] + c1e) + c2e
+// Edge MLP of one layer: m = W2e silu(W1e [h_i; h_j; e] + c1e) + c2e.
+// ENC: first layer without a stored edge state; e is encoded from the two edge
+// features (weights w) as the fragments are formed.
+template <bool ENC>
 __global__ void __launch_bounds__(256) k_edge_fwd(int E, const int32_t *__restrict__ erow,
                                                   const int32_t *__restrict__ ecol,
                                                   const __bf16 *__restrict__ hin,
                                                   const __bf16 *__restrict__ ein,
+                                                  const float *__restrict__ ge,
+                                                  const float *__restrict__ w,
                                                   __bf16 *__restrict__ eout,
                                                   const LayerBf *__restrict__ B,
                                                   const float *__restrict__ Lw) {
     __shared__ __bf16 lds[kWavesPerWg][32 * 40];
+    __shared__ float4 encw[H];
+    if constexpr (ENC) {
+        if (threadIdx.x < H) {
+            const int o = threadIdx.x;
+            encw[o] = make_float4(w[EEW + 2 * o], w[EEW + 2 * o + 1], w[EEB + o], 0.0f);
+        }
+        __syncthreads();
+    }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     __bf16 *T = lds[wv];
     bf16x8 w1[6], w2[2];
@@ -372,28 +392,41 @@ __global__ void __launch_bounds__(256) k_edge_fwd(int E, const int32_t *__restri
         i = erow[e];
         j = ecol[e];
     };
-    auto gather = [&](int t, int i, int j, bf16x8 (&a)[6]) {
+    constexpr int NF = ENC ? 4 : 6;  // fragments gathered from memory
+    auto gather = [&](int t, int i, int j, bf16x8 (&a)[6], float2 &gf) {
         const int e = min(t * 32 + (lane & 31), E - 1);
         const __bf16 *src[3] = {hin + (size_t)i * H, hin + (size_t)j * H, ein + (size_t)e * H};
 #pragma unroll
-        for (int c = 0; c < 6; ++c)
+        for (int c = 0; c < NF; ++c)
             a[c] = *reinterpret_cast<const bf16x8 *>(src[c >> 1] + 16 * (c & 1) + 8 * hh);
+        if constexpr (ENC) gf = make_float2(ge[2 * e], ge[2 * e + 1]);
     };
     int tile = blockIdx.x * kWavesPerWg + wv;
     bf16x8 a[6];
+    float2 gf = make_float2(0.0f, 0.0f);
     int i_nx = 0, j_nx = 0;
     if (tile < ntiles) {
         int i0, j0;
         ends(tile, i0, j0);
-        gather(tile, i0, j0, a);
+        gather(tile, i0, j0, a, gf);
         if (tile + stride < ntiles) ends(tile + stride, i_nx, j_nx);
     }
     for (; tile < ntiles; tile += stride) {
         bf16x8 a_nx[6];
+        float2 gf_nx = make_float2(0.0f, 0.0f);
         const int t1 = tile + stride;
         if (t1 < ntiles) {
-            gather(t1, i_nx, j_nx, a_nx);
+            gather(t1, i_nx, j_nx, a_nx, gf_nx);
             if (t1 + stride < ntiles) ends(t1 + stride, i_nx, j_nx);
+        }
+        if constexpr (ENC) {
+#pragma unroll
+            for (int c = 4; c < 6; ++c)
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const float4 q = encw[16 * (c & 1) + 8 * hh + k];
+                    a[c][k] = edge_code(q.x, q.y, q.z, gf.x, gf.y);
+                }
         }
         f32x16 z = splat16(b1);
 #pragma unroll
@@ -422,7 +455,8 @@ __global__ void __launch_bounds__(256) k_edge_fwd(int E, const int32_t *__restri
         }
         wave_lds_sync();
 #pragma unroll
-        for (int c = 0; c < 6; ++c) a[c] = a_nx[c];
+        for (int c = 0; c < NF; ++c) a[c] = a_nx[c];
+        gf = gf_nx;
     }
 }
 
@@ -1013,14 +1047,25 @@ bool fits(const spcg_mpnn *g, const spcg_mpnn_ws *w) {
 
 int forward(spcg_mpnn *g, spcg_mpnn_ws *ws, const float *w, hipStream_t s) {
     hipLaunchKernelGGL(k_prep_weights, dim3(NL), dim3(256), 0, s, w, ws->wbf);
-    hipLaunchKernelGGL(k_encode, dim3(g1(std::max(g->n, g->E))), dim3(256), 0, s, g->n, g->E, w,
-                       (const float *)g->fe, (const float *)g->ge, hbuf(ws, 0), ebuf(ws, 0));
+    // Without training the encoded edge state is never stored: the first edge
+    // layer forms it from the edge features. Training keeps it for the backward pass.
+    const bool fuse = !ws->train;
+    const int64_t E_enc = fuse ? 0 : g->E;
+    hipLaunchKernelGGL(k_encode, dim3(g1(std::max<int64_t>(g->n, E_enc))), dim3(256), 0, s, g->n, (int)E_enc,
+                       w, (const float *)g->fe, (const float *)g->ge, hbuf(ws, 0), ebuf(ws, 0));
     for (int l = 1; l <= NL; ++l) {
         const float *Lw = w + L0 + (l - 1) * LSZ;
-        if (g->E > 0)
-            hipLaunchKernelGGL(k_edge_fwd, dim3(tile_wgs(g->E, kEdgeCap)), dim3(256), 0, s, g->E,
-                               g->erow, g->ecol, hbuf(ws, l - 1), ebuf(ws, l - 1), ebuf(ws, l),
-                               ws->wbf + (l - 1), Lw);
+        if (g->E > 0) {
+            const dim3 grid(tile_wgs(g->E, kEdgeCap));
+            if (l == 1 && fuse)
+                hipLaunchKernelGGL(k_edge_fwd<true>, grid, dim3(256), 0, s, g->E, g->erow, g->ecol,
+                                   hbuf(ws, 0), (const __bf16 *)nullptr, (const float *)g->ge, w,
+                                   ebuf(ws, 1), ws->wbf, Lw);
+            else
+                hipLaunchKernelGGL(k_edge_fwd<false>, grid, dim3(256), 0, s, g->E, g->erow, g->ecol,
+                                   hbuf(ws, l - 1), ebuf(ws, l - 1), (const float *)nullptr, w,
+                                   ebuf(ws, l), ws->wbf + (l - 1), Lw);
+        }
         hipLaunchKernelGGL(k_node_fwd, dim3(tile_wgs(g->n, kFwdCap)), dim3(256), 0, s, g->n,
                            g->eptr, hbuf(ws, l - 1), ebuf(ws, l), hbuf(ws, l), ws->wbf + (l - 1), Lw);
     }
