@@ -200,7 +200,7 @@ __global__ void __launch_bounds__(256) k_scan_apply(int n, const int32_t *__rest
     sh[threadIdx.x] = s;
     __syncthreads();
     for (int o = 1; o < 256; o <<= 1) {
-        const int32_t v = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+        const int32_t v = (int)threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
         __syncthreads();
         sh[threadIdx.x] += v;
         __syncthreads();
