@@ -85,6 +85,22 @@ def test_forward_matches_oracle(N, seed):
     assert cos(gv, ref) >= 0.9999 and rel(gv, ref) <= 2e-2, (cos(gv, ref), rel(gv, ref))
 
 
+@pytest.mark.parametrize("N,seed", [(12, 2), (31, 5)])
+def test_inference_forward_equals_training_forward(N, seed):
+    """Without training the first edge layer encodes the edge state itself; with
+    training the encoder stores it. Both round each encoded value once to BF16
+    from the same FP32 operations, so the two factors agree bit for bit."""
+    A, _, _ = I.fv_diffusion(N, seed, corr_len=2.0)
+    w = torch.tensor(mpnn.flatten(weights(seed)), dtype=torch.float32, device="cuda")
+    _, gi = graph(A)
+    _, gt = graph(A, train=True)
+    gi.predict(w)
+    gt.predict(w)
+    _, _, gv_i, gtv_i = gi.factor_arrays()
+    _, _, gv_t, gtv_t = gt.factor_arrays()
+    assert np.array_equal(gv_i, gv_t) and np.array_equal(gtv_i, gtv_t)
+
+
 # N = 21: 62 181 edges, 1944 tiles with a ragged last one, more than the
 # backward kernels' wavefronts, so their loops and per-wave partials cover
 # several tiles each
