@@ -44,9 +44,10 @@ def spmv_bytes(n, nnz, sv=8, sx=8):
 
 
 def jpcg_pass_bytes(n, nnz):
-    """FP64 Jacobi-PCG pass: SpMV + 88 n (x, p, r, q, dinv read and x, r
-    written by the update; r, dinv, p read and p written by the direction)."""
-    return spmv_bytes(n, nnz) + 88 * n
+    """FP64 Jacobi-PCG pass: SpMV + 80 n (r, q, dinv read and r written by the
+    residual update; r, dinv, p, x read and p, x written by the direction
+    update, which also does x += alpha p)."""
+    return spmv_bytes(n, nnz) + 80 * n
 
 
 # sources of the CG pass kernels (k_cg_q and the kernels around it)

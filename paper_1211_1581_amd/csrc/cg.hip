@@ -293,12 +293,14 @@ k_fin_q(CgState *st, const T *part, int nslots, int expect) {
     if (PP) st->kq = expect;
 }
 
-// K2: x += alpha p, r -= alpha q, z = M^-1 r; partials (r.z, r.r).
-// PRE = LEARNED: r.r only (z comes from two SpMVs).  T = float: mixed inner.
+// K2: r -= alpha q, z = M^-1 r; partials (r.z, r.r).  x += alpha p is done by
+// the pass end (K3F, K3L), which reads p anyway, so this kernel reads neither
+// x nor p.  PRE = LEARNED: r.r only (z comes from two SpMVs).  T = float: mixed
+// inner.
 template <typename T, int PRE>
 __global__ void __launch_bounds__(kBlock)
-k_cg_xr(int n, int expect, T *__restrict__ x, T *__restrict__ r, const T *__restrict__ p,
-        const T *__restrict__ q, const T *__restrict__ dinv, const CgState *st, T *part) {
+k_cg_xr(int n, int expect, T *__restrict__ r, const T *__restrict__ q, const T *__restrict__ dinv,
+        const CgState *st, T *part) {
     __shared__ T red[kWaves * 2];
     if (st->halt != RUN || st->k != expect) return;
     const T alpha = st_alpha<T>(st);
@@ -309,10 +311,9 @@ k_cg_xr(int n, int expect, T *__restrict__ x, T *__restrict__ r, const T *__rest
         for (int u = 0; u < kVecPer; ++u) {
             const int i = base + u * kBlock;
             if (i < n) {
-                // x and q are not read again before they are next written:
-                // non-temporal accesses leave the MALL to the matrix and to
-                // the vectors that are
-                __builtin_nontemporal_store(__builtin_nontemporal_load(x + i) + alpha * p[i], x + i);
+                // q is not read again before it is next written: a
+                // non-temporal load leaves the MALL to the matrix and to the
+                // vectors that are
                 const T ri = r[i] - alpha * __builtin_nontemporal_load(q + i);
                 r[i] = ri;
                 if constexpr (PRE == SPCG_PRECOND_JACOBI) rz += ri * (dinv[i] * ri);
@@ -380,25 +381,29 @@ constexpr int kApplyGrid = 4096;
 // same rho' and ||r||^2 and take the same stop decision; unless the pass ends
 // the loop (converged, out of passes, breakdown) they update p.  Workgroup 0
 // records the pass: count, history, rho' (into the other parity slot), beta,
-// decision.  The gate is kq (F1 of this pass ran), which those writes do not
-// touch.  T = float: the mixed inner loop (replacement instead of stop).
+// decision.  The gate is kq (F1 of this pass ran, and so K2), which those
+// writes do not touch.  x += alpha p of the pass is done here for every pass
+// K2 ran, also one that ends the loop, so K2 reads neither x nor p.
+// T = float: the mixed inner loop (replacement instead of stop).
 template <typename T, int PRE, bool MIXED>
 __global__ void __launch_bounds__(kBlock)
 k_cg_pf(int n, int expect, const T *__restrict__ r, const T *__restrict__ dinv,
-        T *__restrict__ p, CgState *st, const T *__restrict__ part, int nslots,
+        T *__restrict__ p, T *__restrict__ x, CgState *st, const T *__restrict__ part, int nslots,
         double *__restrict__ hist) {
     __shared__ T sh[kWaves * 2];
     if (st->kq != expect) return;
+    const T alpha = st_alpha<T>(st);  // set by F1 of this pass; not written below
     // the first tile's operands are requested before the partials are summed
     const int tid = threadIdx.x;
     int tile = blockIdx.x;
-    T rv[kVecPer], dv[kVecPer], pv[kVecPer];
+    T rv[kVecPer], dv[kVecPer], pv[kVecPer], xv[kVecPer];
 #pragma unroll
     for (int u = 0; u < kVecPer; ++u) {
         const int i = min(tile * kVecBlock + tid + u * kBlock, n - 1);
         rv[u] = r[i];
         dv[u] = PRE == SPCG_PRECOND_JACOBI ? dinv[i] : T(1);
         pv[u] = p[i];
+        xv[u] = __builtin_nontemporal_load(x + i);
     }
     T t0, t1;
     wg_totals<2, 0, 2, 1>(part, nslots, part, nslots, t0, t1, sh);
@@ -447,14 +452,16 @@ k_cg_pf(int n, int expect, const T *__restrict__ r, const T *__restrict__ dinv,
             if (halt != RUN) st->halt = halt;
         }
     }
-    if (brk || (halt != RUN && halt != H_REPLACE)) return;
+    // p is left as it is when the pass ends the loop; x is always updated
+    const bool upd_p = !(brk || (halt != RUN && halt != H_REPLACE));
     for (;;) {
 #pragma unroll
         for (int u = 0; u < kVecPer; ++u) {
             const int i = tile * kVecBlock + tid + u * kBlock;
             if (i < n) {
+                __builtin_nontemporal_store(xv[u] + alpha * pv[u], x + i);
                 const T zi = PRE == SPCG_PRECOND_JACOBI ? dv[u] * rv[u] : rv[u];
-                p[i] = zi + beta * pv[u];
+                if (upd_p) p[i] = zi + beta * pv[u];
             }
         }
         tile += gridDim.x;
@@ -465,6 +472,7 @@ k_cg_pf(int n, int expect, const T *__restrict__ r, const T *__restrict__ dinv,
             rv[u] = r[i];
             dv[u] = PRE == SPCG_PRECOND_JACOBI ? dinv[i] : T(1);
             pv[u] = p[i];
+            xv[u] = __builtin_nontemporal_load(x + i);
         }
     }
 }
@@ -829,19 +837,21 @@ k_g_dia(DiaDev G, const double *__restrict__ t, const double *__restrict__ r,
 // learned pass (converged, out of passes, budget used up, breakdown) and
 // updates p unless the pass ends the loop; workgroup 0 records the pass.
 __global__ void __launch_bounds__(kBlock)
-k_cg_pl(int n, int expect, const double *__restrict__ z, double *__restrict__ p, CgState *st,
-        const double *__restrict__ part_xr, int n_xr, const double *__restrict__ part_g, int n_g,
-        double *__restrict__ hist) {
+k_cg_pl(int n, int expect, const double *__restrict__ z, double *__restrict__ p,
+        double *__restrict__ x, CgState *st, const double *__restrict__ part_xr, int n_xr,
+        const double *__restrict__ part_g, int n_g, double *__restrict__ hist) {
     __shared__ double sh[kWaves * 2];
     if (st->kq != expect) return;
+    const double alpha = st->alpha;  // set by F1 of this pass; not written below
     const int tid = threadIdx.x;
     int tile = blockIdx.x;
-    double zv[kVecPer], pv[kVecPer];
+    double zv[kVecPer], pv[kVecPer], xv[kVecPer];
 #pragma unroll
     for (int u = 0; u < kVecPer; ++u) {
         const int i = min(tile * kVecBlock + tid + u * kBlock, n - 1);
         zv[u] = z[i];
         pv[u] = p[i];
+        xv[u] = __builtin_nontemporal_load(x + i);
     }
     double rr, rho;
     wg_totals<2, 1, 1, 0>(part_xr, n_xr, part_g, n_g, rr, rho, sh);
@@ -881,12 +891,16 @@ k_cg_pl(int n, int expect, const double *__restrict__ z, double *__restrict__ p,
             }
         }
     }
-    if (brk || halt != RUN) return;
+    // p is left as it is when the pass ends the loop; x is always updated
+    const bool upd_p = !(brk || halt != RUN);
     for (;;) {
 #pragma unroll
         for (int u = 0; u < kVecPer; ++u) {
             const int i = tile * kVecBlock + tid + u * kBlock;
-            if (i < n) p[i] = zv[u] + beta * pv[u];
+            if (i < n) {
+                __builtin_nontemporal_store(xv[u] + alpha * pv[u], x + i);
+                if (upd_p) p[i] = zv[u] + beta * pv[u];
+            }
         }
         tile += gridDim.x;
         if (tile * kVecBlock >= n) break;
@@ -895,6 +909,7 @@ k_cg_pl(int n, int expect, const double *__restrict__ z, double *__restrict__ p,
             const int i = min(tile * kVecBlock + tid + u * kBlock, n - 1);
             zv[u] = z[i];
             pv[u] = p[i];
+            xv[u] = __builtin_nontemporal_load(x + i);
         }
     }
 }
@@ -1721,16 +1736,16 @@ struct Solver {
                                (int)gA(), e);
             if (pre == SPCG_PRECOND_JACOBI) {
                 hipLaunchKernelGGL((k_cg_xr<double, SPCG_PRECOND_JACOBI>), dim3(gx), dim3(kBlock), 0,
-                                   s, n, e, x, w.r, w.p, w.q, w.dinv, w.st, w.partd);
+                                   s, n, e, w.r, (const double *)w.q, (const double *)w.dinv, w.st, w.partd);
                 hipLaunchKernelGGL((k_cg_pf<double, SPCG_PRECOND_JACOBI, false>), dim3(gx),
                                    dim3(kBlock), 0, s, n, e, (const double *)w.r,
-                                   (const double *)w.dinv, w.p, w.st, pd, (int)gx, w.hist);
+                                   (const double *)w.dinv, w.p, x, w.st, pd, (int)gx, w.hist);
             } else {
                 hipLaunchKernelGGL((k_cg_xr<double, SPCG_PRECOND_NONE>), dim3(gx), dim3(kBlock), 0,
-                                   s, n, e, x, w.r, w.p, w.q, w.dinv, w.st, w.partd);
+                                   s, n, e, w.r, (const double *)w.q, (const double *)w.dinv, w.st, w.partd);
                 hipLaunchKernelGGL((k_cg_pf<double, SPCG_PRECOND_NONE, false>), dim3(gx),
                                    dim3(kBlock), 0, s, n, e, (const double *)w.r,
-                                   (const double *)w.dinv, w.p, w.st, pd, (int)gx, w.hist);
+                                   (const double *)w.dinv, w.p, x, w.st, pd, (int)gx, w.hist);
             }
         } else {
             // F1, K2 (r.r), z = G (G^T r) with r.z, K3L (pass end folded in)
@@ -1738,9 +1753,9 @@ struct Solver {
             hipLaunchKernelGGL((k_fin_q<double, true>), dim3(1), dim3(kFinThreads), 0, s, w.st, pd,
                                (int)gA(), e);
             hipLaunchKernelGGL((k_cg_xr<double, SPCG_PRECOND_LEARNED>), dim3(gx), dim3(kBlock),
-                               0, s, n, e, x, w.r, w.p, w.q, w.dinv, w.st, w.partd);
+                               0, s, n, e, w.r, (const double *)w.q, (const double *)w.dinv, w.st, w.partd);
             apply_factor(e);
-            hipLaunchKernelGGL(k_cg_pl, dim3(gx), dim3(kBlock), 0, s, n, e, (const double *)w.z, w.p,
+            hipLaunchKernelGGL(k_cg_pl, dim3(gx), dim3(kBlock), 0, s, n, e, (const double *)w.z, w.p, x,
                                w.st, pd, (int)gx, (const double *)w.partg, (int)gG(), w.hist);
         }
         SPCG_LAUNCH_CHECK("cg pass");
@@ -1769,10 +1784,10 @@ struct Solver {
         hipLaunchKernelGGL((k_fin_q<float, true>), dim3(1), dim3(kFinThreads), 0, s, w.st, pf,
                            (int)gA(), e);
         hipLaunchKernelGGL((k_cg_xr<float, SPCG_PRECOND_JACOBI>), dim3(gx), dim3(kBlock), 0, s,
-                           n, e, w.x32, w.r32, w.p32, w.q32, w.dinv32, w.st, w.partf);
+                           n, e, w.r32, (const float *)w.q32, (const float *)w.dinv32, w.st, w.partf);
         hipLaunchKernelGGL((k_cg_pf<float, SPCG_PRECOND_JACOBI, true>), dim3(gx), dim3(kBlock), 0,
-                           s, n, e, (const float *)w.r32, (const float *)w.dinv32, w.p32, w.st, pf,
-                           (int)gx, w.hist);
+                           s, n, e, (const float *)w.r32, (const float *)w.dinv32, w.p32, w.x32, w.st,
+                           pf, (int)gx, w.hist);
         SPCG_LAUNCH_CHECK("mixed pass");
         return SPCG_OK;
     }
