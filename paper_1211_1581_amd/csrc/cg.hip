@@ -835,7 +835,9 @@ k_g_dia(DiaDev G, const double *__restrict__ t, const double *__restrict__ r,
 // workgroup sums ||r||^2 from K2's partials (second value of each slot) and
 // r.z from the G apply's partials in one fixed order, takes the decision of a
 // learned pass (converged, out of passes, budget used up, breakdown) and
-// updates p unless the pass ends the loop; workgroup 0 records the pass.
+// updates p unless the pass ends the loop; workgroup 0 records the pass.  As
+// in K3F, x += alpha p of the pass is done here, also in a pass that ends the
+// loop.
 __global__ void __launch_bounds__(kBlock)
 k_cg_pl(int n, int expect, const double *__restrict__ z, double *__restrict__ p,
         double *__restrict__ x, CgState *st, const double *__restrict__ part_xr, int n_xr,
