@@ -36,3 +36,34 @@ def test_trained_factor_beats_jacobi(seed):
     assert counts["trained"] <= 0.6 * j["iters"], (counts, j["iters"])
     # the weights file records a held-out loss well below Jacobi's
     assert meta["heldout_loss"] < 0.5 * meta["heldout_loss_jacobi"]
+
+
+def test_full_size_learned_and_fsai_fv128():
+    """The solver forms at the size they are timed at: the unseen 128^3
+    diffusion matrix of seed 1000 (n = 2 097 152), the learned factor from the
+    committed weights with its pass budget, and FSAI on the same pattern. Each
+    solve reaches the 1e-10 FP64 residual recomputed by the oracle, both
+    factors need at most 0.6 x the Jacobi passes (the learned one within its
+    budget, no fallback), and Jacobi-PCG takes the oracle's pass count."""
+    S = spcg()
+    A, _, xs = I.fv_diffusion(128, 1000)
+    b_np = I.rhs_from_solution(A, xs)
+    b = torch.as_tensor(b_np, device="cuda")
+    M = S.CsrMatrix.from_host(A)
+    w, meta = train.load_weights()
+    budget = train.budget_for(128, meta.get("mean_learned_passes_48", 117.0))
+    g = S.MpnnGraph(M)
+    g.predict(torch.tensor(w, dtype=torch.float32, device="cuda"))
+    rl = S.cg_solve(M, b, tol=1e-10, maxit=20000, precond="learned", G=g.G, GT=g.GT, budget=budget)
+    gf = S.MpnnGraph(M, ws=g.ws)
+    S.fsai_values(M, gf.G, gf.GT)
+    rf = S.cg_solve(M, b, tol=1e-10, maxit=20000, precond="learned", G=gf.G, GT=gf.GT, budget=20000)
+    rj = S.cg_solve(M, b, tol=1e-10, maxit=20000, precond="jacobi")
+    for r in (rl, rf, rj):
+        assert r["status"] == S.OK
+        assert oracle.true_relres(A, b_np, r["x"].cpu().numpy()) <= 1e-10
+    assert rl["iters_fallback"] == 0 and rl["iters"] <= budget
+    assert rl["iters"] <= 0.6 * rj["iters"], (rl["iters"], rj["iters"])
+    assert rf["iters"] <= 0.6 * rj["iters"], (rf["iters"], rj["iters"])
+    ref = oracle.pcg(A, b_np, tol=1e-10, maxit=20000, precond="jacobi")
+    assert abs(rj["iters"] - ref["iters"]) <= 0.02 * ref["iters"] + 2, (rj["iters"], ref["iters"])
