@@ -87,6 +87,23 @@ def test_mixed_precision_fv():
     assert g["iters"] <= 1.15 * j["iters"] + 5
 
 
+
+def test_mixed_precision_full_size_fv160():
+    """The mixed form at the size it is timed at (160^3 diffusion, seed 3,
+    n = 4 096 000; its FP32 copy takes the 16-bit column offsets): both
+    solves reach the 1e-10 FP64 residual recomputed by the oracle, the FP32
+    inner loop needs no more passes than the FP32 band around FP64 Jacobi-PCG
+    allows, and a handful of FP64 replacements suffice."""
+    A, _, xs = I.fv_diffusion(160, 3)
+    b = I.rhs_from_solution(A, xs)
+    g = solve(A, b, tol=1e-10, maxit=20000, precond="jacobi", precision="mixed")
+    j = solve(A, b, tol=1e-10, maxit=20000, precond="jacobi")
+    for r in (g, j):
+        assert r["status"] == 0
+        assert oracle.true_relres(A, b, r["x"]) <= 1e-10
+    assert g["iters"] <= 1.15 * j["iters"] + 5, (g["iters"], j["iters"])
+    assert 1 <= g["n_updates"] <= 30, g["n_updates"]
+
 def test_learned_form_with_jacobi_factor():
     A, _, xs = I.fv_diffusion(24, 5)
     b = I.rhs_from_solution(A, xs)
