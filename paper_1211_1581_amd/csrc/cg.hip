@@ -615,47 +615,49 @@ __device__ __forceinline__ void ell_rows_times(const EllDev &F, const double *__
     }
 }
 
-// t = G^T r  (ELL).  kexp: pass number, or -1 at a phase start.
+// t = G^T r  (ELL); partial t.t per workgroup, which is r.z for z = G t
+// (r.z = r^T G G^T r = |G^T r|^2), so the G apply need not read r.
+// kexp: pass number, or -1 at a phase start.
 template <int W, bool KEEP>
 __global__ void __launch_bounds__(kBlock)
 k_gt_ell(EllDev GT, const double *__restrict__ r, double *__restrict__ t, const CgState *st,
-         int kexp) {
+         double *part, int kexp) {
     constexpr int R = ell_rows<W>();
+    __shared__ double red[kWaves];
     if (st->halt != RUN || (kexp >= 0 && st->k != kexp)) return;
+    double acc = 0.0;
     for (int base = blockIdx.x * kBlock * R; base < GT.n; base += gridDim.x * kBlock * R) {
         double sv[R];
         ell_rows_times<W, R, KEEP>(GT, r, base, sv);
 #pragma unroll
         for (int u = 0; u < R; ++u) {
             const int i = base + u * kBlock + threadIdx.x;
-            if (i < GT.n) t[i] = sv[u];
+            if (i < GT.n) {
+                t[i] = sv[u];
+                acc += sv[u] * sv[u];
+            }
         }
     }
+    const double v[1] = {acc};
+    store_block_partials(part, blockIdx.x, v, red);
 }
 
-// z = G t (ELL); partial r.z per workgroup
+// z = G t (ELL)
 template <int W, bool KEEP>
 __global__ void __launch_bounds__(kBlock)
-k_g_ell(EllDev G, const double *__restrict__ t, const double *__restrict__ r,
-        double *__restrict__ z, const CgState *st, double *part, int kexp) {
+k_g_ell(EllDev G, const double *__restrict__ t, double *__restrict__ z, const CgState *st,
+        int kexp) {
     constexpr int R = ell_rows<W>();
-    __shared__ double red[kWaves];
     if (st->halt != RUN || (kexp >= 0 && st->k != kexp)) return;
-    double acc = 0.0;
     for (int base = blockIdx.x * kBlock * R; base < G.n; base += gridDim.x * kBlock * R) {
         double sv[R];
         ell_rows_times<W, R, KEEP>(G, t, base, sv);
 #pragma unroll
         for (int u = 0; u < R; ++u) {
             const int i = base + u * kBlock + threadIdx.x;
-            if (i < G.n) {
-                z[i] = sv[u];
-                acc += r[i] * sv[u];
-            }
+            if (i < G.n) z[i] = sv[u];
         }
     }
-    const double v[1] = {acc};
-    store_block_partials(part, blockIdx.x, v, red);
 }
 
 // ------------------------------------- learned: factors as DIA planes --
@@ -788,47 +790,49 @@ __device__ __forceinline__ void dia_rows_times(const DiaDev &F, const double *__
     }
 }
 
-// t = G^T r  (DIA)
+// t = G^T r  (DIA); partial t.t per workgroup, which is r.z for z = G t
+// (r.z = r^T G G^T r = |G^T r|^2), so the G apply need not read r.
+// kexp: pass number, or -1 at a phase start.
 template <int W, bool KEEP>
 __global__ void __launch_bounds__(kBlock)
 k_gt_dia(DiaDev GT, const double *__restrict__ r, double *__restrict__ t, const CgState *st,
-         int kexp) {
+         double *part, int kexp) {
     constexpr int R = ell_rows<W>();
+    __shared__ double red[kWaves];
     if (st->halt != RUN || (kexp >= 0 && st->k != kexp)) return;
+    double acc = 0.0;
     for (int base = blockIdx.x * kBlock * R; base < GT.n; base += gridDim.x * kBlock * R) {
         double sv[R];
         dia_rows_times<W, R, KEEP>(GT, r, base, sv);
 #pragma unroll
         for (int u = 0; u < R; ++u) {
             const int i = base + u * kBlock + threadIdx.x;
-            if (i < GT.n) t[i] = sv[u];
+            if (i < GT.n) {
+                t[i] = sv[u];
+                acc += sv[u] * sv[u];
+            }
         }
     }
+    const double v[1] = {acc};
+    store_block_partials(part, blockIdx.x, v, red);
 }
 
-// z = G t (DIA); partial r.z per workgroup
+// z = G t (DIA)
 template <int W, bool KEEP>
 __global__ void __launch_bounds__(kBlock)
-k_g_dia(DiaDev G, const double *__restrict__ t, const double *__restrict__ r,
-        double *__restrict__ z, const CgState *st, double *part, int kexp) {
+k_g_dia(DiaDev G, const double *__restrict__ t, double *__restrict__ z, const CgState *st,
+        int kexp) {
     constexpr int R = ell_rows<W>();
-    __shared__ double red[kWaves];
     if (st->halt != RUN || (kexp >= 0 && st->k != kexp)) return;
-    double acc = 0.0;
     for (int base = blockIdx.x * kBlock * R; base < G.n; base += gridDim.x * kBlock * R) {
         double sv[R];
         dia_rows_times<W, R, KEEP>(G, t, base, sv);
 #pragma unroll
         for (int u = 0; u < R; ++u) {
             const int i = base + u * kBlock + threadIdx.x;
-            if (i < G.n) {
-                z[i] = sv[u];
-                acc += r[i] * sv[u];
-            }
+            if (i < G.n) z[i] = sv[u];
         }
     }
-    const double v[1] = {acc};
-    store_block_partials(part, blockIdx.x, v, red);
 }
 
 // K3L: the learned pass's end folded into p = z + beta p, as K3F: every
@@ -1576,25 +1580,26 @@ struct Solver {
         return w.w_g ? ell_grid() : std::min<unsigned>(factor_grid(o->G), kApplyGrid);
     }
 
-    // z = G (G^T r); r.z partials of the G apply in w.partg
+    // z = G (G^T r); r.z partials in w.partg (ELL, DIA: t.t from the G^T apply,
+    // on the same grid; CSR: r.z from the G apply)
     unsigned ell_grid() const { return std::min<unsigned>(grid_of(A->n_rows, kBlock), kEllGrid); }
 
     template <int WG, int WT, bool KEEP>
     void apply_ell(int kexp) {
         const EllDev gt{w.gt_col, w.gt_val, A->n_rows}, g{w.g_col, w.g_val, A->n_rows};
         hipLaunchKernelGGL((k_gt_ell<WT, KEEP>), dim3(ell_grid()), dim3(kBlock), 0, s, gt,
-                           (const double *)w.r, w.t, w.st, kexp);
+                           (const double *)w.r, w.t, w.st, w.partg, kexp);
         hipLaunchKernelGGL((k_g_ell<WG, KEEP>), dim3(ell_grid()), dim3(kBlock), 0, s, g,
-                           (const double *)w.t, (const double *)w.r, w.z, w.st, w.partg, kexp);
+                           (const double *)w.t, w.z, w.st, kexp);
     }
 
     template <int WG, int WT, bool KEEP>
     void apply_dia(int kexp) {
         const DiaDev gt{w.gt_val, dia_gt, A->n_rows}, g{w.g_val, dia_g, A->n_rows};
         hipLaunchKernelGGL((k_gt_dia<WT, KEEP>), dim3(ell_grid()), dim3(kBlock), 0, s, gt,
-                           (const double *)w.r, w.t, w.st, kexp);
+                           (const double *)w.r, w.t, w.st, w.partg, kexp);
         hipLaunchKernelGGL((k_g_dia<WG, KEEP>), dim3(ell_grid()), dim3(kBlock), 0, s, g,
-                           (const double *)w.t, (const double *)w.r, w.z, w.st, w.partg, kexp);
+                           (const double *)w.t, w.z, w.st, kexp);
     }
 
     void apply_factor(int kexp) {
