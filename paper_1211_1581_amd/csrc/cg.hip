@@ -372,8 +372,8 @@ __device__ __forceinline__ void wg_totals(const T *__restrict__ a, int na, const
 // Update kernels of the folded pass end run with at most kXrGrid workgroups
 // (each walks a range of tiles), so K3F sums at most 2 kXrGrid partials.
 constexpr int kXrGrid = 1024;
-// Workgroups of the learned form's z = G t (each walks a range of row blocks
-// or short-row steps): K3L sums one partial per workgroup.
+// Workgroups of the learned form's t = G^T r in CSR form (each walks a range
+// of row blocks or short-row steps): K3L sums one partial per workgroup.
 constexpr int kApplyGrid = 4096;
 
 // K3F: the end-of-pass finalize folded into p = z + beta p.  Every workgroup
@@ -492,58 +492,59 @@ struct FactorDev {
     int n;
 };
 
-// t = G^T r.  kexp: pass number the state must be at, or -1 at a phase start.
-// SHORT: every row of G^T has at most kShortLen entries.  KEEP: load policy
-// of the factor's streams (keep_bytes).
-template <bool SHORT, bool KEEP>
-SPCG_ROWBLOCK_KERNEL
-k_gt_apply(FactorDev GT, const double *__restrict__ r, double *__restrict__ t, const CgState *st,
-           int kexp) {
-    __shared__ SpmvSmem<double> sm;
-    if (st->halt != RUN || (kexp >= 0 && st->k != kexp)) return;
-    int bs, be;
-    EpiStore64 epi{t};
-    if constexpr (SHORT) {
-        block_range((int)short_steps(GT.n), bs, be);
-        for (int k = bs; k < be; ++k)
-            spmv_short<float, double, double, KEEP>(GT.A.row_ptr, GT.A.col, GT.vals, r, GT.n, k, epi);
-    } else {
-        block_range(GT.A.n_blocks, bs, be);
-        for (int k = bs; k < be; ++k) spmv_block<float, double, double, KEEP>(GT.A, GT.vals, r, k, sm, epi, k + 1 < be);
-    }
-}
-
-struct EpiZ {
-    double *__restrict__ z;
-    const double *__restrict__ r;
+struct EpiTT {
+    double *__restrict__ t;
     double acc;
-    __device__ __forceinline__ double load(int i) const { return r[i]; }
-    __device__ __forceinline__ void row(int i, double s, double ri) {
-        z[i] = s;
-        acc += ri * s;
+    __device__ __forceinline__ NoOperand load(int) const { return {}; }
+    __device__ __forceinline__ void row(int i, double s, NoOperand) {
+        t[i] = s;
+        acc += s * s;
     }
 };
 
-// z = G t; partial r.z
+// t = G^T r; partial t.t per workgroup, which is r.z for z = G t
+// (r.z = r^T G G^T r = |G^T r|^2), so the G apply need not read r.  kexp:
+// pass number the state must be at, or -1 at a phase start.  SHORT: every row
+// of G^T has at most kShortLen entries.  KEEP: load policy of the factor's
+// streams (keep_bytes).
 template <bool SHORT, bool KEEP>
 SPCG_ROWBLOCK_KERNEL
-k_g_apply(FactorDev G, const double *__restrict__ t, const double *__restrict__ r,
-          double *__restrict__ z, const CgState *st, double *part, int kexp) {
+k_gt_apply(FactorDev GT, const double *__restrict__ r, double *__restrict__ t, const CgState *st,
+           double *part, int kexp) {
     __shared__ SpmvSmem<double> sm;
     if (st->halt != RUN || (kexp >= 0 && st->k != kexp)) return;
     int bs, be;
-    EpiZ epi{z, r, 0.0};
+    EpiTT epi{t, 0.0};
     int slot;
     if constexpr (SHORT) {
-        slot = block_range((int)short_steps(G.n), bs, be);
+        slot = block_range((int)short_steps(GT.n), bs, be);
         for (int k = bs; k < be; ++k)
-            spmv_short<float, double, double, KEEP>(G.A.row_ptr, G.A.col, G.vals, t, G.n, k, epi);
+            spmv_short<float, double, double, KEEP>(GT.A.row_ptr, GT.A.col, GT.vals, r, GT.n, k, epi);
     } else {
-        slot = block_range(G.A.n_blocks, bs, be);
-        for (int k = bs; k < be; ++k) spmv_block<float, double, double, KEEP>(G.A, G.vals, t, k, sm, epi, k + 1 < be);
+        slot = block_range(GT.A.n_blocks, bs, be);
+        for (int k = bs; k < be; ++k) spmv_block<float, double, double, KEEP>(GT.A, GT.vals, r, k, sm, epi, k + 1 < be);
     }
     const double v[1] = {epi.acc};
     store_block_partials(part, slot, v, sm.red);
+}
+
+// z = G t
+template <bool SHORT, bool KEEP>
+SPCG_ROWBLOCK_KERNEL
+k_g_apply(FactorDev G, const double *__restrict__ t, double *__restrict__ z, const CgState *st,
+          int kexp) {
+    __shared__ SpmvSmem<double> sm;
+    if (st->halt != RUN || (kexp >= 0 && st->k != kexp)) return;
+    int bs, be;
+    EpiStore64 epi{z};
+    if constexpr (SHORT) {
+        block_range((int)short_steps(G.n), bs, be);
+        for (int k = bs; k < be; ++k)
+            spmv_short<float, double, double, KEEP>(G.A.row_ptr, G.A.col, G.vals, t, G.n, k, epi);
+    } else {
+        block_range(G.A.n_blocks, bs, be);
+        for (int k = bs; k < be; ++k) spmv_block<float, double, double, KEEP>(G.A, G.vals, t, k, sm, epi, k + 1 < be);
+    }
 }
 
 // ----------------------------------- learned: factors as padded ELL --
@@ -1575,13 +1576,12 @@ struct Solver {
     unsigned gv() const { return grid_of(A->n_rows, kVecBlock); }
     unsigned gxr() const { return std::min<unsigned>(gv(), kXrGrid); }
     unsigned gA() const { return spmv_grid(A->n_blocks); }
-    // the G apply's workgroups (and r.z partials, which every workgroup of K3L sums)
+    // the G^T apply's workgroups (and r.z partials, which every workgroup of K3L sums)
     unsigned gG() const {
-        return w.w_g ? ell_grid() : std::min<unsigned>(factor_grid(o->G), kApplyGrid);
+        return w.w_g ? ell_grid() : std::min<unsigned>(factor_grid(o->GT), kApplyGrid);
     }
 
-    // z = G (G^T r); r.z partials in w.partg (ELL, DIA: t.t from the G^T apply,
-    // on the same grid; CSR: r.z from the G apply)
+    // z = G (G^T r); r.z partials (t.t from the G^T apply) in w.partg
     unsigned ell_grid() const { return std::min<unsigned>(grid_of(A->n_rows, kBlock), kEllGrid); }
 
     template <int WG, int WT, bool KEEP>
@@ -1628,10 +1628,10 @@ struct Solver {
                       : (keep_g ? k_gt_apply<false, true> : k_gt_apply<false, false>);
         auto g = sg ? (keep_g ? k_g_apply<true, true> : k_g_apply<true, false>)
                     : (keep_g ? k_g_apply<false, true> : k_g_apply<false, false>);
-        hipLaunchKernelGGL(gt, dim3(factor_grid(o->GT)), dim3(kBlock), 0, s, factor_view(o->GT),
-                           (const double *)w.r, w.t, w.st, kexp);
-        hipLaunchKernelGGL(g, dim3(gG()), dim3(kBlock), 0, s, factor_view(o->G),
-                           (const double *)w.t, (const double *)w.r, w.z, w.st, w.partg, kexp);
+        hipLaunchKernelGGL(gt, dim3(gG()), dim3(kBlock), 0, s, factor_view(o->GT),
+                           (const double *)w.r, w.t, w.st, w.partg, kexp);
+        hipLaunchKernelGGL(g, dim3(factor_grid(o->G)), dim3(kBlock), 0, s, factor_view(o->G),
+                           (const double *)w.t, w.z, w.st, kexp);
     }
 
     int resid(int mode, float *r32) {
