@@ -836,6 +836,52 @@ k_g_dia(DiaDev G, const double *__restrict__ t, double *__restrict__ z, const Cg
     }
 }
 
+// The decision of a learned pass from ||r||^2 and r.z (converged, out of
+// passes, budget used up, breakdown), taken alike by every workgroup of a
+// kernel that folds the pass end in; workgroup 0 records the pass: count,
+// history, rho (into the other parity slot), beta, decision.  Returns whether
+// the loop goes on (then p = z + beta p).
+__device__ __forceinline__ bool learned_pass_end(CgState *st, int expect, double rr, double rho,
+                                                 double *__restrict__ hist, double &beta) {
+    const int k = expect + 1;
+    const double est = sqrt(rr);
+    bool brk = false;
+    double brk_v = NAN;
+    int halt = RUN;
+    beta = 0.0;
+    if (!finite_d(rr) || !finite_d(rho)) {
+        brk = true;
+    } else if (est <= st->thresh) {
+        halt = H_CONV;
+    } else if (k >= st->maxit) {
+        halt = H_MAXIT;
+    } else if (k >= st->budget) {
+        halt = H_BUDGET;
+    } else if (rr > 0.0 && !(rho > 0.0)) {
+        brk = true;
+        brk_v = rho;
+    } else {
+        beta = rho / st->rho_pp[expect & 1];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->k = k;
+        hist[k] = est / st->nb;
+        if (brk) {
+            set_break(st, brk_v);
+        } else {
+            st->rr = rr;
+            if (halt != RUN) {
+                st->halt = halt;
+            } else {
+                st->beta = beta;
+                st->rho = rho;
+                st->rho_pp[k & 1] = rho;
+            }
+        }
+    }
+    return !(brk || halt != RUN);
+}
+
 // K3L: the learned pass's end folded into p = z + beta p, as K3F: every
 // workgroup sums ||r||^2 from K2's partials (second value of each slot) and
 // r.z from the G apply's partials in one fixed order, takes the decision of a
@@ -862,44 +908,9 @@ k_cg_pl(int n, int expect, const double *__restrict__ z, double *__restrict__ p,
     }
     double rr, rho;
     wg_totals<2, 1, 1, 0>(part_xr, n_xr, part_g, n_g, rr, rho, sh);
-    const int k = expect + 1;
-    const double est = sqrt(rr);
-    bool brk = false;
-    double brk_v = NAN;
-    int halt = RUN;
-    double beta = 0.0;
-    if (!finite_d(rr) || !finite_d(rho)) {
-        brk = true;
-    } else if (est <= st->thresh) {
-        halt = H_CONV;
-    } else if (k >= st->maxit) {
-        halt = H_MAXIT;
-    } else if (k >= st->budget) {
-        halt = H_BUDGET;
-    } else if (rr > 0.0 && !(rho > 0.0)) {
-        brk = true;
-        brk_v = rho;
-    } else {
-        beta = rho / st->rho_pp[expect & 1];
-    }
-    if (blockIdx.x == 0 && tid == 0) {
-        st->k = k;
-        hist[k] = est / st->nb;
-        if (brk) {
-            set_break(st, brk_v);
-        } else {
-            st->rr = rr;
-            if (halt != RUN) {
-                st->halt = halt;
-            } else {
-                st->beta = beta;
-                st->rho = rho;
-                st->rho_pp[k & 1] = rho;
-            }
-        }
-    }
+    double beta;
     // p is left as it is when the pass ends the loop; x is always updated
-    const bool upd_p = !(brk || halt != RUN);
+    const bool upd_p = learned_pass_end(st, expect, rr, rho, hist, beta);
     for (;;) {
 #pragma unroll
         for (int u = 0; u < kVecPer; ++u) {
@@ -918,6 +929,54 @@ k_cg_pl(int n, int expect, const double *__restrict__ z, double *__restrict__ p,
             pv[u] = p[i];
             xv[u] = __builtin_nontemporal_load(x + i);
         }
+    }
+}
+
+// K3G: z = G t from the ELL or DIA copy with the learned pass's end folded in.
+// The G^T apply of the pass has already written the r.z = t.t partials, so
+// every workgroup sums ||r||^2 and r.z as K3L does, takes the same decision,
+// and uses each z_i at once: x += alpha p, and p = z + beta p unless the pass
+// ends the loop.  z is neither stored nor read back, and K3L is not launched.
+// Gate: kq, as K3L (workgroup 0 rewrites k and halt while the others run).
+template <int W, bool KEEP, bool DIA, class Dev>
+__global__ void __launch_bounds__(kBlock)
+k_g_pass(Dev G, const double *__restrict__ t, double *__restrict__ p, double *__restrict__ x,
+         CgState *st, const double *__restrict__ part_xr, int n_xr,
+         const double *__restrict__ part_g, int n_g, double *__restrict__ hist, int expect) {
+    constexpr int R = ell_rows<W>();
+    __shared__ double sh[kWaves * 2];
+    if (st->kq != expect) return;
+    const double alpha = st->alpha;  // set by F1 of this pass; not written below
+    const int n = G.n, tid = threadIdx.x;
+    const int stride = gridDim.x * kBlock * R;
+    double sv[R], pv[R], xv[R];
+    auto fetch = [&](int b) {
+        if constexpr (DIA) dia_rows_times<W, R, KEEP>(G, t, b, sv);
+        else ell_rows_times<W, R, KEEP>(G, t, b, sv);
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int i = min(b + u * kBlock + tid, n - 1);
+            pv[u] = p[i];
+            xv[u] = __builtin_nontemporal_load(x + i);
+        }
+    };
+    // the first rows' products and operands are requested before the partials are summed
+    int base = blockIdx.x * kBlock * R;
+    if (base < n) fetch(base);
+    double rr, rho;
+    wg_totals<2, 1, 1, 0>(part_xr, n_xr, part_g, n_g, rr, rho, sh);
+    double beta;
+    const bool upd_p = learned_pass_end(st, expect, rr, rho, hist, beta);
+    for (; base < n; base += stride) {
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int i = base + u * kBlock + tid;
+            if (i < n) {
+                __builtin_nontemporal_store(xv[u] + alpha * pv[u], x + i);
+                if (upd_p) p[i] = sv[u] + beta * pv[u];
+            }
+        }
+        if (base + stride < n) fetch(base + stride);
     }
 }
 
@@ -1584,31 +1643,48 @@ struct Solver {
     // z = G (G^T r); r.z partials (t.t from the G^T apply) in w.partg
     unsigned ell_grid() const { return std::min<unsigned>(grid_of(A->n_rows, kBlock), kEllGrid); }
 
+    // the G apply with the pass end folded in (K3G) in place of z = G t and K3L
+    template <int WG, bool KEEP, bool DIA, class Dev>
+    void g_pass(const Dev &g, int e) {
+        hipLaunchKernelGGL((k_g_pass<WG, KEEP, DIA, Dev>), dim3(ell_grid()), dim3(kBlock), 0, s, g,
+                           (const double *)w.t, w.p, x, w.st, (const double *)w.partd, (int)gxr(),
+                           (const double *)w.partg, (int)gG(), w.hist, e);
+    }
+
     template <int WG, int WT, bool KEEP>
-    void apply_ell(int kexp) {
+    void apply_ell(int kexp, bool fused) {
         const EllDev gt{w.gt_col, w.gt_val, A->n_rows}, g{w.g_col, w.g_val, A->n_rows};
         hipLaunchKernelGGL((k_gt_ell<WT, KEEP>), dim3(ell_grid()), dim3(kBlock), 0, s, gt,
                            (const double *)w.r, w.t, w.st, w.partg, kexp);
-        hipLaunchKernelGGL((k_g_ell<WG, KEEP>), dim3(ell_grid()), dim3(kBlock), 0, s, g,
-                           (const double *)w.t, w.z, w.st, kexp);
+        if (fused)
+            g_pass<WG, KEEP, false>(g, kexp);
+        else
+            hipLaunchKernelGGL((k_g_ell<WG, KEEP>), dim3(ell_grid()), dim3(kBlock), 0, s, g,
+                               (const double *)w.t, w.z, w.st, kexp);
     }
 
     template <int WG, int WT, bool KEEP>
-    void apply_dia(int kexp) {
+    void apply_dia(int kexp, bool fused) {
         const DiaDev gt{w.gt_val, dia_gt, A->n_rows}, g{w.g_val, dia_g, A->n_rows};
         hipLaunchKernelGGL((k_gt_dia<WT, KEEP>), dim3(ell_grid()), dim3(kBlock), 0, s, gt,
                            (const double *)w.r, w.t, w.st, w.partg, kexp);
-        hipLaunchKernelGGL((k_g_dia<WG, KEEP>), dim3(ell_grid()), dim3(kBlock), 0, s, g,
-                           (const double *)w.t, w.z, w.st, kexp);
+        if (fused)
+            g_pass<WG, KEEP, true>(g, kexp);
+        else
+            hipLaunchKernelGGL((k_g_dia<WG, KEEP>), dim3(ell_grid()), dim3(kBlock), 0, s, g,
+                               (const double *)w.t, w.z, w.st, kexp);
     }
 
-    void apply_factor(int kexp) {
+    // z = G (G^T r).  fused (a pass, kexp >= 0): with the ELL or DIA copies the
+    // G apply also ends the pass (K3G) and z is not stored; returns whether it
+    // did, else the caller launches K3L.
+    bool apply_factor(int kexp, bool fused = false) {
         if (dia) {
 #define SPCG_DIA(WG, WT)                                        \
     if (wd_g == WG && wd_gt == WT) {                            \
-        if (keep_g) apply_dia<WG, WT, true>(kexp);              \
-        else apply_dia<WG, WT, false>(kexp);                    \
-        return;                                                 \
+        if (keep_g) apply_dia<WG, WT, true>(kexp, fused);       \
+        else apply_dia<WG, WT, false>(kexp, fused);             \
+        return fused;                                           \
     }
             SPCG_DIA(4, 4) SPCG_DIA(4, 8) SPCG_DIA(8, 4) SPCG_DIA(8, 8)
 #undef SPCG_DIA
@@ -1616,9 +1692,9 @@ struct Solver {
         if (w.w_g) {
 #define SPCG_ELL(WG, WT)                                        \
     if (w.w_g == WG && w.w_gt == WT) {                          \
-        if (keep_g) apply_ell<WG, WT, true>(kexp);              \
-        else apply_ell<WG, WT, false>(kexp);                    \
-        return;                                                 \
+        if (keep_g) apply_ell<WG, WT, true>(kexp, fused);       \
+        else apply_ell<WG, WT, false>(kexp, fused);             \
+        return fused;                                           \
     }
             SPCG_ELL(4, 4) SPCG_ELL(4, 8) SPCG_ELL(8, 4) SPCG_ELL(8, 8)
 #undef SPCG_ELL
@@ -1632,6 +1708,7 @@ struct Solver {
                            (const double *)w.r, w.t, w.st, w.partg, kexp);
         hipLaunchKernelGGL(g, dim3(factor_grid(o->G)), dim3(kBlock), 0, s, factor_view(o->G),
                            (const double *)w.t, w.z, w.st, kexp);
+        return false;
     }
 
     int resid(int mode, float *r32) {
@@ -1761,9 +1838,9 @@ struct Solver {
                                (int)gA(), e);
             hipLaunchKernelGGL((k_cg_xr<double, SPCG_PRECOND_LEARNED>), dim3(gx), dim3(kBlock),
                                0, s, n, e, w.r, (const double *)w.q, (const double *)w.dinv, w.st, w.partd);
-            apply_factor(e);
-            hipLaunchKernelGGL(k_cg_pl, dim3(gx), dim3(kBlock), 0, s, n, e, (const double *)w.z, w.p, x,
-                               w.st, pd, (int)gx, (const double *)w.partg, (int)gG(), w.hist);
+            if (!apply_factor(e, true))
+                hipLaunchKernelGGL(k_cg_pl, dim3(gx), dim3(kBlock), 0, s, n, e, (const double *)w.z, w.p,
+                                   x, w.st, pd, (int)gx, (const double *)w.partg, (int)gG(), w.hist);
         }
         SPCG_LAUNCH_CHECK("cg pass");
         return SPCG_OK;
