@@ -1643,10 +1643,12 @@ struct Solver {
     // z = G (G^T r); r.z partials (t.t from the G^T apply) in w.partg
     unsigned ell_grid() const { return std::min<unsigned>(grid_of(A->n_rows, kBlock), kEllGrid); }
 
-    // the G apply with the pass end folded in (K3G) in place of z = G t and K3L
+    // the G apply with the pass end folded in (K3G) in place of z = G t and K3L;
+    // on the update kernels' grid (at most 1024 workgroups, each walking a range
+    // of rows), since every workgroup sums all the partials first
     template <int WG, bool KEEP, bool DIA, class Dev>
     void g_pass(const Dev &g, int e) {
-        hipLaunchKernelGGL((k_g_pass<WG, KEEP, DIA, Dev>), dim3(ell_grid()), dim3(kBlock), 0, s, g,
+        hipLaunchKernelGGL((k_g_pass<WG, KEEP, DIA, Dev>), dim3(std::min(ell_grid(), gxr())), dim3(kBlock), 0, s, g,
                            (const double *)w.t, w.p, x, w.st, (const double *)w.partd, (int)gxr(),
                            (const double *)w.partg, (int)gG(), w.hist, e);
     }
