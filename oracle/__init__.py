@@ -64,7 +64,8 @@ def lib():
                                  P, P, P]
         L.oracle_pcg_learned.argtypes = [i32, P, P, P, P, P, P, P, P, f64, i32, i32,
                                          P, P, P, P, P]
-        L.oracle_cg_mixed.argtypes = [i32, P, P, P, P, P, f64, i32, f64, P, P, P, P]
+        L.oracle_cg_mixed.argtypes = [i32, P, P, P, P, P, f64, i32, f64, ctypes.c_int, P, P,
+                                      P, P]
         L.oracle_cg_single_reduction.argtypes = [i32, P, P, P, P, P, ctypes.c_int, f64, i32, P, P, P]
         _lib = L
     return _lib
@@ -183,14 +184,18 @@ def pcg_learned(A, b, G, x0=None, tol=1e-10, maxit=20000, budget=1000):
                 hist_fallback=hf[:ifb.value + 1].copy(), true_relres=tr.value)
 
 
-def cg_mixed(A, b, x0=None, tol=1e-10, maxit=20000, delta=0.1):
+def cg_mixed(A, b, x0=None, tol=1e-10, maxit=20000, delta=0.1, dot_order="tree"):
+    """FP32-inner / FP64-outer reliable-update CG.  dot_order: "tree" (FP32
+    inner products as a balanced binary tree, the order of a data-parallel
+    reduction) or "blocked" (blocks of 4096 in index order)."""
+    order = {"blocked": 0, "tree": 1}[dot_order]
     rp, c, v, b = _i32(A.row_ptr), _i32(A.col), _f64(A.vals), _f64(b)
     x = np.zeros(A.n_rows) if x0 is None else _f64(x0).copy()
     hist = np.full(maxit + 1, np.nan)
     it, nu = ctypes.c_int32(0), ctypes.c_int32(0)
     tr = ctypes.c_double(0.0)
     st = lib().oracle_cg_mixed(A.n_rows, _p(rp), _p(c), _p(v), _p(b), _p(x), tol, maxit,
-                               delta, ctypes.byref(it), ctypes.byref(nu), _p(hist),
+                               delta, order, ctypes.byref(it), ctypes.byref(nu), _p(hist),
                                ctypes.byref(tr))
     k = it.value
     return dict(status=st, x=x, iters=k, n_updates=nu.value, hist=hist[:k + 1].copy(),

@@ -150,6 +150,35 @@ static float dot_f32(int64_t n, const float *a, const float *b) {
     return s;
 }
 
+/* The same FP32 inner product summed as a balanced binary tree: at each level
+ * the adjacent pairs (2i, 2i + 1) are added and an unpaired last element moves
+ * up unchanged, until one value is left.  This is the order of a data-parallel
+ * reduction (the paper's CG takes its inner products with a whole-container
+ * add-reduce), and its rounding error grows with log2(n), not with the block
+ * length of the sequential order above. */
+static float dot_f32_tree(int64_t n, const float *a, const float *b) {
+    if (n <= 0) return 0.0f;
+    float *u = (float *)malloc((size_t)n * sizeof(float));
+    float *v = (float *)malloc((size_t)((n + 1) / 2) * sizeof(float));
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) u[i] = a[i] * b[i];
+    int64_t m = n;
+    while (m > 1) {
+        const int64_t h = m / 2;
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < h; ++i) v[i] = u[2 * i] + u[2 * i + 1];
+        if (m & 1) v[h] = u[m - 1];
+        m = (m + 1) / 2;
+        float *t = u;
+        u = v;
+        v = t;
+    }
+    const float s = u[0];
+    free(u);
+    free(v);
+    return s;
+}
+
 /* -------------------------------------------------------- preconditioners -- */
 
 /* dinv_i = 1 / a_ii, the diagonal summed over duplicate entries.  A missing or
@@ -432,17 +461,23 @@ int oracle_pcg_learned(int32_t n, const int32_t *row_ptr, const int32_t *col,
  *           r32 = fl32(r64);  z = dinv32 r32;  rho = r32.z;  rlast = ||r64||
  *           stop when ||r64|| <= tol ||b||            (p is kept)
  *
+ * The FP32 inner products are summed in blocks of 4096 in index order
+ * (dot_order 0) or as a balanced binary tree (dot_order 1); FP64 ones always
+ * in blocks.  The FP32 recursion is sensitive to this choice: sequential
+ * FP32 sums of 4096 terms carry errors up to ~4096 u32, a tree ~log2(n) u32.
  * dinv32 = fl32(1 / a_ii) with the division in FP64.  hist[k] is the FP32
  * recursive estimate ||r32|| / ||b|| (after a replacement, the FP64 value).
  * n_updates counts FP64 residual replacements (outer refinements).
  */
 int oracle_cg_mixed(int32_t n, const int32_t *row_ptr, const int32_t *col, const double *vals,
                     const double *b, double *x, double tol, int32_t maxit, double delta,
-                    int32_t *iters, int32_t *n_updates, double *hist, double *true_relres) {
+                    int dot_order, int32_t *iters, int32_t *n_updates, double *hist,
+                    double *true_relres) {
     *iters = 0;
     *n_updates = 0;
     *true_relres = 0.0;
     if (n < 0 || maxit < 0 || !(tol >= 0.0) || !(delta > 0.0 && delta < 1.0)) return OR_INVALID_ARG;
+    if (dot_order != 0 && dot_order != 1) return OR_INVALID_ARG;
     if (!all_finite(n, b) || !all_finite(n, x)) return OR_NON_FINITE;
     double nb = sqrt(oracle_dot(n, b, b));
     if (nb == 0.0) {
@@ -458,6 +493,7 @@ int oracle_cg_mixed(int32_t n, const int32_t *row_ptr, const int32_t *col, const
     float *dinv32 = malloc(nd * sizeof(float)), *r32 = malloc(nd * sizeof(float));
     float *z32 = malloc(nd * sizeof(float)), *p32 = malloc(nd * sizeof(float));
     float *q32 = malloc(nd * sizeof(float)), *x32 = malloc(nd * sizeof(float));
+    float (*dotf)(int64_t, const float *, const float *) = dot_order ? dot_f32_tree : dot_f32;
     int32_t k = 0;
     int status = oracle_jacobi_dinv(n, row_ptr, col, vals, dinv);
     if (status != OR_OK) goto done;
@@ -475,7 +511,7 @@ int oracle_cg_mixed(int32_t n, const int32_t *row_ptr, const int32_t *col, const
         p32[i] = z32[i];
         x32[i] = 0.0f;
     }
-    float rho = dot_f32(n, r32, z32);
+    float rho = dotf(n, r32, z32);
     status = OR_NOT_CONVERGED;
     if (rlast <= tol * nb) { status = OR_OK; goto finish; }
     while (k < maxit) {
@@ -484,7 +520,7 @@ int oracle_cg_mixed(int32_t n, const int32_t *row_ptr, const int32_t *col, const
             for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) t += v32[e] * p32[col[e]];
             q32[i] = t;
         }
-        float sigma = dot_f32(n, p32, q32);
+        float sigma = dotf(n, p32, q32);
         if (!isfinite(sigma)) { status = OR_NON_FINITE; goto finish; }
         if (!(sigma > 0.0f)) { status = OR_NOT_SPD; goto finish; }
         float alpha = rho / sigma;
@@ -493,8 +529,8 @@ int oracle_cg_mixed(int32_t n, const int32_t *row_ptr, const int32_t *col, const
             r32[i] -= alpha * q32[i];
             z32[i] = dinv32[i] * r32[i];
         }
-        float rho_new = dot_f32(n, r32, z32);
-        float rr = dot_f32(n, r32, r32);
+        float rho_new = dotf(n, r32, z32);
+        float rr = dotf(n, r32, r32);
         float beta = rho_new / rho;
         for (int32_t i = 0; i < n; ++i) p32[i] = z32[i] + beta * p32[i];
         rho = rho_new;
@@ -514,7 +550,7 @@ int oracle_cg_mixed(int32_t n, const int32_t *row_ptr, const int32_t *col, const
                 r32[i] = (float)r64[i];
                 z32[i] = dinv32[i] * r32[i];
             }
-            rho = dot_f32(n, r32, z32);
+            rho = dotf(n, r32, z32);
             if (rlast <= tol * nb) { status = OR_OK; break; }
         }
     }

@@ -1313,7 +1313,11 @@ k_cg_regs(int n, int64_t nnz, const int32_t *__restrict__ rp, const int32_t *__r
     // this thread's own entries of r and D^-1 (only it reads them): LDS keeps
     // the registers for the matrix
     __shared__ double rl_[R * kSmallThreads], dl[R * kSmallThreads];
-    __shared__ double sh[2][kSmallThreads / 64];
+    // wavefront partials: sh[0] p.q, sh[1] r.z, sh[2] r.r.  sigma is read from
+    // sh[0] after the first barrier of a pass and sh[0] is next written after
+    // the barrier that ends the pass, so no slot is rewritten while a slower
+    // wavefront may still read it
+    __shared__ double sh[3][kSmallThreads / 64];
     if (st->halt != RUN) return;
     const int tid = threadIdx.x;
     uint32_t c[R][MP];
@@ -1388,7 +1392,7 @@ k_cg_regs(int n, int64_t nnz, const int32_t *__restrict__ rp, const int32_t *__r
         rl = wave_sum(rl);
         if ((tid & 63) == 0) {
             sh[1][tid >> 6] = rz;
-            sh[0][tid >> 6] = rl;  // every thread read sigma before the barrier above
+            sh[2][tid >> 6] = rl;
         }
         __syncthreads();
         double rzs = 0.0;
@@ -1396,7 +1400,7 @@ k_cg_regs(int n, int64_t nnz, const int32_t *__restrict__ rp, const int32_t *__r
 #pragma unroll
         for (int w = 0; w < kSmallThreads / 64; ++w) {
             rzs += sh[1][w];
-            rr += sh[0][w];
+            rr += sh[2][w];
         }
         ++k;
         const double est = sqrt(rr);

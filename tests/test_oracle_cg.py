@@ -156,16 +156,92 @@ def test_learned_form_zero_head_is_jacobi():
     assert L["true_relres"] <= 1e-10
 
 
-def test_mixed_reliable_update():
+@pytest.mark.parametrize("order", ["tree", "blocked"])
+def test_mixed_reliable_update(order):
     A, _, xs = I.fv_diffusion(16, 3)
     b = I.rhs_from_solution(A, xs)
     j = oracle.pcg(A, b, tol=1e-10, maxit=5000, precond="jacobi")
-    m = oracle.cg_mixed(A, b, tol=1e-10, maxit=5000, delta=0.1)
+    m = oracle.cg_mixed(A, b, tol=1e-10, maxit=5000, delta=0.1, dot_order=order)
     assert m["status"] == oracle.OK
     assert oracle.true_relres(A, b, m["x"]) <= 1e-10
     assert m["n_updates"] >= 5
     # the kept direction keeps the inner count near the FP64 count
     assert m["iters"] <= 1.15 * j["iters"] + 5
+
+
+# The mixed solver's inner loop is FP32 arithmetic (Sec. 3.4 CG loop in FP32
+# under FP64 residual replacement).  Its pins: an independent numpy restatement
+# with every rounding spelled out (tests/fp32_replay.py) reproduces it bit for
+# bit, which a wider accumulator anywhere in the row sums or inner products
+# would break; and the true residual at the first replacement sits at FP32
+# attainable accuracy, which FP64 vectors would not.
+
+@pytest.mark.parametrize("order", ["tree", "blocked"])
+def test_mixed_first_passes_replay_bitwise(order):
+    # 17^3 = 4913 rows: the blocked order spans two blocks.  Two passes, then
+    # the pass cap forces a replacement: x = fl64(x32) after two FP32 passes,
+    # hist[1] the FP32 recursive residual of pass 1.
+    import fp32_replay as R
+    A, _, xs = I.fv_diffusion(17, 3)
+    b = I.rhs_from_solution(A, xs)
+    ro = "pairwise" if order == "tree" else "blocked"
+    o = oracle.cg_mixed(A, b, tol=1e-10, maxit=2, delta=1e-30, dot_order=order)
+    r = R.cg_mixed(A, b, tol=1e-10, maxit=2, delta=1e-30, order=ro)
+    assert o["iters"] == r["iters"] == 2 and o["n_updates"] == r["n_updates"] == 1
+    assert np.array_equal(o["x"], r["x"])
+    assert np.array_equal(o["hist"], r["hist"])
+    # the FP32 correction is an FP32 vector: every entry of x is a float
+    assert np.array_equal(o["x"].astype(np.float32).astype(np.float64), o["x"])
+
+
+@pytest.mark.parametrize("N,seed,x0seed", [(16, 3, None), (20, 6, 77), (24, 5, None)])
+@pytest.mark.parametrize("order", ["tree", "blocked"])
+def test_mixed_full_solve_replay_bitwise(N, seed, x0seed, order):
+    import fp32_replay as R
+    A, _, xs = I.fv_diffusion(N, seed)
+    b = I.rhs_from_solution(A, xs)
+    x0 = None if x0seed is None else I.uniform_vector(A.n_rows, x0seed)
+    ro = "pairwise" if order == "tree" else "blocked"
+    o = oracle.cg_mixed(A, b, x0=x0, tol=1e-10, maxit=5000, delta=0.1, dot_order=order)
+    r = R.cg_mixed(A, b, x0=x0, tol=1e-10, maxit=5000, delta=0.1, order=ro)
+    assert o["status"] == oracle.OK
+    assert (o["iters"], o["n_updates"]) == (r["iters"], r["n_updates"])
+    assert np.array_equal(o["hist"], r["hist"]) and np.array_equal(o["x"], r["x"])
+    assert o["true_relres"] == r["true_relres"]
+
+
+def test_mixed_attainable_accuracy_is_fp32():
+    # With delta tiny, the first replacement comes only when the FP32
+    # recursion claims tol: the FP64 residual recomputed there is the FP32
+    # solve's attainable accuracy (about u32 times the condition number), far
+    # above tol; an inner loop in FP64 would track its recursion to ~1e-12.
+    A, _, xs = I.fv_diffusion(16, 3)
+    b = I.rhs_from_solution(A, xs)
+    o = oracle.cg_mixed(A, b, tol=1e-10, maxit=400, delta=1e-30)
+    h = o["hist"]
+    jumps = np.flatnonzero(h[1:] > 10.0 * h[:-1]) + 1
+    assert jumps.size > 0
+    j = int(jumps[0])
+    assert h[j - 1] <= 1e-9          # FP32 recursive residual near tol
+    assert h[j] >= 1e-8              # FP64 true residual at FP32 accuracy
+    assert np.all(h[1:j] < 1.0)      # the FP32 recursion descended until then
+
+
+def test_mixed_inner_count_depends_on_fp32_sum_order():
+    # From a nonzero initial guess on FV 20^3 the FP32 inner pass count moves
+    # by more than 10 % between two valid summation orders of the FP32 inner
+    # products (sequential blocks of 4096 against a tree), while each order's
+    # count is reproduced exactly by the replay above: device reductions, which
+    # are trees, are compared with the tree order.
+    A, _, xs = I.fv_diffusion(20, 6)
+    b = I.rhs_from_solution(A, xs)
+    x0 = I.uniform_vector(A.n_rows, 77)
+    t = oracle.cg_mixed(A, b, x0=x0, tol=1e-10, maxit=5000, dot_order="tree")
+    k = oracle.cg_mixed(A, b, x0=x0, tol=1e-10, maxit=5000, dot_order="blocked")
+    j = oracle.pcg(A, b, x0=x0, tol=1e-10, maxit=5000, precond="jacobi")
+    assert t["status"] == k["status"] == oracle.OK
+    assert abs(t["iters"] - k["iters"]) > 0.1 * t["iters"]
+    assert abs(t["iters"] - j["iters"]) <= 2
 
 
 # ------------------------------------------- single-reduction (Chronopoulos-Gear) --
