@@ -151,7 +151,8 @@ typedef struct {
 
 typedef struct {
     int32_t iters;          /* passes of the (first) solver: products A p */
-    int32_t iters_fallback; /* passes of the Jacobi fallback (learned form) */
+    int32_t iters_fallback; /* passes of the Jacobi fallback (learned form); iters + iters_fallback
+                               <= maxit */
     int32_t n_updates;      /* mixed: FP64 residual replacements */
     int32_t n_restarts;     /* true-residual restarts */
     double true_relres;     /* ||b - A x||_2 / ||b||_2 recomputed in FP64 at exit */
@@ -180,15 +181,18 @@ size_t spcg_cg_workspace_bytes(spcg_csr_t A, const spcg_cg_opts *opts);
  * A: F64 handle.  d_b double[n], d_x double[n] (in: x0, out: x).
  * d_work: spcg_cg_workspace_bytes(A, opts) bytes, 256-byte aligned.
  * h_hist: NULL or host double[maxit + 1] receiving ||r_k|| / ||b|| for
- *   k = 0..iters (FP32 estimates between replacements for the mixed form).
+ *   k = 0..iters + iters_fallback (FP32 estimates between replacements for the
+ *   mixed form; after a learned-form fallback, entry iters is the residual the
+ *   Jacobi phase starts from and its passes follow).
  * res: filled on every return that is not INVALID_ARG.
  * ||b|| = 0 gives x = 0 and zero passes.  Synchronous (returns after the
  * final check); the loop itself keeps its scalars on the device and the host
  * reads one status word every check_every passes.
  * Mixed precision: FP32 values, vectors and reductions inside, FP64 only for
  * r = b - A x, x += d and the final check.  Learned: M^-1 = G G^T for at most
- * `budget` passes, then (or on breakdown) Jacobi-PCG from the current x and
- * status SPCG_FELL_BACK.
+ * `budget` passes, then Jacobi-PCG from the current x (from x0 after a
+ * breakdown) and status SPCG_FELL_BACK; maxit bounds the passes of both
+ * phases together.
  */
 int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *opts,
              void *d_work, size_t work_bytes, spcg_cg_result *res, double *h_hist,

@@ -423,7 +423,8 @@ done:
  * M^-1 = G G^T for at most `budget` passes; if that does not reach tol, or
  * breaks down (not SPD / non-finite), Jacobi-PCG finishes from the current x
  * (from x0 after a breakdown) and the status is OR_FELL_BACK when it
- * converges.  iters_learned / iters_fallback count the passes of each phase.
+ * converges.  iters_learned / iters_fallback count the passes of each phase,
+ * whose sum maxit bounds.
  */
 int oracle_pcg_learned(int32_t n, const int32_t *row_ptr, const int32_t *col,
                        const double *vals, const double *b, double *x,
@@ -440,7 +441,7 @@ int oracle_pcg_learned(int32_t n, const int32_t *row_ptr, const int32_t *col,
     if (st == OR_OK || st == OR_INVALID_ARG) { free(x0); return st; }
     if (st == OR_NOT_SPD || st == OR_NON_FINITE) memcpy(x, x0, (size_t)n * sizeof(double));
     free(x0);
-    int32_t rest = maxit - (st == OR_NOT_CONVERGED ? *iters_learned : 0);
+    int32_t rest = maxit - *iters_learned;  /* maxit bounds both phases together */
     if (rest < 0) rest = 0;
     int st2 = oracle_pcg(n, row_ptr, col, vals, b, x, OR_PRECOND_JACOBI, NULL, NULL, NULL,
                          NULL, tol, rest, iters_fallback, hist_fallback, true_relres);
@@ -515,6 +516,7 @@ int oracle_cg_mixed(int32_t n, const int32_t *row_ptr, const int32_t *col, const
     status = OR_NOT_CONVERGED;
     if (rlast <= tol * nb) { status = OR_OK; goto finish; }
     while (k < maxit) {
+#pragma omp parallel for schedule(static)
         for (int32_t i = 0; i < n; ++i) {
             float t = 0.0f;
             for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) t += v32[e] * p32[col[e]];
@@ -524,6 +526,7 @@ int oracle_cg_mixed(int32_t n, const int32_t *row_ptr, const int32_t *col, const
         if (!isfinite(sigma)) { status = OR_NON_FINITE; goto finish; }
         if (!(sigma > 0.0f)) { status = OR_NOT_SPD; goto finish; }
         float alpha = rho / sigma;
+#pragma omp parallel for schedule(static)
         for (int32_t i = 0; i < n; ++i) {
             x32[i] += alpha * p32[i];
             r32[i] -= alpha * q32[i];
@@ -532,6 +535,7 @@ int oracle_cg_mixed(int32_t n, const int32_t *row_ptr, const int32_t *col, const
         float rho_new = dotf(n, r32, z32);
         float rr = dotf(n, r32, r32);
         float beta = rho_new / rho;
+#pragma omp parallel for schedule(static)
         for (int32_t i = 0; i < n; ++i) p32[i] = z32[i] + beta * p32[i];
         rho = rho_new;
         ++k;

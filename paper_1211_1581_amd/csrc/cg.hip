@@ -79,10 +79,13 @@ __device__ __forceinline__ void set_break(CgState *s, double v) {
 // ------------------------------------------------------------- set-up --
 // ------------------------------------------------------------- set-up --
 
-__global__ void k_init_state(CgState *st, int maxit, double delta, int budget) {
+// k0: passes already taken (a fallback phase continues the pass count and
+// the history of the phase before it, and maxit bounds both together)
+__global__ void k_init_state(CgState *st, int maxit, double delta, int budget, int k0) {
     if (threadIdx.x == 0) {
         CgState s;
         memset(&s, 0, sizeof s);
+        s.k = k0;
         s.maxit = maxit;
         s.delta = delta;
         s.budget = budget;
@@ -2058,7 +2061,7 @@ int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o
     int rc;
     const int budget = learned ? std::min(o->budget, o->maxit) : o->maxit;
     hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, s, w.st, learned ? budget : o->maxit,
-                       o->delta, budget);
+                       o->delta, budget, 0);
     SPCG_LAUNCH_CHECK("k_init_state");
     if (o->precond == SPCG_PRECOND_JACOBI || learned) {
         hipLaunchKernelGGL(k_diag_inv, dim3(grid_of(n, kBlock)), dim3(kBlock), 0, s, n,
@@ -2173,7 +2176,10 @@ int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o
         const int halt = h->halt;
         if (pre == SPCG_PRECOND_LEARNED &&
             (halt == H_BUDGET || halt == H_BREAK || halt == H_MAXIT)) {
-            // fall back to Jacobi-PCG: from x0 after a breakdown, else from x
+            // fall back to Jacobi-PCG: from x0 after a breakdown, else from x.
+            // Its passes follow the learned ones in the pass count and the
+            // history (its first entry replaces the learned phase's last), and
+            // maxit bounds the two phases together
             learned_iters = h->k;
             fell_back = true;
             pre = SPCG_PRECOND_JACOBI;
@@ -2182,9 +2188,8 @@ int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o
                                    (int64_t)n, (const double *)w.x0, d_x);
                 SPCG_LAUNCH_CHECK("k_copy");
             }
-            hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, s, w.st,
-                               o->maxit - (halt == H_BREAK ? 0 : learned_iters), o->delta,
-                               o->maxit);
+            hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, s, w.st, o->maxit, o->delta,
+                               o->maxit, learned_iters);
             SPCG_LAUNCH_CHECK("k_init_state");
             if ((rc = S.resid(R_INIT, nullptr))) return rc;
             if ((rc = S.start(pre))) return rc;
@@ -2222,7 +2227,7 @@ int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o
     }
     if (fell_back) {
         res->iters = learned_iters;
-        res->iters_fallback = h->k;
+        res->iters_fallback = h->k - learned_iters;
         if (status == SPCG_OK) status = SPCG_FELL_BACK;
     } else {
         res->iters = h->k;

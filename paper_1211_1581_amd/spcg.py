@@ -236,11 +236,15 @@ def cg_solve(A: CsrMatrix, b: torch.Tensor, x: torch.Tensor | None = None, *, op
     st = lib().cg_solve(A.handle, _ptr(b), _ptr(x), ctypes.byref(opts), _ptr(work.buf),
                         work.nbytes, ctypes.byref(res), hp, _stream())
     _check(st, "cg_solve")
-    k = res.iters_fallback if res.iters_fallback > 0 or st == FELL_BACK else res.iters
+    return _result(st, x, res, hist)
+
+
+def _result(st, x, res, hist):
+    k = res.iters + res.iters_fallback  # one history over both phases of a fallback
     out = dict(status=st, x=x, iters=res.iters, iters_fallback=res.iters_fallback,
                n_updates=res.n_updates, n_restarts=res.n_restarts,
                true_relres=res.true_relres, spmv_ms=res.spmv_ms, spmv_calls=res.spmv_calls)
-    if want_hist:
+    if hist is not None:
         import numpy as np
         out["hist"] = np.ctypeslib.as_array(hist)[:k + 1].copy()
     return out

@@ -90,19 +90,23 @@ def test_mixed_precision_fv():
 
 def test_mixed_precision_full_size_fv160():
     """The mixed form at the size it is timed at (160^3 diffusion, seed 3,
-    n = 4 096 000; its FP32 copy takes the 16-bit column offsets): both
-    solves reach the 1e-10 FP64 residual recomputed by the oracle, the FP32
-    inner loop needs no more passes than the FP32 band around FP64 Jacobi-PCG
-    allows, and a handful of FP64 replacements suffice."""
+    n = 4 096 000; its FP32 copy takes the 16-bit column offsets) against the
+    oracle's mixed solve on the same system: inner passes within 5 % + 3,
+    FP64 replacements within 2, the first history entries within 1e-4 (FP32
+    sums of 4 M terms), and both the mixed and the FP64 Jacobi solve at the
+    1e-10 FP64 residual recomputed by the oracle."""
     A, _, xs = I.fv_diffusion(160, 3)
     b = I.rhs_from_solution(A, xs)
+    ref = oracle.cg_mixed(A, b, tol=1e-10, maxit=20000, delta=0.1)
     g = solve(A, b, tol=1e-10, maxit=20000, precond="jacobi", precision="mixed")
     j = solve(A, b, tol=1e-10, maxit=20000, precond="jacobi")
+    assert ref["status"] == 0
     for r in (g, j):
         assert r["status"] == 0
         assert oracle.true_relres(A, b, r["x"]) <= 1e-10
-    assert g["iters"] <= 1.15 * j["iters"] + 5, (g["iters"], j["iters"])
-    assert 1 <= g["n_updates"] <= 30, g["n_updates"]
+    assert within(g["iters"], ref["iters"], 0.05, 3), (g["iters"], ref["iters"])
+    assert abs(g["n_updates"] - ref["n_updates"]) <= 2, (g["n_updates"], ref["n_updates"])
+    assert np.allclose(g["hist"][:10], ref["hist"][:10], rtol=1e-4, atol=0)
 
 def test_learned_form_with_jacobi_factor():
     A, _, xs = I.fv_diffusion(24, 5)
@@ -124,12 +128,22 @@ def test_learned_form_with_jacobi_factor():
     x = g["x"].cpu().numpy()
     assert g["status"] == 0 and within(g["iters"], ref["iters"])
     assert oracle.true_relres(A, b, x) <= 1e-10
-    # budget exhausted -> Jacobi-PCG finishes from the current x
+    # budget exhausted -> Jacobi-PCG finishes from the current x; one history
+    # over both phases (the fallback's first entry replaces the learned
+    # phase's last one)
     f = S.cg_solve(M, to_dev(b), tol=1e-10, maxit=5000, precond="learned", G=G, GT=GT, budget=5)
     assert f["status"] == S.FELL_BACK and f["iters"] == 5
     assert oracle.true_relres(A, b, f["x"].cpu().numpy()) <= 1e-10
     fo = oracle.pcg_learned(A, b, Lh2, tol=1e-10, maxit=5000, budget=5)
     assert fo["status"] == oracle.FELL_BACK and within(f["iters_fallback"], fo["iters_fallback"])
+    both = np.concatenate([fo["hist_learned"][:5], fo["hist_fallback"]])
+    assert len(f["hist"]) == f["iters"] + f["iters_fallback"] + 1
+    assert np.allclose(f["hist"][:40], both[:40], rtol=1e-6, atol=0)
+    # maxit bounds both phases together
+    c = S.cg_solve(M, to_dev(b), tol=1e-10, maxit=12, precond="learned", G=G, GT=GT, budget=5)
+    co = oracle.pcg_learned(A, b, Lh2, tol=1e-10, maxit=12, budget=5)
+    assert c["status"] == S.NOT_CONVERGED and co["status"] == oracle.NOT_CONVERGED
+    assert (c["iters"], c["iters_fallback"]) == (5, 7) == (co["iters_learned"], co["iters_fallback"])
 
 
 def _irregular_spd(n, seed):
@@ -358,15 +372,12 @@ def test_nonzero_initial_guess(form):
     # FP32 inner products of 8000 terms differ by a few units of 2^-24 times
     # sqrt(n) between summation orders, so the mixed history agrees to 1e-4
     assert np.allclose(g["hist"][:10], ref["hist"][:10], rtol=1e-4 if form == "mixed" else 1e-6)
+    # FP32 inner passes are compared with the oracle's tree-ordered FP32
+    # inner products (sequential blocks of 4096 give 114 instead of 100 passes
+    # on this system: the count depends on the FP32 sum order)
+    assert within(g["iters"], ref["iters"], 0.05, 3), (g["iters"], ref["iters"])
     if form == "mixed":
-        # FP32 inner passes: near 1e-9 the count depends on how the FP32 inner
-        # products are rounded (the oracle sums blocks of 4096 in order, the
-        # device in trees), so the band is the FP64 Jacobi count's, as in the
-        # oracle's own pin
-        j = oracle.pcg(A, b, x0=x0, precond="jacobi", **kw)
-        assert g["iters"] <= 1.15 * j["iters"] + 5 and abs(g["n_updates"] - ref["n_updates"]) <= 2
-    else:
-        assert within(g["iters"], ref["iters"], 0.05, 3)
+        assert abs(g["n_updates"] - ref["n_updates"]) <= 2
 
 
 def _sym_csr(n, diag, pairs):
@@ -408,5 +419,7 @@ def test_mixed_precision_column_layouts(case):
     g = solve(A, b, tol=1e-10, maxit=5000, precond="jacobi", precision="mixed")
     assert g["status"] == 0 and ref["status"] == 0
     assert oracle.true_relres(A, b, g["x"]) <= 1e-10
-    assert within(g["iters"], ref["iters"], 0.05, 3) or g["iters"] <= 1.15 * j64["iters"] + 5
+    assert within(g["iters"], ref["iters"], 0.05, 3), (g["iters"], ref["iters"])
+    assert abs(g["n_updates"] - ref["n_updates"]) <= 2
+    assert g["iters"] <= 1.15 * j64["iters"] + 5
     assert np.allclose(g["hist"][:5], ref["hist"][:5], rtol=1e-4)

@@ -149,15 +149,18 @@ def test_learned_cg_with_predicted_factor():
     M, g = graph(A)
     g.predict(torch.tensor(mpnn.flatten(P), dtype=torch.float32, device="cuda"))
     S = spcg()
-    out = S.cg_solve(M, to_dev(b), tol=1e-10, maxit=5000, precond="learned", G=g.G, GT=g.GT)
+    out = S.cg_solve(M, to_dev(b), tol=1e-10, maxit=5000, precond="learned", G=g.G, GT=g.GT,
+                     budget=400)
     assert out["status"] in (S.OK, S.FELL_BACK)
     assert oracle.true_relres(A, b, out["x"].cpu().numpy()) <= 1e-10
-    # the oracle solve with the same (FP32) factor takes a comparable count
+    # the oracle's learned solve with the same (FP32) factor and budget: same
+    # outcome, and each phase's pass count within the rounding band
     rp, col, gv, _ = g.factor_arrays()
     Gh = I.CSR(A.n_rows, A.n_rows, rp, col, gv.astype(np.float64))
-    ro = oracle.pcg(A, b, tol=1e-10, maxit=5000, precond="g", G=Gh)
-    if out["status"] == S.OK:
-        assert abs(out["iters"] - ro["iters"]) <= 0.02 * ro["iters"] + 2
+    ro = oracle.pcg_learned(A, b, Gh, tol=1e-10, maxit=5000, budget=400)
+    assert (out["status"] == S.FELL_BACK) == (ro["status"] == oracle.FELL_BACK)
+    assert abs(out["iters"] - ro["iters_learned"]) <= 0.02 * ro["iters_learned"] + 2
+    assert abs(out["iters_fallback"] - ro["iters_fallback"]) <= 0.02 * ro["iters_fallback"] + 2
 
 
 def test_invalid_patterns_rejected():
