@@ -43,6 +43,7 @@ extern "C" {
 #define SPCG_HIP_ERROR (-3)
 #define SPCG_NOT_SPD (-4)     /* p.Ap <= 0, r.z <= 0 or a non-positive diagonal */
 #define SPCG_NON_FINITE (-5)  /* NaN/Inf in the input or in a residual */
+#define SPCG_TOO_LARGE (-6)   /* the solve needs more than the static scratch area (cg_solve_static) */
 
 /* value types */
 #define SPCG_F64 0
@@ -197,6 +198,27 @@ size_t spcg_cg_workspace_bytes(spcg_csr_t A, const spcg_cg_opts *opts);
 int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *opts,
              void *d_work, size_t work_bytes, spcg_cg_result *res, double *h_hist,
              hipStream_t stream);
+
+/*
+ * cg_solve without a workspace argument, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments, semantics and results as cg_solve
+ * (bitwise: the same kernels run), except that the workspace is the library's
+ * static device scratch area of SPCG_STATIC_WORK_BYTES (96 MiB: the 128^3
+ * 7-point Jacobi-PCG workspace, 67.5 MB, fits; every device the library runs
+ * on holds one such area until the process ends).  The call allocates nothing:
+ * no hipMalloc, no hipFree, no event (opts->timing must be 0, else
+ * SPCG_INVALID_ARG).  A solve whose spcg_cg_workspace_bytes exceeds the area
+ * returns SPCG_TOO_LARGE (spcg_last_error gives both sizes) before any work.
+ * The current device must be the handle's (else SPCG_INVALID_ARG).  All calls
+ * on one device share that device's area: calls that overlap on one device
+ * (two host threads, or two streams whose work interleaves) race and give
+ * wrong results; the area keeps the last call's contents, and every solve
+ * initialises what it reads.  Synchronous, like cg_solve.
+ */
+#define SPCG_STATIC_WORK_BYTES ((size_t)96 << 20)
+int cg_solve_static(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *opts,
+                    spcg_cg_result *res, double *h_hist, hipStream_t stream);
 
 /* ------------------------------ factorized sparse approximate inverse (FSAI) */
 

@@ -21,10 +21,12 @@
 // t = G^T r and z = G t are two SpMV-shaped launches on the handles of G^T
 // and G, with r.z folded into the second one.
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include <hip/hip_ext.h>
 
@@ -1990,6 +1992,31 @@ static int launch_regs(Solver &S, int pre, double *d_x) {
     return SPCG_OK;
 }
 
+// ------------------------------------------------ static scratch area --
+// The workspace of cg_solve_static.  In host code `scratch` names a host-side
+// stand-in, not device memory: the device address comes from
+// hipGetSymbolAddress, once per device with that device current, and only
+// that address is passed to kernels.
+static __device__ __align__(256) char scratch[SPCG_STATIC_WORK_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[kMaxDevices] = {};
+
+static int scratch_address(int dev, void **out) {
+    if (dev < 0 || dev >= kMaxDevices) return SPCG_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_status(e, "hipGetSymbolAddress(scratch)");
+        if (!p || ((uintptr_t)p & 255) != 0) return SPCG_HIP_ERROR;
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return SPCG_OK;
+}
+
 }  // namespace spcg
 
 using namespace spcg;
@@ -2240,6 +2267,28 @@ int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o
         SPCG_TRY(hipStreamSynchronize(s));
     }
     return status;
+}
+
+int cg_solve_static(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o,
+                    spcg_cg_result *res, double *h_hist, hipStream_t s) {
+    if (!A || !o || !res) return SPCG_INVALID_ARG;
+    memset(res, 0, sizeof *res);
+    if (o->timing > 0) return SPCG_INVALID_ARG;  // timing mode creates events
+    int dev = -1;
+    SPCG_TRY(hipGetDevice(&dev));
+    if (dev != A->device) return SPCG_INVALID_ARG;
+    const size_t need = spcg_cg_workspace_bytes(A, o);
+    if (need > SPCG_STATIC_WORK_BYTES) {
+        char msg[160];
+        snprintf(msg, sizeof msg, "cg_solve_static: the solve needs %zu bytes of workspace, the static "
+                 "scratch area holds %zu", need, (size_t)SPCG_STATIC_WORK_BYTES);
+        set_error_text(msg);
+        return SPCG_TOO_LARGE;
+    }
+    void *work = nullptr;
+    const int rc = scratch_address(dev, &work);
+    if (rc) return rc;
+    return cg_solve(A, d_b, d_x, o, work, SPCG_STATIC_WORK_BYTES, res, h_hist, s);
 }
 
 }  // extern "C"

@@ -21,6 +21,8 @@ void set_error(hipError_t e, const char *what) {
     snprintf(g_err, sizeof g_err, "%s: %s", what, hipGetErrorString(e));
 }
 
+void set_error_text(const char *text) { snprintf(g_err, sizeof g_err, "%s", text); }
+
 int hip_status(hipError_t e, const char *what) {
     set_error(e, what);
     return SPCG_HIP_ERROR;
@@ -203,6 +205,7 @@ const char *spcg_status_str(int status) {
         case SPCG_HIP_ERROR: return "HIP_ERROR";
         case SPCG_NOT_SPD: return "NOT_SPD";
         case SPCG_NON_FINITE: return "NON_FINITE";
+        case SPCG_TOO_LARGE: return "TOO_LARGE";
         default: return "UNKNOWN";
     }
 }

@@ -79,6 +79,7 @@ inline int64_t matrix_bytes(int64_t n_rows, int64_t nnz, int val_bytes) {
 #define SPCG_ROWBLOCK_KERNEL __global__ void __launch_bounds__(256)
 
 void set_error(hipError_t e, const char *what);
+void set_error_text(const char *text);
 int hip_status(hipError_t e, const char *what);
 
 #define SPCG_TRY(expr)                                   \

@@ -16,7 +16,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libspcg.so")
 
 OK, NOT_CONVERGED, FELL_BACK = 0, 1, 2
-INVALID_ARG, INVALID_CSR, HIP_ERROR, NOT_SPD, NON_FINITE = -1, -2, -3, -4, -5
+INVALID_ARG, INVALID_CSR, HIP_ERROR, NOT_SPD, NON_FINITE, TOO_LARGE = -1, -2, -3, -4, -5, -6
+STATIC_WORK_BYTES = 96 << 20  # SPCG_STATIC_WORK_BYTES
 F64, F32 = 0, 1
 PRECOND = {"none": 0, "jacobi": 1, "learned": 2}
 PRECISION = {"f64": 0, "mixed": 1}
@@ -76,6 +77,8 @@ def lib():
         L.spcg_cg_workspace_bytes.restype = sz
         L.cg_solve.argtypes = [P, P, P, ctypes.POINTER(CgOpts), P, sz,
                                ctypes.POINTER(CgResult), P, P]
+        L.cg_solve_static.argtypes = [P, P, P, ctypes.POINTER(CgOpts),
+                                      ctypes.POINTER(CgResult), P, P]
         _lib = L
     return _lib
 
@@ -236,6 +239,24 @@ def cg_solve(A: CsrMatrix, b: torch.Tensor, x: torch.Tensor | None = None, *, op
     st = lib().cg_solve(A.handle, _ptr(b), _ptr(x), ctypes.byref(opts), _ptr(work.buf),
                         work.nbytes, ctypes.byref(res), hp, _stream())
     _check(st, "cg_solve")
+    return _result(st, x, res, hist)
+
+
+def cg_solve_static(A: CsrMatrix, b: torch.Tensor, x: torch.Tensor | None = None, *, opts=None,
+                    want_hist=True, **kw):
+    """cg_solve on the library's static scratch area (cg_solve_static): no
+    workspace argument, no device allocation in the call.  Same result dict."""
+    if opts is None:
+        opts = cg_opts(**kw)
+    if x is None:
+        x = torch.zeros_like(b)
+    assert b.dtype == torch.float64 and x.dtype == torch.float64 and x.is_contiguous()
+    res = CgResult()
+    hist = (ctypes.c_double * (opts.maxit + 1))() if want_hist else None
+    hp = ctypes.cast(hist, ctypes.c_void_p) if want_hist else ctypes.c_void_p(0)
+    st = lib().cg_solve_static(A.handle, _ptr(b), _ptr(x), ctypes.byref(opts),
+                               ctypes.byref(res), hp, _stream())
+    _check(st, "cg_solve_static")
     return _result(st, x, res, hist)
 
 
