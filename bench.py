@@ -7,18 +7,23 @@ device-side stop test and the final FP64 residual check.  Inputs (matrix, b,
 x0 = 0) are resident in HBM before the timed region.
 
 Prints ONE JSON line.  `value` is the hot path's algorithmic HBM throughput
-(passes x algorithmic bytes per pass / wall time of the solves); the roofline
-object reports the dominant kernel (SpMV + p.q) from HIP events recorded
-around each of its launches on the solve's stream; `cpu_baseline` times the
-FP64 oracle on the host cores on a bounded sample of the same workload;
+(passes x algorithmic bytes per pass / wall time of the solves).  `roofline`
+reports the product y = A x of the same matrix read from HBM (rotating device
+copies that together exceed the 256 MB memory-side cache), timed by HIP events
+on its stream; `roofline_in_cg` the same product inside the pass loop, where A
+stays in that cache.  Every result carries its error against the FP64 oracle
+(`err_vs_oracle`).  `cpu_baseline` times the oracle on the host cores (all
+threads, pinned, and one thread) on a bounded sample of the same workload.
 `forms` gives the time to tolerance of the mixed-precision and learned forms
-beside plain FP64 Jacobi-PCG on their own matrices.
+beside plain FP64 Jacobi-PCG on their own matrices, the learned one also over
+the 16 unseen evaluation matrices.
 
-`workloads` adds plain CG on the 2-D Poisson 64^2 system and the cold
-standalone SpMV of the other matrices and precisions; `copy_gbs` is the
-measured device-copy ceiling.
+`workloads` adds plain CG on the 2-D Poisson 64^2 system, the single-reduction
+loop, and the cold standalone SpMV of the other matrices and precisions;
+`copy_gbs` and `read_gbs` are the measured streaming ceilings.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--cpu-seconds 15] [--no-forms]
+                    [--no-eval16] [--no-cpu] [--spmv CASE] [--form mixed|learned] [--tables]
 """
 from __future__ import annotations
 
@@ -32,6 +37,13 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# OpenMP threads of the CPU baseline pinned one per core, packed (OpenMP reads
+# these when its runtime starts, so before torch or the oracle loads it; the
+# runtime then binds the main thread to the first core, so the host's CPU
+# count is taken here)
+os.environ.setdefault("OMP_PLACES", "cores")
+os.environ.setdefault("OMP_PROC_BIND", "close")
+HOST_CPUS = len(os.sched_getaffinity(0))
 
 PEAK_HBM_GBS = 8000.0
 METRIC = "SpMV GB/s (% HBM peak); CG time to 1e-10 rel. residual, learned vs plain"
@@ -50,8 +62,10 @@ def jpcg_pass_bytes(n, nnz):
     return spmv_bytes(n, nnz) + 80 * n
 
 
-# sources of the CG pass kernels (k_cg_q and the kernels around it)
+# sources of the CG pass kernels (k_cg_q and the kernels around it) and of the
+# standalone product (k_spmv)
 CG_SOURCES = ("internal.h", "cg.hip")
+SPMV_SOURCES = ("internal.h", "csr.hip")
 
 
 def kernel_source_hash(files=None):
@@ -72,7 +86,7 @@ def kernel_source_hash(files=None):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, sources):
     """HBM bytes per launch from committed rocprofv3 counter summaries, if they
     were taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
@@ -80,31 +94,46 @@ def measured_traffic(kernel, workload):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("source_hash") != kernel_source_hash(CG_SOURCES):
+    if d.get("source_hash") != kernel_source_hash(sources):
         return None
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(A, b, seconds):
-    """The oracle (plain FP64 C, OpenMP rows) on a bounded sample: as many
-    Jacobi-PCG passes of the same system as fit in about `seconds`."""
+def _oracle_jpcg_sample(A, b, seconds, full_passes):
+    """Jacobi-PCG passes of the oracle on A x = b for about `seconds`: (passes, s)."""
     import oracle
-    n, nnz = A.n_rows, A.nnz
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    # calibrate with a short run, then size the sample
     t = time.perf_counter()
     r = oracle.pcg(A, b, tol=0.0, maxit=3, precond="jacobi")
-    dt = time.perf_counter() - t
-    per = dt / max(r["iters"], 1)
-    passes = int(max(5, min(425, seconds / max(per, 1e-6))))
+    per = (time.perf_counter() - t) / max(r["iters"], 1)
+    passes = int(max(3, min(full_passes, seconds / max(per, 1e-6))))
     t = time.perf_counter()
     r = oracle.pcg(A, b, tol=0.0, maxit=passes, precond="jacobi")
-    dt = time.perf_counter() - t
-    gbs = r["iters"] * jpcg_pass_bytes(n, nnz) / dt / 1e9
+    return r["iters"], time.perf_counter() - t
+
+
+def cpu_baseline(A, b, seconds, full_passes):
+    """The oracle (plain FP64 C, OpenMP rows, threads pinned one per core) on a
+    bounded sample of the same workload: as many Jacobi-PCG passes of the same
+    system as fit in about `seconds` on all threads, then in about a third of
+    that on one thread; time to tolerance extrapolated to the full pass count."""
+    import oracle
+    n, nnz = A.n_rows, A.nnz
+    threads = oracle.set_threads(0)
+    k, dt = _oracle_jpcg_sample(A, b, seconds, full_passes)
+    gbs = k * jpcg_pass_bytes(n, nnz) / dt / 1e9
+    oracle.set_threads(1)
+    k1, dt1 = _oracle_jpcg_sample(A, b, seconds / 3.0, full_passes)
+    oracle.set_threads(threads)
     out = {"value": round(gbs, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
-           "sample": f"{r['iters']} Jacobi-PCG passes (with set-up) of the 128^3 Poisson "
-                     f"system in {dt:.1f} s; a full solve takes 425 passes",
-           "est_time_to_tol_s": round(dt / r["iters"] * 425, 2)}
+           "sample": f"{k} Jacobi-PCG passes (with set-up) of the 128^3 Poisson system in "
+                     f"{dt:.1f} s on {threads} threads, {k1} passes in {dt1:.1f} s on one "
+                     f"thread; a full solve takes {full_passes} passes",
+           "est_time_to_tol_s": round(dt / k * full_passes, 2),
+           "one_thread": {"value": round(k1 * jpcg_pass_bytes(n, nnz) / dt1 / 1e9, 3),
+                          "est_time_to_tol_s": round(dt1 / k1 * full_passes, 2)},
+           "omp": {"OMP_PLACES": os.environ.get("OMP_PLACES"),
+                   "OMP_PROC_BIND": os.environ.get("OMP_PROC_BIND"),
+                   "host_cpus_in_affinity": HOST_CPUS}}
     out["spmv_gbs"] = cpu_spmv_rates(A)
     return out
 
@@ -148,6 +177,8 @@ def main():
                          "hardware byte counters)")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the mixed-precision (160^3) and learned (128^3) time-to-tolerance")
+    ap.add_argument("--no-eval16", action="store_true",
+                    help="skip the learned form over the 16 unseen 128^3 matrices")
     ap.add_argument("--tables", action="store_true",
                     help="run the paper's own input tables instead (SpMV over the Table 1 "
                          "matrices, plain CG over the Table 2 banded systems) beside the "
@@ -155,6 +186,9 @@ def main():
     ap.add_argument("--form", choices=("mixed", "learned"), default=None,
                     help="run only this solver form beside FP64 Jacobi-PCG and print its "
                          "record (for kernel traces of one workload)")
+    ap.add_argument("--spmv", choices=SPMV_CASES, default=None,
+                    help="run only the cold standalone SpMV of this matrix and precision and "
+                         "print its record (for kernel traces and counters of one product)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -169,6 +203,15 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calib and args.spmv:
+        src = torch.ones(2 ** 25, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.spmv:
+        print(json.dumps(spmv_case(args.spmv)), flush=True)
+        return
     if args.form:
         print(json.dumps(forms(args, only=args.form)), flush=True)
         return
@@ -232,24 +275,13 @@ def main():
     b_spmv = spmv_bytes(n, nnz)
     avg_us = spmv_ms * 1e3 / max(spmv_calls, 1)
     achieved = b_spmv / (avg_us * 1e-6) / 1e9
-    traffic = measured_traffic("k_cg_q", "poisson128")
+    traffic_cg = measured_traffic("k_cg_q", "poisson128", CG_SOURCES)
     matrix_mb = (nnz * 12 + 4 * (n + 1)) / 1e6
+    err_jpcg = oracle_errors(A, b, xs, x.cpu().numpy())
 
-    # standalone SpMV, cold: rotate over 3 copies (651 MB > the 256 MB MALL)
-    copies = [M] + [spcg.CsrMatrix.from_host(A, device=dev) for _ in range(2)]
-    xt = torch.as_tensor(xs, device=dev)
-    y = torch.empty(n, dtype=torch.float64, device=dev)
-    for i in range(6):
-        spcg.spmv_csr(copies[i % 3], xt, y)
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(30)]
-    for i, (e0, e1) in enumerate(evs):
-        e0.record()
-        spcg.spmv_csr(copies[i % 3], xt, y)
-        e1.record()
-    torch.cuda.synchronize()
-    cold_us = float(np.median([e0.elapsed_time(e1) * 1e3 for e0, e1 in evs]))
-    del copies
+    # the standalone product of the same matrix, cold: rotating over device
+    # copies whose total exceeds the 256 MB MALL, so every launch reads A from HBM
+    cold = cold_spmv(A, xs, "f64", first=M)
 
     line = {
         "metric": METRIC,
@@ -270,21 +302,34 @@ def main():
         "time_to_tol_ms": round(ms_per_step, 3),
         "iters": iters,
         "true_relres": outs[-1]["true_relres"],
+        "err_vs_oracle": err_jpcg,
         "analysis_ms": round(analysis_ms, 2),
         "analysis_device_ms": round(analysis_device_ms, 3),
-        "spmv_in_cg_gbs": round(achieved, 1),
-        "spmv_in_cg_pct_peak": round(100 * achieved / PEAK_HBM_GBS, 1),
-        "spmv_cold_gbs": round(b_spmv / (cold_us * 1e-6) / 1e9, 1),
-        "spmv_cold_us": round(cold_us, 2),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": traffic, "kernel": "k_cg_q (SpMV q = A p with p.q partials)",
-                     "bytes_per_launch": b_spmv, "avg_launch_us": round(avg_us, 2),
-                     "launches": spmv_calls,
-                     "note": ("A's streams (%.1f MB) fit the cache-allocating limit (%d MiB), so A stays in "
-                              "the 256 MB MALL across passes; the cold HBM rate is spmv_cold_gbs"
-                              % (matrix_mb, spcg.keep_bytes() >> 20)) if matrix_mb * 1e6 <= spcg.keep_bytes()
-                             else "A streams from HBM with non-temporal loads"},
+        "spmv_cold_gbs": cold["gbs"],
+        "spmv_cold_us": cold["us"],
+        "roofline": {"bound": "hbm", "achieved": cold["gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(cold["gbs"] / PEAK_HBM_GBS, 4),
+                     "traffic": measured_traffic("k_spmv", "poisson128", SPMV_SOURCES),
+                     "kernel": "k_spmv<double> (y = A x, 128^3 Poisson, A read from HBM)",
+                     "bytes_per_launch": b_spmv, "avg_launch_us": cold["us"],
+                     "launches": cold["launches"],
+                     "timing": ("HIP events on the launch stream around %d back-to-back launches "
+                                "rotating over %d device copies of A (%.0f MB in all, more than the "
+                                "256 MB MALL), after %d warm-up launches"
+                                % (cold["launches"], cold["copies"],
+                                   cold["copies"] * matrix_mb, cold["warmup"])),
+                     "err_vs_oracle": cold["err_vs_oracle"]},
+        "roofline_in_cg": {"bound": "mall", "achieved": round(achieved, 1), "unit": "GB/s",
+                           "traffic": traffic_cg,
+                           "kernel": "k_cg_q (q = A p with p.q partials, inside the Jacobi-PCG pass)",
+                           "bytes_per_launch": b_spmv, "avg_launch_us": round(avg_us, 2),
+                           "launches": spmv_calls,
+                           "note": ("A's streams (%.1f MB) fit the cache-allocating limit (%d MiB), so "
+                                    "A stays in the 256 MB MALL across passes: an algorithmic rate of "
+                                    "a cache-served product, not a share of HBM peak"
+                                    % (matrix_mb, spcg.keep_bytes() >> 20))
+                           if matrix_mb * 1e6 <= spcg.keep_bytes()
+                           else "A streams from HBM with non-temporal loads"},
     }
     line["copy_gbs"] = copy_rate()
     line["read_gbs"] = read_rate()
@@ -292,8 +337,18 @@ def main():
         line["workloads"] = workloads(A, xs)
         line["forms"] = forms(args)
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(A, b, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(A, b, args.cpu_seconds, iters)
     print(json.dumps(line), flush=True)
+
+
+def oracle_errors(A, b, xstar, x):
+    """Error of a device solution x against the FP64 oracle: ||b - A x|| / ||b||
+    recomputed by the oracle, and the forward error against x*."""
+    import numpy as np
+
+    import oracle
+    return {"true_relres": oracle.true_relres(A, b, x),
+            "x_err": float(np.linalg.norm(x - xstar) / np.linalg.norm(xstar))}
 
 
 def read_rate():
@@ -338,35 +393,79 @@ def copy_rate():
     return round(2 * 2 ** 29 / float(np.median(ts)) / 1e9, 1)
 
 
-def cold_spmv(A, x, dtype, reps=30):
-    """Median duration of spmv_csr rotating over enough device copies of A
-    that their total exceeds 600 MB (more than twice the 256 MB last-level
-    cache), so every launch streams the matrix from HBM."""
+def cold_spmv(A, x, dtype, launches=60, first=None):
+    """Cold standalone SpMV: spmv_csr rotating over enough device copies of A
+    that their total exceeds 600 MB (more than twice the 256 MB MALL), so every
+    launch streams the matrix from HBM.  `us` = the average duration of
+    `launches` back-to-back launches between two HIP events on the launch
+    stream (after warm-up launches); `us_bracketed` = the median of launches
+    bracketed one by one (each then also carries the event and launch gaps).
+    The last product is compared with the FP64 oracle (FP32: also with the
+    oracle's FP64 sum of the same FP32 inputs)."""
     import numpy as np
     import torch
 
+    import oracle
     from paper_1211_1581_amd import spcg
     tdt = torch.float64 if dtype == "f64" else torch.float32
     sv = 8 if dtype == "f64" else 4
     b = spmv_bytes(A.n_rows, A.nnz, sv=sv, sx=sv)
     ncopy = max(3, -(-600_000_000 // b))
-    copies = [spcg.CsrMatrix.from_host(A, dtype=tdt) for _ in range(ncopy)]
+    copies = ([first] if first is not None else []) + \
+        [spcg.CsrMatrix.from_host(A, dtype=tdt) for _ in range(ncopy - (first is not None))]
     xt = torch.as_tensor(x).to(tdt).cuda()
     y = torch.empty(A.n_rows, dtype=tdt, device="cuda")
-    for i in range(2 * ncopy):
+    warm = 2 * ncopy
+    for i in range(warm):
         spcg.spmv_csr(copies[i % ncopy], xt, y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(launches):
+        spcg.spmv_csr(copies[i % ncopy], xt, y)
+    e1.record()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(reps)]
-    for i, (e0, e1) in enumerate(evs):
-        e0.record()
+           for _ in range(30)]
+    for i, (f0, f1) in enumerate(evs):
+        f0.record()
         spcg.spmv_csr(copies[i % ncopy], xt, y)
-        e1.record()
+        f1.record()
     torch.cuda.synchronize()
-    us = float(np.median([e0.elapsed_time(e1) * 1e3 for e0, e1 in evs]))
+    us = e0.elapsed_time(e1) * 1e3 / launches
+    us_br = float(np.median([f0.elapsed_time(f1) * 1e3 for f0, f1 in evs]))
+    yh = y.cpu().numpy().astype(np.float64)
     del copies
+    if dtype == "f64":
+        ref = oracle.spmv(A, x)
+        err = {"rel_err": float(np.linalg.norm(yh - ref) / np.linalg.norm(ref))}
+    else:
+        v32 = np.asarray(A.vals, dtype=np.float32)
+        x32 = np.asarray(x, dtype=np.float32)
+        ref32 = oracle.spmv_f32in(A, v32, x32)
+        ref = oracle.spmv(A, x)
+        err = {"rel_err_same_fp32_inputs": float(np.linalg.norm(yh - ref32) / np.linalg.norm(ref32)),
+               "rel_err_vs_fp64_product": float(np.linalg.norm(yh - ref) / np.linalg.norm(ref))}
     gbs = b / (us * 1e-6) / 1e9
-    return {"us": round(us, 2), "gbs": round(gbs, 1), "pct_peak": round(100 * gbs / PEAK_HBM_GBS, 1),
-            "bytes": b, "copies": ncopy}
+    return {"us": round(us, 2), "us_bracketed": round(us_br, 2), "gbs": round(gbs, 1),
+            "pct_peak": round(100 * gbs / PEAK_HBM_GBS, 1), "bytes": b, "copies": ncopy,
+            "launches": launches, "warmup": warm, "err_vs_oracle": err}
+
+
+SPMV_CASES = ("poisson128_f64", "poisson128_f32", "lognormal_f64", "lognormal_f32")
+
+
+def spmv_case(name):
+    """Cold standalone SpMV of one matrix (the 128^3 Poisson matrix with the
+    seed-1 vector, or the lognormal irregular matrix) in one precision."""
+    from paper_1211_1581_amd import inputs as I
+    mat, dtype = name.split("_")
+    if mat == "poisson128":
+        A = I.poisson3d(128)
+        x = I.uniform_vector(A.n_rows, 1)
+    else:
+        A, x = I.lognormal_irregular()
+    r = cold_spmv(A, x, dtype)
+    r["case"] = name
+    return r
 
 
 def workloads(A128, x128):
@@ -384,20 +483,22 @@ def workloads(A128, x128):
     M = spcg.CsrMatrix.from_host(P)
     bt = torch.as_tensor(b, device="cuda")
     opts = spcg.cg_opts(tol=1e-10, maxit=2000, precond="none")
-    r = _time_solve(M, bt, opts, spcg.CgWorkspace(M, opts), reps=10)
+    r = _time_solve(M, bt, opts, spcg.CgWorkspace(M, opts), reps=10, check=(P, b, I.uniform_vector(P.n_rows, 0)))
     out["cg_poisson2d_64"] = {"workload": "2-D 5-point Poisson 64^2, plain CG to 1e-10 (one "
                                           "workgroup holds the whole loop)",
                               "ms": r["ms"], "iters": r["iters"],
                               "us_per_pass": round(1e3 * r["ms"] / max(r["iters"], 1), 2),
-                              "true_relres": r["true_relres"], "status": r["status"]}
+                              "true_relres": r["true_relres"], "status": r["status"],
+                              "err_vs_oracle": r["err_vs_oracle"]}
     del M, bt
     # the single-reduction (Chronopoulos-Gear) variant on the headline system
     M = spcg.CsrMatrix.from_host(A128)
-    bt = torch.as_tensor(I.rhs_from_solution(A128, x128), device="cuda")
+    b128 = I.rhs_from_solution(A128, x128)
+    bt = torch.as_tensor(b128, device="cuda")
     res = {}
     for variant in ("standard", "single_reduction"):
         opts = spcg.cg_opts(tol=1e-10, maxit=20000, precond="jacobi", variant=variant)
-        res[variant] = _time_solve(M, bt, opts, spcg.CgWorkspace(M, opts))
+        res[variant] = _time_solve(M, bt, opts, spcg.CgWorkspace(M, opts), check=(A128, b128, x128))
     out["jpcg_poisson128_variants"] = {
         "workload": "3-D Poisson 128^3 FP64 Jacobi-PCG to 1e-10: the two-reduction loop vs the "
                     "single-reduction (Chronopoulos-Gear) loop",
@@ -480,7 +581,9 @@ def tables():
     return out
 
 
-def _time_solve(M, bt, opts, work, reps=3, pre=None):
+def _time_solve(M, bt, opts, work, reps=3, pre=None, check=None):
+    """Best of `reps` timed solves after one warm-up.  check = (A, b, x*) on the
+    host: the last solution's errors against the FP64 oracle."""
     import torch
 
     from paper_1211_1581_amd import spcg
@@ -496,8 +599,11 @@ def _time_solve(M, bt, opts, work, reps=3, pre=None):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         best = dt if best is None else min(best, dt)
-    return {"ms": round(1e3 * best, 2), "iters": r["iters"], "iters_fallback": r["iters_fallback"],
-            "n_updates": r["n_updates"], "true_relres": r["true_relres"], "status": r["status"]}
+    out = {"ms": round(1e3 * best, 2), "iters": r["iters"], "iters_fallback": r["iters_fallback"],
+           "n_updates": r["n_updates"], "true_relres": r["true_relres"], "status": r["status"]}
+    if check is not None:
+        out["err_vs_oracle"] = oracle_errors(check[0], check[1], check[2], x.cpu().numpy())
+    return out
 
 
 def forms(args, only=None):
@@ -505,12 +611,15 @@ def forms(args, only=None):
     beside FP64 Jacobi-PCG on the same matrix (best of 3 after a warm-up):
     mixed precision on the 160^3 finite-volume diffusion matrix (seed 3), and
     the learned factor (committed weights, prediction included) on the first
-    unseen 128^3 diffusion matrix (seed 1000)."""
+    unseen 128^3 diffusion matrix (seed 1000), then on all 16 unseen ones
+    (seeds 1000-1015, best of 2)."""
     out = {}
     if only != "learned":
         out["mixed_vs_jacobi"] = _mixed_form()
     if only != "mixed":
         out["learned_vs_jacobi"] = _learned_form()
+        if not getattr(args, "no_eval16", False):
+            out["learned_eval_16"] = _learned_eval(range(1000, 1016))
     return out
 
 
@@ -524,37 +633,55 @@ def _mixed_form():
     M = spcg.CsrMatrix.from_host(A, device=dev)
     bt = torch.as_tensor(I.rhs_from_solution(A, xs), device=dev)
     res = {}
+    b = I.rhs_from_solution(A, xs)
     for prec in ("f64", "mixed"):
         opts = spcg.cg_opts(tol=1e-10, maxit=20000, precond="jacobi", precision=prec)
-        res[prec] = _time_solve(M, bt, opts, spcg.CgWorkspace(M, opts))
+        res[prec] = _time_solve(M, bt, opts, spcg.CgWorkspace(M, opts), check=(A, b, xs))
     return {"workload": "FV diffusion 160^3 (n=4096000), GRF seed 3; FP64 "
                         "Jacobi-PCG vs FP32-inner / FP64 reliable-update",
             "jacobi_f64": res["f64"], "mixed": res["mixed"],
             "speedup": round(res["f64"]["ms"] / res["mixed"]["ms"], 3)}
 
 
-def _learned_form():
+def _learned_setup(N, seed):
     import torch
 
     from paper_1211_1581_amd import inputs as I
-    from paper_1211_1581_amd import spcg, train
-    dev = torch.device("cuda:0")
-    A, _, xs = I.fv_diffusion(128, 1000)
-    M = spcg.CsrMatrix.from_host(A, device=dev)
-    bt = torch.as_tensor(I.rhs_from_solution(A, xs), device=dev)
-    w, meta = train.load_weights()
-    wt = torch.tensor(w, device=dev)
-    g = spcg.MpnnGraph(M)
-    budget = train.budget_for(128, meta.get("mean_learned_passes_48", 117.0))
+    from paper_1211_1581_amd import spcg
+    A, _, xs = I.fv_diffusion(N, seed)
+    b = I.rhs_from_solution(A, xs)
+    M = spcg.CsrMatrix.from_host(A)
+    return A, xs, b, M, torch.as_tensor(b, device="cuda")
+
+
+def _learned_solves(A, xs, b, M, bt, w, budget, ws=None, reps=3):
+    """Jacobi-PCG, the learned factor (prediction included) and FSAI (set-up
+    included) on one system, each with its oracle errors."""
+    from paper_1211_1581_amd import spcg
+    g = spcg.MpnnGraph(M, ws=ws)
     oj = spcg.cg_opts(tol=1e-10, maxit=20000, precond="jacobi")
     ol = spcg.cg_opts(tol=1e-10, maxit=20000, precond="learned", G=g.G, GT=g.GT, budget=budget)
-    rj = _time_solve(M, bt, oj, spcg.CgWorkspace(M, oj))
-    rl = _time_solve(M, bt, ol, spcg.CgWorkspace(M, ol), pre=lambda: g.predict(wt))
+    chk = (A, b, xs)
+    rj = _time_solve(M, bt, oj, spcg.CgWorkspace(M, oj), reps=reps, check=chk)
+    rl = _time_solve(M, bt, ol, spcg.CgWorkspace(M, ol), reps=reps, pre=lambda: g.predict(w),
+                     check=chk)
     # classical FSAI on the same pattern (set-up included), the non-learned comparator
     gf = spcg.MpnnGraph(M, ws=g.ws)
     of = spcg.cg_opts(tol=1e-10, maxit=20000, precond="learned", G=gf.G, GT=gf.GT, budget=20000)
-    rf = _time_solve(M, bt, of, spcg.CgWorkspace(M, of),
-                     pre=lambda: spcg.fsai_values(M, gf.G, gf.GT))
+    rf = _time_solve(M, bt, of, spcg.CgWorkspace(M, of), reps=reps,
+                     pre=lambda: spcg.fsai_values(M, gf.G, gf.GT), check=chk)
+    return rj, rl, rf, g.ws
+
+
+def _learned_form():
+    import torch
+
+    from paper_1211_1581_amd import train
+    A, xs, b, M, bt = _learned_setup(128, 1000)
+    w, meta = train.load_weights()
+    wt = torch.tensor(w, device="cuda")
+    budget = train.budget_for(128, meta.get("mean_learned_passes_48", 117.0))
+    rj, rl, rf, _ = _learned_solves(A, xs, b, M, bt, wt, budget)
     return {"workload": "FV diffusion 128^3 (n=2097152), unseen seed 1000; "
                         "FP64 Jacobi-PCG vs learned G G^T (prediction "
                         "included, training excluded) and FSAI G G^T on the same "
@@ -562,6 +689,43 @@ def _learned_form():
             "jacobi_f64": rj, "learned": rl, "fsai": rf, "budget": budget,
             "speedup": round(rj["ms"] / rl["ms"], 3),
             "fsai_speedup": round(rj["ms"] / rf["ms"], 3)}
+
+
+def _learned_eval(seeds):
+    """The learned factor over the unseen 128^3 evaluation matrices: per seed
+    the passes and times (best of 2) of Jacobi-PCG, the learned PCG
+    (prediction included) and FSAI, with the oracle's residual of each
+    solution; then the means and the fallback count."""
+    import numpy as np
+    import torch
+
+    from paper_1211_1581_amd import train
+    w, meta = train.load_weights()
+    wt = torch.tensor(w, device="cuda")
+    budget = train.budget_for(128, meta.get("mean_learned_passes_48", 117.0))
+    rows, ws = [], None
+    for seed in seeds:
+        A, xs, b, M, bt = _learned_setup(128, seed)
+        rj, rl, rf, ws = _learned_solves(A, xs, b, M, bt, wt, budget, ws=ws, reps=2)
+        rows.append({"seed": seed,
+                     "jacobi": [rj["iters"], rj["ms"]],
+                     "learned": [rl["iters"], rl["iters_fallback"], rl["ms"]],
+                     "fsai": [rf["iters"], rf["ms"]],
+                     "oracle_true_relres_max": max(r["err_vs_oracle"]["true_relres"]
+                                                   for r in (rj, rl, rf)),
+                     "status": [rj["status"], rl["status"], rf["status"]]})
+        del M, bt
+    mean = lambda k, i: round(float(np.mean([r[k][i] for r in rows])), 2)
+    return {"workload": "FV diffusion 128^3, unseen seeds %d-%d; per seed [passes, ms] for "
+                        "Jacobi and FSAI, [learned passes, fallback passes, ms] for the learned "
+                        "form (prediction included)" % (seeds[0], seeds[-1]),
+            "budget": budget, "rows": rows,
+            "mean_passes": {"jacobi": mean("jacobi", 0), "learned": mean("learned", 0),
+                            "fsai": mean("fsai", 0)},
+            "mean_ms": {"jacobi": mean("jacobi", 1), "learned": mean("learned", 2),
+                        "fsai": mean("fsai", 1)},
+            "fallbacks": sum(1 for r in rows if r["learned"][1] > 0 or r["status"][1] == 2),
+            "oracle_true_relres_max": max(r["oracle_true_relres_max"] for r in rows)}
 
 
 if __name__ == "__main__":

@@ -259,30 +259,32 @@ int spcg_fsai_values(spcg_csr_t A, spcg_csr_t G, spcg_csr_t GT, hipStream_t stre
 #define SPCG_MPNN_TRAIN 1
 
 typedef struct spcg_mpnn *spcg_mpnn_t;
-typedef struct spcg_mpnn_ws *spcg_mpnn_ws_t;
 
 /*
  * Per-matrix network state for A (F64 handle, square, sorted columns, one
  * positive diagonal entry per row, structurally symmetric): edge lists,
  * reverse-edge map, the patterns of G = tril and G^T = triu, features, and
  * the factor values.  With SPCG_MPNN_TRAIN it also keeps an FP32 copy of A's
- * values for the probe loss.  A must outlive the graph.  Allocates;
- * synchronous.  SPCG_INVALID_CSR for a pattern that breaks the rules above,
- * SPCG_NOT_SPD for a non-positive diagonal.
+ * values for the probe loss.  A must outlive the graph.  Allocates these
+ * per-matrix arrays once (like spcg_csr_create); the network calls below run
+ * on a caller workspace.  Synchronous.  SPCG_INVALID_CSR for a pattern that
+ * breaks the rules above, SPCG_NOT_SPD for a non-positive diagonal.
  */
 int spcg_mpnn_create(spcg_mpnn_t *out, spcg_csr_t A, int32_t flags, hipStream_t stream);
 int spcg_mpnn_destroy(spcg_mpnn_t g);
 int spcg_mpnn_info(spcg_mpnn_t g, int64_t *n_edges, int64_t *nnz_factor);
 
 /*
- * Activation and gradient buffers for graphs of up to max_rows rows and
- * max_edges off-diagonal entries, shareable by many graphs used one at a time
- * on one stream.  SPCG_MPNN_TRAIN keeps every layer's activations and the
- * backward scratch (needed by spcg_mpnn_loss_grad).  Allocates.
+ * Bytes of device workspace (256-byte aligned) that spcg_mpnn_predict needs
+ * for graphs of up to max_rows rows and max_edges off-diagonal entries: BF16
+ * node and edge activations of two alternating layers, the BF16 weight copies
+ * and a few scalars.  With SPCG_MPNN_TRAIN: what spcg_mpnn_loss_grad needs
+ * (every layer's activations, the FP32 backward scratch, the probe products
+ * and the per-workgroup partials; about 0.6 GB for a 48^3 matrix).  One
+ * workspace serves many graphs used one at a time on one stream.  0 for
+ * invalid sizes.
  */
-int spcg_mpnn_ws_create(spcg_mpnn_ws_t *out, int64_t max_rows, int64_t max_edges, int32_t flags,
-                        hipStream_t stream);
-int spcg_mpnn_ws_destroy(spcg_mpnn_ws_t ws);
+size_t spcg_mpnn_workspace_bytes(int64_t max_rows, int64_t max_edges, int32_t flags);
 
 /* Handles of G and G^T (FP32 values owned by the graph, filled by predict),
  * ready for spcg_cg_opts.G / .GT.  Valid until spcg_mpnn_destroy. */
@@ -294,18 +296,23 @@ int spcg_mpnn_factor_arrays(spcg_mpnn_t g, const int32_t **d_row_ptr, const int3
                             const float **d_vals, const float **d_t_vals);
 
 /* Inference: G and G^T values from the weights d_w (float[SPCG_MPNN_PARAMS]).
- * ws must fit the graph (else SPCG_INVALID_ARG).  Asynchronous. */
-int spcg_mpnn_predict(spcg_mpnn_t g, spcg_mpnn_ws_t ws, const float *d_w, hipStream_t stream);
+ * d_work: at least spcg_mpnn_workspace_bytes(n, n_edges, 0) bytes, 256-byte
+ * aligned, caller-owned (else SPCG_INVALID_ARG).  Asynchronous. */
+int spcg_mpnn_predict(spcg_mpnn_t g, const float *d_w, void *d_work, size_t work_bytes,
+                      hipStream_t stream);
 
 /*
  * Probe loss L = sum_k ||G^T A G v_k - v_k||^2 / (n m) for the m probe vectors
  * d_probes (float[m][n], 1 <= m <= 64) and, if d_grad is not NULL, dL/dw into
- * d_grad (float[SPCG_MPNN_PARAMS], overwritten).  Graph and workspace need
- * SPCG_MPNN_TRAIN.  Runs the forward pass too (G and G^T values are updated).
- * h_loss: NULL or receives L (then the call synchronises `stream`).
+ * d_grad (float[SPCG_MPNN_PARAMS], overwritten).  The graph needs
+ * SPCG_MPNN_TRAIN; d_work at least spcg_mpnn_workspace_bytes(n, n_edges,
+ * SPCG_MPNN_TRAIN) bytes, 256-byte aligned, caller-owned.  Runs the forward
+ * pass too (G and G^T values are updated).  h_loss: NULL or receives L (then
+ * the call synchronises `stream`).
  */
-int spcg_mpnn_loss_grad(spcg_mpnn_t g, spcg_mpnn_ws_t ws, const float *d_w, const float *d_probes,
-                        int32_t m, float *d_grad, double *h_loss, hipStream_t stream);
+int spcg_mpnn_loss_grad(spcg_mpnn_t g, const float *d_w, const float *d_probes, int32_t m,
+                        float *d_grad, double *h_loss, void *d_work, size_t work_bytes,
+                        hipStream_t stream);
 
 /* One Adam step on FP32 master weights: m, v moments in place, bias-corrected
  * with step t >= 1.  Asynchronous. */

@@ -73,7 +73,9 @@ struct spcg_mpnn {
     void *h_pinned = nullptr;
 };
 
-// Activations and training scratch, shareable by the graphs of many matrices.
+// Activations and training scratch: a view of slices of the caller's
+// workspace (carve_ws), shareable by the graphs of many matrices used one at a
+// time on one stream.
 struct spcg_mpnn_ws {
     int64_t max_n = 0, max_E = 0, max_nG = 0;
     bool train = false;
@@ -82,7 +84,6 @@ struct spcg_mpnn_ws {
     float *dh[2] = {}, *de[2] = {}, *dxi = nullptr, *dxj = nullptr, *dagg = nullptr;
     float *pw = nullptr, *pu = nullptr, *ps = nullptr, *py = nullptr, *pq = nullptr;
     float *gG = nullptr, *wpart = nullptr, *lpart = nullptr, *scal = nullptr;
-    void *h_pinned = nullptr;
 };
 
 namespace spcg {
@@ -1007,25 +1008,6 @@ int release(spcg_mpnn *g) {
     return SPCG_OK;
 }
 
-int release_ws(spcg_mpnn_ws *w) {
-    if (!w) return SPCG_OK;
-    for (int l = 0; l <= NL; ++l) {
-        free_dev(w->h[l]);
-        free_dev(w->e[l]);
-    }
-    free_dev(w->wbf);
-    for (int q = 0; q < 2; ++q) {
-        free_dev(w->dh[q]);
-        free_dev(w->de[q]);
-    }
-    free_dev(w->dxi); free_dev(w->dxj); free_dev(w->dagg); free_dev(w->pw); free_dev(w->pu);
-    free_dev(w->ps); free_dev(w->py); free_dev(w->pq); free_dev(w->gG); free_dev(w->wpart);
-    free_dev(w->lpart); free_dev(w->scal);
-    if (w->h_pinned) (void)hipHostFree(w->h_pinned);
-    delete w;
-    return SPCG_OK;
-}
-
 unsigned g1(int64_t n, int per = 256) { return (unsigned)std::max<int64_t>((n + per - 1) / per, 1); }
 
 // workgroups of the tile kernels: forward, and backward (bounded: per-wave partials).
@@ -1041,8 +1023,55 @@ constexpr int kFwdCap = 2048, kEdgeCap = 768, kBwdCap = 256, kSmallCap = 512, kM
 __bf16 *hbuf(const spcg_mpnn_ws *w, int l) { return w->train ? w->h[l] : w->h[l & 1]; }
 __bf16 *ebuf(const spcg_mpnn_ws *w, int l) { return w->train ? w->e[l] : w->e[l & 1]; }
 
-bool fits(const spcg_mpnn *g, const spcg_mpnn_ws *w) {
-    return g->n <= w->max_n && g->E <= w->max_E && g->nG <= w->max_nG;
+// Workspace slices (256-byte aligned) for graphs of up to n rows and E edges:
+// per layer BF16 node and edge activations (all layers when training, two
+// alternating ones for inference), the BF16 weight copies, scalars and, for
+// training, the gradient and probe-product scratch.  base = nullptr only sizes.
+size_t carve_ws(int64_t n, int64_t E, bool train, char *base, spcg_mpnn_ws *w) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void * {
+        char *q = base ? base + off : nullptr;
+        off += align256(std::max<size_t>(bytes, 1));
+        return q;
+    };
+    spcg_mpnn_ws W;
+    W.max_n = n;
+    W.max_E = E;
+    W.max_nG = n + E / 2;
+    W.train = train;
+    const int nbuf = train ? NL + 1 : 2;
+    for (int l = 0; l < nbuf; ++l) {
+        W.h[l] = (__bf16 *)take(sizeof(__bf16) * n * H);
+        W.e[l] = (__bf16 *)take(sizeof(__bf16) * E * H);
+    }
+    W.wbf = (LayerBf *)take(sizeof(LayerBf) * NL);
+    W.scal = (float *)take(sizeof(float) * 64);
+    if (train) {
+        for (int q = 0; q < 2; ++q) {
+            W.dh[q] = (float *)take(sizeof(float) * n * H);
+            W.de[q] = (float *)take(sizeof(float) * E * H);
+        }
+        W.dxi = (float *)take(sizeof(float) * E * H);
+        W.dxj = (float *)take(sizeof(float) * E * H);
+        W.dagg = (float *)take(sizeof(float) * n * H);
+        float **vecs[] = {&W.pw, &W.pu, &W.ps, &W.py, &W.pq};
+        for (float **v : vecs) *v = (float *)take(sizeof(float) * n);
+        W.gG = (float *)take(sizeof(float) * W.max_nG);
+        W.wpart = (float *)take(sizeof(float) * std::max<int64_t>((int64_t)kBwdCap * kWavesPerWg * 4160,
+                                                                    (int64_t)g1(n) * 66));
+        W.lpart = (float *)take(sizeof(float) * (size_t)kMaxProbes * kMaxGrid);
+    }
+    if (w) *w = W;
+    return off;
+}
+
+// The caller's workspace as slices for graph g, or an error if it is too small
+// or misaligned.
+int bind_ws(const spcg_mpnn *g, bool train, void *d_work, size_t work_bytes, spcg_mpnn_ws *w) {
+    if (!d_work || ((uintptr_t)d_work & 255) != 0) return SPCG_INVALID_ARG;
+    if (work_bytes < carve_ws(g->n, g->E, train, nullptr, nullptr)) return SPCG_INVALID_ARG;
+    carve_ws(g->n, g->E, train, (char *)d_work, w);
+    return SPCG_OK;
 }
 
 int forward(spcg_mpnn *g, spcg_mpnn_ws *ws, const float *w, hipStream_t s) {
@@ -1081,57 +1110,9 @@ int forward(spcg_mpnn *g, spcg_mpnn_ws *ws, const float *w, hipStream_t s) {
 
 extern "C" {
 
-int spcg_mpnn_ws_create(spcg_mpnn_ws_t *out, int64_t max_rows, int64_t max_edges, int32_t flags,
-                        hipStream_t s) {
-    (void)s;
-    if (!out || max_rows < 1 || max_edges < 0) return SPCG_INVALID_ARG;
-    *out = nullptr;
-    spcg_mpnn_ws *w = new (std::nothrow) spcg_mpnn_ws;
-    if (!w) return SPCG_INVALID_ARG;
-    w->max_n = max_rows;
-    w->max_E = max_edges;
-    w->max_nG = max_rows + max_edges / 2;
-    w->train = (flags & SPCG_MPNN_TRAIN) != 0;
-#define WS_TRY(expr)                                                            \
-    do {                                                                        \
-        hipError_t e_ = (expr);                                                 \
-        if (e_ != hipSuccess) { release_ws(w); return hip_status(e_, #expr); } \
-    } while (0)
-#define WS_ALLOC(ptr, count) WS_TRY(hipMalloc(&(ptr), sizeof(*(ptr)) * (size_t)std::max<int64_t>((count), 1)))
-    const int64_t n = max_rows, E = max_edges;
-    const int nbuf = w->train ? NL + 1 : 2;
-    for (int l = 0; l < nbuf; ++l) {
-        WS_ALLOC(w->h[l], n * H);
-        WS_ALLOC(w->e[l], E * H);
-    }
-    WS_ALLOC(w->wbf, NL);
-    WS_ALLOC(w->scal, 64);
-    WS_TRY(hipHostMalloc(&w->h_pinned, 256, hipHostMallocDefault));
-    if (w->train) {
-        for (int q = 0; q < 2; ++q) {
-            WS_ALLOC(w->dh[q], n * H);
-            WS_ALLOC(w->de[q], E * H);
-        }
-        WS_ALLOC(w->dxi, E * H);
-        WS_ALLOC(w->dxj, E * H);
-        WS_ALLOC(w->dagg, n * H);
-        float **vecs[] = {&w->pw, &w->pu, &w->ps, &w->py, &w->pq};
-        for (float **v : vecs) WS_ALLOC(*v, n);
-        WS_ALLOC(w->gG, w->max_nG);
-        WS_ALLOC(w->wpart, (int64_t)std::max<int64_t>(kBwdCap * kWavesPerWg * 4160, g1(n) * 66));
-        WS_ALLOC(w->lpart, (int64_t)kMaxProbes * kMaxGrid);
-    }
-#undef WS_ALLOC
-#undef WS_TRY
-    *out = w;
-    return SPCG_OK;
-}
-
-int spcg_mpnn_ws_destroy(spcg_mpnn_ws_t w) {
-    if (!w) return SPCG_INVALID_ARG;
-    hipError_t e = hipDeviceSynchronize();
-    release_ws(w);
-    return e == hipSuccess ? SPCG_OK : hip_status(e, "hipDeviceSynchronize");
+size_t spcg_mpnn_workspace_bytes(int64_t max_rows, int64_t max_edges, int32_t flags) {
+    if (max_rows < 1 || max_edges < 0) return 0;
+    return carve_ws(max_rows, max_edges, (flags & SPCG_MPNN_TRAIN) != 0, nullptr, nullptr);
 }
 
 int spcg_mpnn_create(spcg_mpnn_t *out, spcg_csr_t A, int32_t flags, hipStream_t s) {
@@ -1276,17 +1257,24 @@ int spcg_mpnn_factor_arrays(spcg_mpnn_t g, const int32_t **d_row_ptr, const int3
     return SPCG_OK;
 }
 
-int spcg_mpnn_predict(spcg_mpnn_t g, spcg_mpnn_ws_t ws, const float *d_w, hipStream_t s) {
-    if (!g || !ws || !d_w || !fits(g, ws)) return SPCG_INVALID_ARG;
-    return forward(g, ws, d_w, s);
+int spcg_mpnn_predict(spcg_mpnn_t g, const float *d_w, void *d_work, size_t work_bytes,
+                      hipStream_t s) {
+    if (!g || !d_w) return SPCG_INVALID_ARG;
+    spcg_mpnn_ws view;
+    int rc = bind_ws(g, false, d_work, work_bytes, &view);
+    if (rc) return rc;
+    return forward(g, &view, d_w, s);
 }
 
-int spcg_mpnn_loss_grad(spcg_mpnn_t g, spcg_mpnn_ws_t ws, const float *d_w, const float *d_probes,
-                        int32_t m, float *d_grad, double *h_loss, hipStream_t s) {
-    if (!g || !ws || !d_w || !d_probes || m < 1 || m > kMaxProbes || !g->train || !ws->train ||
-        !fits(g, ws))
-        return SPCG_INVALID_ARG;
-    int rc = forward(g, ws, d_w, s);
+int spcg_mpnn_loss_grad(spcg_mpnn_t g, const float *d_w, const float *d_probes, int32_t m,
+                        float *d_grad, double *h_loss, void *d_work, size_t work_bytes,
+                        hipStream_t s) {
+    if (!g || !d_w || !d_probes || m < 1 || m > kMaxProbes || !g->train) return SPCG_INVALID_ARG;
+    spcg_mpnn_ws view;
+    int rc = bind_ws(g, true, d_work, work_bytes, &view);
+    if (rc) return rc;
+    spcg_mpnn_ws *ws = &view;
+    rc = forward(g, ws, d_w, s);
     if (rc) return rc;
     const int n = g->n, E = g->E;
     const CsrDev Gd = dev_view(g->G), GTd = dev_view(g->GT), Ad = dev_view(g->A32);
@@ -1356,7 +1344,7 @@ int spcg_mpnn_loss_grad(spcg_mpnn_t g, spcg_mpnn_ws_t ws, const float *d_w, cons
         SPCG_LAUNCH_CHECK("mpnn backward");
     }
     if (h_loss) {
-        float *hp = (float *)ws->h_pinned;
+        float *hp = (float *)g->h_pinned;
         SPCG_TRY(hipMemcpyAsync(hp, ws->scal + 1, sizeof(float), hipMemcpyDeviceToHost, s));
         SPCG_TRY(hipStreamSynchronize(s));
         *h_loss = (double)hp[0] / ((double)n * (double)m);

@@ -286,10 +286,11 @@ def _mpnn_sigs(L):
     L.spcg_mpnn_factor.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P)]
     L.spcg_mpnn_factor_arrays.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P),
                                           ctypes.POINTER(P), ctypes.POINTER(P)]
-    L.spcg_mpnn_ws_create.argtypes = [ctypes.POINTER(P), i64, i64, i32, P]
-    L.spcg_mpnn_ws_destroy.argtypes = [P]
-    L.spcg_mpnn_predict.argtypes = [P, P, P, P]
-    L.spcg_mpnn_loss_grad.argtypes = [P, P, P, P, i32, P, ctypes.POINTER(ctypes.c_double), P]
+    L.spcg_mpnn_workspace_bytes.argtypes = [i64, i64, i32]
+    L.spcg_mpnn_workspace_bytes.restype = ctypes.c_size_t
+    L.spcg_mpnn_predict.argtypes = [P, P, P, ctypes.c_size_t, P]
+    L.spcg_mpnn_loss_grad.argtypes = [P, P, P, i32, P, ctypes.POINTER(ctypes.c_double), P,
+                                      ctypes.c_size_t, P]
     L.spcg_adam_step.argtypes = [P, P, P, P, i64, i32, ctypes.c_float, ctypes.c_float,
                                  ctypes.c_float, ctypes.c_float, P]
     L._mpnn_ready = True
@@ -309,32 +310,16 @@ class _Borrowed:
 
 
 class MpnnWorkspace:
-    """Activation / gradient buffers shared by graphs (see spcg_mpnn_ws_create)."""
+    """Device workspace of the network calls (spcg_mpnn_workspace_bytes), a
+    torch buffer shared by the graphs of many matrices used one at a time."""
 
-    def __init__(self, max_rows: int, max_edges: int, train: bool = False):
+    def __init__(self, max_rows: int, max_edges: int, train: bool = False, device="cuda"):
         L = _mpnn_sigs(lib())
-        self._h = ctypes.c_void_p(0)
         self.max_rows, self.max_edges, self.train = max_rows, max_edges, train
-        st = L.spcg_mpnn_ws_create(ctypes.byref(self._h), max_rows, max_edges,
-                                   1 if train else 0, _stream())
-        if st != OK:
-            self._h = ctypes.c_void_p(0)
-            raise SpcgError(st, "spcg_mpnn_ws_create")
-
-    @property
-    def handle(self):
-        return self._h
-
-    def close(self):
-        if self._h and self._h.value:
-            lib().spcg_mpnn_ws_destroy(self._h)
-            self._h = ctypes.c_void_p(0)
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        self.nbytes = L.spcg_mpnn_workspace_bytes(max_rows, max_edges, 1 if train else 0)
+        if self.nbytes == 0:
+            raise SpcgError(INVALID_ARG, "spcg_mpnn_workspace_bytes")
+        self.buf = _workspace(self.nbytes, device)
 
 
 class MpnnGraph:
@@ -356,12 +341,13 @@ class MpnnGraph:
         hg, hgt = ctypes.c_void_p(0), ctypes.c_void_p(0)
         _check(L.spcg_mpnn_factor(self._h, ctypes.byref(hg), ctypes.byref(hgt)), "spcg_mpnn_factor")
         self.G, self.GT = _Borrowed(hg.value, self), _Borrowed(hgt.value, self)
-        self.ws = ws if ws is not None else MpnnWorkspace(A.n_rows, self.n_edges, train)
+        self.ws = ws if ws is not None else MpnnWorkspace(A.n_rows, self.n_edges, train,
+                                                          A.vals.device)
 
     def predict(self, w: torch.Tensor):
         assert w.dtype == torch.float32 and w.numel() == MPNN_PARAMS and w.is_contiguous()
-        _check(lib().spcg_mpnn_predict(self._h, self.ws.handle, _ptr(w), _stream()),
-               "spcg_mpnn_predict")
+        _check(lib().spcg_mpnn_predict(self._h, _ptr(w), _ptr(self.ws.buf), self.ws.nbytes,
+                                       _stream()), "spcg_mpnn_predict")
 
     def loss_grad(self, w: torch.Tensor, probes: torch.Tensor, grad: torch.Tensor | None = None,
                   want_loss: bool = True):
@@ -371,9 +357,10 @@ class MpnnGraph:
         assert probes.shape[1] == self.A.n_rows
         m = probes.shape[0]
         loss = ctypes.c_double(0.0)
-        _check(lib().spcg_mpnn_loss_grad(self._h, self.ws.handle, _ptr(w), _ptr(probes), m,
-                                         _ptr(grad), ctypes.byref(loss) if want_loss else None,
-                                         _stream()), "spcg_mpnn_loss_grad")
+        _check(lib().spcg_mpnn_loss_grad(self._h, _ptr(w), _ptr(probes), m, _ptr(grad),
+                                         ctypes.byref(loss) if want_loss else None,
+                                         _ptr(self.ws.buf), self.ws.nbytes, _stream()),
+               "spcg_mpnn_loss_grad")
         return loss.value if want_loss else None
 
     def factor_arrays(self):

@@ -89,3 +89,18 @@ def test_keep_bytes_setting_round_trips():
     assert d == 192 << 20
     assert spcg.keep_bytes(0) == d and spcg.keep_bytes() == 0
     assert spcg.keep_bytes(d) == 0 and spcg.keep_bytes() == d
+
+
+def test_network_workspace_sizes_on_host():
+    # spcg_mpnn_workspace_bytes is host arithmetic: no device call
+    from paper_1211_1581_amd import spcg
+    L = spcg._mpnn_sigs(spcg.lib())
+    n, E = 110592, 649728  # the 48^3 training matrices
+    infer = L.spcg_mpnn_workspace_bytes(n, E, 0)
+    train = L.spcg_mpnn_workspace_bytes(n, E, 1)
+    assert infer % 256 == 0 and train % 256 == 0
+    assert 0 < infer < train
+    # two alternating BF16 layers of width 32 at least
+    assert infer >= 2 * 2 * 32 * (n + E)
+    assert L.spcg_mpnn_workspace_bytes(2 * n, 2 * E, 0) > infer
+    assert L.spcg_mpnn_workspace_bytes(0, E, 0) == 0 and L.spcg_mpnn_workspace_bytes(n, -1, 1) == 0

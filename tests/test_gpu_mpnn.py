@@ -10,6 +10,8 @@ error of the factor values by 2e-2 (measured: 3e-3 .. 6e-3), the loss by
 1e-2, the gradient by 5e-2 (measured: 2e-3 .. 2.3e-2), and require cosine
 similarity >= 0.9999 (factor) / 0.999 (gradients).  A wrong index, sign or
 transposition gives O(1) errors."""
+import ctypes
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -95,7 +97,9 @@ def test_inference_forward_equals_training_forward(N, seed):
     _, gi = graph(A)
     _, gt = graph(A, train=True)
     gi.predict(w)
-    gt.predict(w)
+    # the training forward runs inside the loss (every layer's state stored)
+    V = torch.tensor(I.rademacher_probes(A.n_rows, 2, seed), dtype=torch.float32, device="cuda")
+    gt.loss_grad(w, V, want_loss=False)
     _, _, gv_i, gtv_i = gi.factor_arrays()
     _, _, gv_t, gtv_t = gt.factor_arrays()
     assert np.array_equal(gv_i, gv_t) and np.array_equal(gtv_i, gtv_t)
@@ -172,3 +176,34 @@ def test_invalid_patterns_rejected():
     with pytest.raises(S.SpcgError) as e:
         S.MpnnGraph(M)
     assert e.value.status == S.INVALID_CSR
+
+
+def test_caller_workspace_rules():
+    # the network calls run on a caller-owned workspace: too small or
+    # misaligned is rejected before any work; a larger one shared by a smaller
+    # graph gives the same factor as the graph's own
+    S = spcg()
+    A, _, _ = I.fv_diffusion(10, 3, corr_len=2.0)
+    B, _, _ = I.fv_diffusion(6, 3, corr_len=2.0)
+    w = torch.tensor(mpnn.flatten(weights(3)), dtype=torch.float32, device="cuda")
+    MA, ga = graph(A)
+    MB = S.CsrMatrix.from_host(B)
+    gb_own = S.MpnnGraph(MB)
+    gb_shared = S.MpnnGraph(MB, ws=ga.ws)
+    gb_own.predict(w)
+    gb_shared.predict(w)
+    assert np.array_equal(gb_own.factor_arrays()[2], gb_shared.factor_arrays()[2])
+    L = S.lib()
+    need = L.spcg_mpnn_workspace_bytes(A.n_rows, ga.n_edges, 0)
+    assert need == ga.ws.nbytes
+    buf = ga.ws.buf
+    assert L.spcg_mpnn_predict(ga._h, S._ptr(w), S._ptr(buf), need - 1,
+                               S._stream()) == S.INVALID_ARG
+    assert L.spcg_mpnn_predict(ga._h, S._ptr(w), ctypes.c_void_p(buf.data_ptr() + 8), need,
+                               S._stream()) == S.INVALID_ARG
+    # the training loss needs the training layout
+    gt = S.MpnnGraph(MA, train=True)
+    V = torch.ones((1, A.n_rows), dtype=torch.float32, device="cuda")
+    with pytest.raises(S.SpcgError):
+        gt.ws = ga.ws  # an inference-sized workspace
+        gt.loss_grad(w, V)
