@@ -189,6 +189,8 @@ def main():
     ap.add_argument("--spmv", choices=SPMV_CASES, default=None,
                     help="run only the cold standalone SpMV of this matrix and precision and "
                          "print its record (for kernel traces and counters of one product)")
+    ap.add_argument("--binning", choices=("on", "off"), default="off",
+                    help="row-length binning policy of the standalone products")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -203,6 +205,7 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    spcg.row_binning(args.binning)
     if args.calib and args.spmv:
         src = torch.ones(2 ** 25, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -465,6 +468,8 @@ def spmv_case(name):
         A, x = I.lognormal_irregular()
     r = cold_spmv(A, x, dtype)
     r["case"] = name
+    from paper_1211_1581_amd import spcg
+    r["row_binning"] = spcg.row_binning()
     return r
 
 
@@ -508,6 +513,14 @@ def workloads(A128, x128):
     L, xl = I.lognormal_irregular()
     out["spmv_cold"]["lognormal_f64"] = cold_spmv(L, xl, "f64")
     out["spmv_cold"]["lognormal_f32"] = cold_spmv(L, xl, "f32")
+    # the same products with row-length bins (per-bin lane groups) instead of
+    # the row-block kernel
+    old = spcg.row_binning("on")
+    try:
+        out["spmv_cold"]["lognormal_f64_row_bins"] = cold_spmv(L, xl, "f64")
+        out["spmv_cold"]["lognormal_f32_row_bins"] = cold_spmv(L, xl, "f32")
+    finally:
+        spcg.row_binning(old)
     out["spmv_cold"]["lognormal_workload"] = ("n = 200000, lognormal row lengths (median 48, "
                                               "max 4096), nnz = 15788355, seed 2")
     return out

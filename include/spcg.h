@@ -111,6 +111,35 @@ int64_t spcg_keep_bytes(int64_t bytes);
 int spcg_csr_info(spcg_csr_t A, int64_t *n_blocks, int64_t *n_long_rows, int64_t *max_row_len);
 
 /*
+ * Row-length binning of y = A x (Sec. 3.2's per-row reduction with a lane
+ * group per row sized by the row's length), process-wide policy.  Bin b < 7
+ * holds the rows of at most 4 * 2^b entries (rows of 0..4, 5..8, ..., 129..256
+ * entries), reduced by groups of 2^b lanes (one lane per row up to a whole
+ * wavefront per row); bin 7 holds longer rows, one wavefront per row.  The
+ * analysis lists each bin's rows (12 bytes per row, owned by the handle).
+ *   SPCG_BINNING_OFF (default): spmv_csr uses the row-block kernel (rows
+ *     partitioned into blocks of bounded work, staged through LDS, with a
+ *     lane count per block from its mean row length), which measured faster
+ *     on the irregular lognormal matrix (103 against 130 us in FP64);
+ *   SPCG_BINNING_ON: spcg_csr_create builds the bins and spmv_csr uses them
+ *     (rows of at most 4 entries everywhere keep the short-row kernel).
+ * The policy at spcg_csr_create decides whether a handle has bins; the policy
+ * at spmv_csr whether they are used.  mode < 0 only returns the current
+ * policy; otherwise sets it and returns the previous one (SPCG_INVALID_ARG
+ * for an unknown mode).  The CG solver's products keep the row-block kernel.
+ * Both kernels sum each row in a fixed order that depends only on the matrix
+ * (the two orders differ, within rounding).
+ */
+#define SPCG_NUM_BINS 8
+#define SPCG_BINNING_OFF 0
+#define SPCG_BINNING_ON 1
+int spcg_row_binning(int mode);
+
+/* Rows per bin of a handle built with bins (else SPCG_INVALID_ARG);
+ * counts: int64_t[SPCG_NUM_BINS]. */
+int spcg_csr_bin_counts(spcg_csr_t A, int64_t *counts);
+
+/*
  * y = A x (Sec. 3.2): y_i = sum over the entries k of row i of vals[k] * x[col[k]],
  * for all n_rows rows, overwriting y (an empty row gives 0).  x: n_cols
  * elements, y: n_rows elements, both of the handle's dtype; FP32 matrices

@@ -151,6 +151,7 @@ int launch_spmv(const spcg_csr *A, const T *x, T *y, hipStream_t s) {
         SPCG_LAUNCH_CHECK("k_spmv_short");
         return SPCG_OK;
     }
+    if (use_bins(A)) return launch_spmv_bins<T>(A, x, y, s);
     if (matrix_bytes(A->n_rows, A->nnz, sizeof(T)) <= keep_bytes())
         hipLaunchKernelGGL((k_spmv<T, true>), dim3(spmv_grid(A->n_blocks)), dim3(kBlock), 0, s,
                            dev_view(A), (const T *)A->vals, x, y);
@@ -222,6 +223,8 @@ static void release(spcg_csr *h) {
     if (h->block_k) (void)hipFree(h->block_k);
     if (h->flags) (void)hipFree(h->flags);
     if (h->h_pinned) (void)hipHostFree(h->h_pinned);
+    for (int32_t *p : {h->bin_row, h->bin_k, h->bin_len})
+        if (p) (void)hipFree(p);
     for (int i = 0; i < h->n_events; ++i) (void)hipEventDestroy(h->events[i]);
     delete[] h->events;
     delete h;
@@ -291,6 +294,13 @@ int spcg_csr_create(spcg_csr_t *out, int32_t n_rows, int32_t n_cols, int64_t nnz
     CREATE_TRY(hipMemcpyAsync(hf, h->flags, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
     CREATE_TRY(hipStreamSynchronize(stream));
     h->n_long = hf[2];
+    if (binning_at_create(h)) {
+        const int rc = build_bins(h, stream);
+        if (rc != SPCG_OK) {
+            release(h);
+            return rc;
+        }
+    }
 #undef CREATE_TRY
     *out = h;
     return SPCG_OK;

@@ -45,6 +45,12 @@ struct spcg_csr {
     void *h_pinned = nullptr;      // pinned host words for status reads, owned
     hipEvent_t *events = nullptr;  // timing mode: event pool, owned
     int n_events = 0;
+    // row-length bins (bins.hip): each bin's rows in ascending order with
+    // their first entry and length, owned; built when the binning policy at
+    // creation asks for them
+    int32_t *bin_row = nullptr, *bin_k = nullptr, *bin_len = nullptr;
+    int32_t bin_count[SPCG_NUM_BINS] = {}, bin_start[SPCG_NUM_BINS] = {};
+    bool has_bins = false;
 };
 
 namespace spcg {
@@ -568,6 +574,37 @@ __device__ __forceinline__ int block_range(int nb, int &bs, int &be) {
     be = (int)((int64_t)nb * (w + 1) / P);
     return w;
 }
+
+// ------------------------------------------------------ row-length bins --
+
+constexpr int kNumBins = SPCG_NUM_BINS;
+constexpr int kLongBin = kNumBins - 1;  // rows of more than 4 * 2^(kLongBin - 1) entries
+
+struct BinStarts {
+    int s[kNumBins];
+};
+
+struct BinView {
+    const int32_t *__restrict__ row;  // bin lists (all bins back to back)
+    const int32_t *__restrict__ k;
+    const int32_t *__restrict__ len;
+    const int32_t *__restrict__ col;
+    int nnz;
+    int off;  // first list entry of the bin at hand
+};
+
+struct BinPlan {
+    BinView v;
+    int start[kNumBins], count[kNumBins];
+    int wg[kNumBins];  // first workgroup of each bin
+};
+
+int binning_mode();
+bool binning_at_create(const spcg_csr *A);
+int build_bins(spcg_csr *h, hipStream_t s);
+bool use_bins(const spcg_csr *A);
+template <typename T>
+int launch_spmv_bins(const spcg_csr *A, const T *x, T *y, hipStream_t s);
 
 // Short-row kernels apply when every row has at most kShortLen entries.
 inline bool uses_short_rows(const spcg_csr *A) {

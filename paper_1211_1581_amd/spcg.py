@@ -68,6 +68,9 @@ def lib():
         L.spcg_csr_info.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                     ctypes.POINTER(i64)]
         L.spmv_csr.argtypes = [P, P, P, P]
+        L.spcg_row_binning.argtypes = [ctypes.c_int]
+        L.spcg_row_binning.restype = ctypes.c_int
+        L.spcg_csr_bin_counts.argtypes = [P, ctypes.POINTER(i64)]
         L.spcg_dot_workspace_bytes.argtypes = [i64]
         L.spcg_dot_workspace_bytes.restype = sz
         L.spcg_dot.argtypes = [i64, P, P, P, P, P]
@@ -91,6 +94,20 @@ def keep_bytes(value=None) -> int:
     """Matrix-stream load policy (spcg_keep_bytes): with value, set the limit
     in bytes and return the previous one; without, return the current one."""
     return int(lib().spcg_keep_bytes(-1 if value is None else int(value)))
+
+
+BINNING = {"off": 0, "on": 1}
+BINNING_NAME = {v: k for k, v in BINNING.items()}
+
+
+def row_binning(mode=None):
+    """Row-length binning policy of spmv_csr (spcg_row_binning): with mode
+    ("off", "on"), set it and return the previous one; without, return the
+    current one."""
+    st = lib().spcg_row_binning(-1 if mode is None else BINNING[mode])
+    if st < 0:
+        raise SpcgError(st, "spcg_row_binning")
+    return BINNING_NAME[st]
 
 
 def last_error() -> str:
@@ -157,6 +174,16 @@ class CsrMatrix:
         _check(lib().spcg_csr_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
                "spcg_csr_info")
         return dict(n_blocks=a.value, n_long=b.value, max_row_len=c.value)
+
+    def has_bins(self) -> bool:
+        c = (ctypes.c_int64 * 8)()
+        return lib().spcg_csr_bin_counts(self._h, c) == OK
+
+    def bin_counts(self):
+        """Rows per row-length bin (a list of 8), for a handle made with bins."""
+        c = (ctypes.c_int64 * 8)()
+        _check(lib().spcg_csr_bin_counts(self._h, c), "spcg_csr_bin_counts")
+        return list(c)
 
     def close(self):
         if self._h and self._h.value:

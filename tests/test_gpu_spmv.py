@@ -13,28 +13,74 @@ from gpu_util import U32, check_f64, dense_abs_product, gamma, lower_upper, spcg
 pytestmark = pytest.mark.gpu
 
 
-def run(A, x, dtype=torch.float64):
+def run(A, x, dtype=torch.float64, binning=None):
+    """y = A x on the device.  binning: the row-binning policy in force while
+    the handle is made and the product runs ("off": row-block kernel, "on":
+    row-length bins), restored afterwards; None keeps the default (off)."""
     S = spcg()
-    M = S.CsrMatrix.from_host(A, dtype=dtype)
-    y = S.spmv_csr(M, to_dev(x, dtype))
-    torch.cuda.synchronize()
+    old = S.row_binning(binning) if binning is not None else None
+    try:
+        M = S.CsrMatrix.from_host(A, dtype=dtype)
+        y = S.spmv_csr(M, to_dev(x, dtype))
+        torch.cuda.synchronize()
+    finally:
+        if old is not None:
+            S.row_binning(old)
     return y.cpu().numpy(), M
 
 
+BOTH = pytest.mark.parametrize("binning", ["off", "on"])
+
+
+@BOTH
 @pytest.mark.parametrize("seed", range(4))
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_integer_valued_bit_exact(seed, dtype):
-    # several row blocks, a ragged tail, empty rows, long rows beyond the LDS slab
+def test_integer_valued_bit_exact(seed, dtype, binning):
+    # several row blocks, a ragged tail, empty rows, long rows beyond the LDS
+    # slab; with bins, rows in every bin including the long-row one
     A, x = I.random_csr_small(7001, 6000, seed, max_len=40, integer=True,
                               long_rows=[(5, 5000), (3000, 1900), (7000, 2500)],
                               unsorted=bool(seed % 2), duplicates=(seed == 2))
-    y, M = run(A, x, dtype)
+    y, M = run(A, x, dtype, binning)
     assert M.info()["n_long"] >= 2
+    assert M.has_bins() == (binning == "on")
     assert np.array_equal(y.astype(np.float64), oracle.spmv(A, x))
 
 
-def test_edge_shapes():
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_bins_every_length_class(dtype):
+    # rows of every length from 0 to 600 (both sides of each bin edge 4, 8,
+    # ..., 256), a 5000-entry row, empty rows last: bin counts equal the
+    # histogram of the row lengths, and the binned product is bit-exact
     S = spcg()
+    rng = np.random.default_rng(17)
+    lens = np.concatenate([np.arange(0, 601), [5000], rng.integers(0, 40, 3000), [0, 0, 0]])
+    rng.shuffle(lens[:-3])
+    rp = np.zeros(len(lens) + 1, np.int64)
+    np.cumsum(lens, out=rp[1:])
+    nc = 6000
+    col = np.concatenate([np.sort(rng.choice(nc, l, replace=False)) for l in lens]).astype(np.int32)
+    A = I.CSR(len(lens), nc, rp.astype(np.int32), col,
+              rng.integers(-4, 5, rp[-1]).astype(np.float64))
+    x = rng.integers(-4, 5, nc).astype(np.float64)
+    y, M = run(A, x, dtype, "on")
+    edges = [4 << b for b in range(7)]
+    want = np.bincount(np.searchsorted(edges, lens, side="left"), minlength=8)
+    assert np.array_equal(M.bin_counts(), want)
+    assert np.array_equal(y.astype(np.float64), oracle.spmv(A, x))
+
+
+@BOTH
+def test_edge_shapes(binning):
+    S = spcg()
+    old = S.row_binning(binning)
+    try:
+        _edge_shapes(S)
+    finally:
+        S.row_binning(old)
+
+
+def _edge_shapes(S):
     # n = 1
     A = I.CSR(1, 1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([2.5]))
     assert run(A, np.array([4.0]))[0][0] == 10.0
@@ -160,17 +206,19 @@ def lognormal_200k():
     return I.lognormal_irregular()
 
 
-def test_full_size_lognormal_f64(lognormal_200k):
+@BOTH
+def test_full_size_lognormal_f64(lognormal_200k, binning):
     A, x = lognormal_200k
     assert A.nnz == 15_788_355
-    y, M = run(A, x)
+    y, M = run(A, x, binning=binning)
     check_f64(y, oracle.spmv(A, x), A, x, "lognormal f64")
     assert M.info()["max_row_len"] == 4096
 
 
-def test_full_size_lognormal_f32(lognormal_200k):
+@BOTH
+def test_full_size_lognormal_f32(lognormal_200k, binning):
     A, x = lognormal_200k
-    y, _ = run(A, x, torch.float32)
+    y, _ = run(A, x, torch.float32, binning)
     ref = f32_check(A, x, y)
     # report-only: error against the FP64 product of the unrounded inputs
     ref64 = oracle.spmv(A, x)
@@ -189,10 +237,21 @@ def test_full_size_fv160_both():
 def test_deterministic_repeats():
     S = spcg()
     A, x = I.lognormal_irregular(n=50000, seed=9)
-    M = S.CsrMatrix.from_host(A)
-    xt = to_dev(x)
-    ys = [S.spmv_csr(M, xt).cpu().numpy() for _ in range(3)]
+    old = S.row_binning("on")
+    try:
+        M = S.CsrMatrix.from_host(A)
+        assert M.has_bins()
+        xt = to_dev(x)
+        ys = [S.spmv_csr(M, xt).cpu().numpy() for _ in range(3)]
+    finally:
+        S.row_binning(old)
     assert all(np.array_equal(ys[0], y) for y in ys[1:])
+    # the row-block kernel on the same handle: its own fixed order, also
+    # repeatable, and within the dot-product bound of the oracle
+    zs = [S.spmv_csr(M, xt).cpu().numpy() for _ in range(2)]
+    assert np.array_equal(zs[0], zs[1])
+    check_f64(zs[0], oracle.spmv(A, x), A, x, "row blocks")
+    check_f64(ys[0], oracle.spmv(A, x), A, x, "bins")
 
 
 def test_invalid_csr_rejected_on_device():
@@ -238,8 +297,9 @@ def test_rows_at_the_lds_slab_size(L, dtype):
     vals = rng.integers(-5, 6, rp[-1]).astype(np.float64)
     A = I.CSR(len(lens), nc, rp.astype(np.int32), col, vals)
     x = rng.integers(-3, 4, nc).astype(np.float64)
-    y, M = run(A, x, dtype)
-    assert np.array_equal(y.astype(np.float64), oracle.spmv(A, x))
+    for binning in ("off", "on"):
+        y, M = run(A, x, dtype, binning)
+        assert np.array_equal(y.astype(np.float64), oracle.spmv(A, x))
 
 
 def test_maximum_size():
