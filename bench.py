@@ -191,6 +191,8 @@ def main():
                          "print its record (for kernel traces and counters of one product)")
     ap.add_argument("--binning", choices=("on", "off"), default="off",
                     help="row-length binning policy of the standalone products")
+    ap.add_argument("--runs", choices=("on", "off"), default="off",
+                    help="run-compressed column policy of the standalone products")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -206,6 +208,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     spcg.row_binning(args.binning)
+    spcg.run_columns(args.runs)
     if args.calib and args.spmv:
         src = torch.ones(2 ** 25, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -453,7 +456,8 @@ def cold_spmv(A, x, dtype, launches=60, first=None):
             "launches": launches, "warmup": warm, "err_vs_oracle": err}
 
 
-SPMV_CASES = ("poisson128_f64", "poisson128_f32", "lognormal_f64", "lognormal_f32")
+SPMV_CASES = ("poisson128_f64", "poisson128_f32", "lognormal_f64", "lognormal_f32",
+              "banded1m_f64")
 
 
 def spmv_case(name):
@@ -464,12 +468,17 @@ def spmv_case(name):
     if mat == "poisson128":
         A = I.poisson3d(128)
         x = I.uniform_vector(A.n_rows, 1)
+    elif mat == "banded1m":
+        # the banded shape of the paper's CG inputs at scale: 2^20 rows, bandwidth 63
+        A = I.banded_spd(1 << 20, 63)
+        x = I.uniform_vector(A.n_rows, 63)
     else:
         A, x = I.lognormal_irregular()
     r = cold_spmv(A, x, dtype)
     r["case"] = name
     from paper_1211_1581_amd import spcg
     r["row_binning"] = spcg.row_binning()
+    r["run_columns"] = spcg.run_columns()
     return r
 
 

@@ -140,6 +140,37 @@ int spcg_row_binning(int mode);
 int spcg_csr_bin_counts(spcg_csr_t A, int64_t *counts);
 
 /*
+ * Run-compressed column indices of y = A x, process-wide policy: the index
+ * side of the paper's contiguous-section SpMV (Sec. 3.2, the second mapped
+ * kernel, which reads x over sections of consecutive columns as one piece).
+ * At spcg_csr_create the library cuts the entries each row block stages into
+ * chunks of 64 and, per chunk, keeps a 64-bit mask of run starts (an entry
+ * whose column is not its predecessor's plus one), the chunk's first start and
+ * the start columns (8 + 4 bytes per chunk and 4 per start, owned by the
+ * handle); spmv_csr then derives each column from its run start, so inside a
+ * run no index is read.  The products and their order are unchanged: results
+ * are bitwise equal to the plain kernel's.  Entries of a row longer than the
+ * row block's slab keep reading the column array.
+ *   SPCG_RUNS_OFF (default): plain columns.  Measured cold on this chip the
+ *     run layout is slower although it reads fewer bytes (128^3 7-point, 6 %
+ *     fewer: 54.5 against 43.5 us; 2^20 rows of bandwidth 63, 30 % fewer:
+ *     185 against 161 us): finding a column costs one more dependent load
+ *     (mask and start, then the start column) before the gather of x, and the
+ *     product is bound by that chain, not by bytes;
+ *   SPCG_RUNS_ON: spcg_csr_create builds the runs and spmv_csr uses them.
+ * The policy at spcg_csr_create decides whether a handle has runs; the policy
+ * at spmv_csr whether they are used.  mode < 0 only returns the current
+ * policy.  Binning (SPCG_BINNING_ON) takes precedence in spmv_csr; the CG
+ * solver's products read the plain columns.
+ */
+#define SPCG_RUNS_OFF 0
+#define SPCG_RUNS_ON 1
+int spcg_run_columns(int mode);
+
+/* Chunks and run starts of a handle built with runs (else SPCG_INVALID_ARG). */
+int spcg_csr_run_info(spcg_csr_t A, int64_t *n_chunks, int64_t *n_starts);
+
+/*
  * y = A x (Sec. 3.2): y_i = sum over the entries k of row i of vals[k] * x[col[k]],
  * for all n_rows rows, overwriting y (an empty row gives 0).  x: n_cols
  * elements, y: n_rows elements, both of the handle's dtype; FP32 matrices

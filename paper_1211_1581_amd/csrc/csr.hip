@@ -121,14 +121,16 @@ struct EpiStore {
     __device__ __forceinline__ void row(int i, T s, NoOperand) { y[i] = s; }
 };
 
-template <typename T, bool KEEP>
+// RUNS: columns of the LDS-staged entries from the run-compressed layout
+template <typename T, bool KEEP, bool RUNS = false>
 SPCG_ROWBLOCK_KERNEL
 k_spmv(CsrDev A, const T *__restrict__ vals, const T *__restrict__ x, T *__restrict__ y) {
     __shared__ SpmvSmem<T> sm;
     int bs, be;
     block_range(A.n_blocks, bs, be);
     EpiStore<T> epi{y};
-    for (int b = bs; b < be; ++b) spmv_block<T, T, T, KEEP>(A, vals, x, b, sm, epi, b + 1 < be);
+    for (int b = bs; b < be; ++b)
+        spmv_block<T, T, T, KEEP, false, RUNS>(A, vals, x, b, sm, epi, b + 1 < be);
 }
 
 // y = A x for matrices whose rows have at most kShortLen entries
@@ -152,12 +154,12 @@ int launch_spmv(const spcg_csr *A, const T *x, T *y, hipStream_t s) {
         return SPCG_OK;
     }
     if (use_bins(A)) return launch_spmv_bins<T>(A, x, y, s);
-    if (matrix_bytes(A->n_rows, A->nnz, sizeof(T)) <= keep_bytes())
-        hipLaunchKernelGGL((k_spmv<T, true>), dim3(spmv_grid(A->n_blocks)), dim3(kBlock), 0, s,
-                           dev_view(A), (const T *)A->vals, x, y);
-    else
-        hipLaunchKernelGGL((k_spmv<T, false>), dim3(spmv_grid(A->n_blocks)), dim3(kBlock), 0, s,
-                           dev_view(A), (const T *)A->vals, x, y);
+    const bool keep = matrix_bytes(A->n_rows, A->nnz, sizeof(T)) <= keep_bytes();
+    const bool runs = use_runs(A);
+    auto kern = runs ? (keep ? k_spmv<T, true, true> : k_spmv<T, false, true>)
+                     : (keep ? k_spmv<T, true> : k_spmv<T, false>);
+    hipLaunchKernelGGL(kern, dim3(spmv_grid(A->n_blocks)), dim3(kBlock), 0, s, dev_view(A),
+                       (const T *)A->vals, x, y);
     SPCG_LAUNCH_CHECK("k_spmv");
     return SPCG_OK;
 }
@@ -223,8 +225,9 @@ static void release(spcg_csr *h) {
     if (h->block_k) (void)hipFree(h->block_k);
     if (h->flags) (void)hipFree(h->flags);
     if (h->h_pinned) (void)hipHostFree(h->h_pinned);
-    for (int32_t *p : {h->bin_row, h->bin_k, h->bin_len})
+    for (int32_t *p : {h->bin_row, h->bin_k, h->bin_len, h->run_base, h->run_col, h->run_chunk})
         if (p) (void)hipFree(p);
+    if (h->run_mask) (void)hipFree(h->run_mask);
     for (int i = 0; i < h->n_events; ++i) (void)hipEventDestroy(h->events[i]);
     delete[] h->events;
     delete h;
@@ -296,6 +299,13 @@ int spcg_csr_create(spcg_csr_t *out, int32_t n_rows, int32_t n_cols, int64_t nnz
     h->n_long = hf[2];
     if (binning_at_create(h)) {
         const int rc = build_bins(h, stream);
+        if (rc != SPCG_OK) {
+            release(h);
+            return rc;
+        }
+    }
+    if (runs_mode() == SPCG_RUNS_ON) {
+        const int rc = build_runs(h, stream);
         if (rc != SPCG_OK) {
             release(h);
             return rc;

@@ -51,6 +51,12 @@ struct spcg_csr {
     int32_t *bin_row = nullptr, *bin_k = nullptr, *bin_len = nullptr;
     int32_t bin_count[SPCG_NUM_BINS] = {}, bin_start[SPCG_NUM_BINS] = {};
     bool has_bins = false;
+    // run-compressed columns (runs.hip), owned; built when the run policy at
+    // creation asks for them
+    unsigned long long *run_mask = nullptr;
+    int32_t *run_base = nullptr, *run_col = nullptr, *run_chunk = nullptr;
+    int64_t n_chunks = 0, n_heads = 0;
+    bool has_runs = false;
 };
 
 namespace spcg {
@@ -320,7 +326,28 @@ struct CsrDev {
     // entry k of row block b (the kernels instantiated with C16 read these
     // instead of col)
     const int16_t *__restrict__ off16;
+    // optional run-compressed columns (runs.hip; the kernels instantiated with
+    // RUNS read these instead of col for the entries a block stages in LDS):
+    // the staged entries of block b form 64-entry chunks from run_chunk[b] on;
+    // bit l of run_mask[c] marks entry l of chunk c as the first of a run of
+    // consecutive columns (bit 0 always), run_base[c] is the chunk's first
+    // head in run_col, which holds the columns of the heads
+    const unsigned long long *__restrict__ run_mask;
+    const int32_t *__restrict__ run_base;
+    const int32_t *__restrict__ run_col;
+    const int32_t *__restrict__ run_chunk;
 };
+
+// Column of staged entry t of a block whose chunks start at cb (RUNS layout):
+// the nearest run head at or before t in its chunk, plus the distance to it.
+__device__ __forceinline__ int run_column(const CsrDev &A, int cb, int t) {
+    const int j = t >> 6, l = t & 63;
+    const unsigned long long m = A.run_mask[cb + j];
+    const unsigned long long upto = l == 63 ? m : (m & ((2ull << l) - 1ull));
+    const int nh = __popcll(upto);
+    const int hl = 63 - __clzll(upto);
+    return A.run_col[A.run_base[cb + j] + nh - 1] + (l - hl);
+}
 
 template <typename TA>
 struct SpmvSmem {
@@ -333,11 +360,12 @@ struct SpmvSmem {
 // Products of NU rounds of kBlock entries starting at k0 (cnt >= 1 entries
 // are real; the clamped tail re-reads the last one and is not stored).  KEEP:
 // ordinary loads of col/vals (see keep_bytes), else non-temporal ones.  C16:
-// columns from A.off16 relative to the block's first row r0.
-template <int NU, bool KEEP, bool C16, typename TV, typename TX, typename TA>
+// columns from A.off16 relative to the block's first row r0.  RUNS: columns
+// from the run-compressed layout, the block's chunks starting at cb.
+template <int NU, bool KEEP, bool C16, bool RUNS, typename TV, typename TX, typename TA>
 __device__ __forceinline__ void block_products(const CsrDev &A, const TV *__restrict__ vals,
                                                const TX *__restrict__ x, int k0, int cnt, int r0,
-                                               TA *__restrict__ slab) {
+                                               int cb, TA *__restrict__ slab) {
     const int tid = threadIdx.x;
     int c[NU];
     TV v[NU];
@@ -345,7 +373,9 @@ __device__ __forceinline__ void block_products(const CsrDev &A, const TV *__rest
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
         const int t = min(tid + u * kBlock, cnt - 1);
-        if constexpr (C16) {
+        if constexpr (RUNS) {
+            c[u] = run_column(A, cb, t);
+        } else if constexpr (C16) {
             c[u] = r0 + (KEEP ? A.off16[k0 + t] : __builtin_nontemporal_load(A.off16 + k0 + t));
         } else {
             c[u] = KEEP ? A.col[k0 + t] : __builtin_nontemporal_load(A.col + k0 + t);
@@ -383,7 +413,8 @@ __device__ __forceinline__ int32_t load_uniform(const int32_t *p, int i) {
 // store_block_partials, or the end of the kernel, follows.  KEEP selects the
 // load policy of the matrix streams (keep_bytes); C16 reads the compact
 // columns A.off16.
-template <typename TV, typename TX, typename TA, bool KEEP = false, bool C16 = false, class Epi>
+template <typename TV, typename TX, typename TA, bool KEEP = false, bool C16 = false,
+          bool RUNS = false, class Epi>
 __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict__ vals,
                                            const TX *__restrict__ x, int blk,
                                            SpmvSmem<TA> &sm, Epi &epi, bool more = true) {
@@ -393,6 +424,7 @@ __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict
     if (r0 >= r1) return;  // uniform over the workgroup
     const int k0 = load_uniform(A.block_k, blk);
     const int kend = load_uniform(A.block_k, blk + 1);
+    const int cb = RUNS ? load_uniform(A.run_chunk, blk) : 0;
     // a block whose entries overflow the slab ends in a long row (every other
     // row of a block has fewer than kChunk entries); that row is reduced below
     const bool long_last = (kend - k0) > kSlab;
@@ -406,13 +438,13 @@ __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict
     const int rv = A.row_ptr[r0 + min(tid, nr)];
     const auto pre = epi.load(r0 + min(tid, nr - 1));  // the epilogue's operand of row r0 + tid
     switch ((cnt + kBlock - 1) / kBlock) {
-        case 1: block_products<1, KEEP, C16>(A, vals, x, k0, cnt, r0, sm.slab); break;
-        case 2: block_products<2, KEEP, C16>(A, vals, x, k0, cnt, r0, sm.slab); break;
-        case 3: block_products<3, KEEP, C16>(A, vals, x, k0, cnt, r0, sm.slab); break;
-        case 4: block_products<4, KEEP, C16>(A, vals, x, k0, cnt, r0, sm.slab); break;
-        case 5: block_products<5, KEEP, C16>(A, vals, x, k0, cnt, r0, sm.slab); break;
-        case 6: block_products<6, KEEP, C16>(A, vals, x, k0, cnt, r0, sm.slab); break;
-        case 7: block_products<7, KEEP, C16>(A, vals, x, k0, cnt, r0, sm.slab); break;
+        case 1: block_products<1, KEEP, C16, RUNS>(A, vals, x, k0, cnt, r0, cb, sm.slab); break;
+        case 2: block_products<2, KEEP, C16, RUNS>(A, vals, x, k0, cnt, r0, cb, sm.slab); break;
+        case 3: block_products<3, KEEP, C16, RUNS>(A, vals, x, k0, cnt, r0, cb, sm.slab); break;
+        case 4: block_products<4, KEEP, C16, RUNS>(A, vals, x, k0, cnt, r0, cb, sm.slab); break;
+        case 5: block_products<5, KEEP, C16, RUNS>(A, vals, x, k0, cnt, r0, cb, sm.slab); break;
+        case 6: block_products<6, KEEP, C16, RUNS>(A, vals, x, k0, cnt, r0, cb, sm.slab); break;
+        case 7: block_products<7, KEEP, C16, RUNS>(A, vals, x, k0, cnt, r0, cb, sm.slab); break;
         default: break;  // only empty rows
     }
     static_assert(kSlab <= 7 * kBlock, "block_products covers at most 7 rounds");
@@ -606,13 +638,18 @@ bool use_bins(const spcg_csr *A);
 template <typename T>
 int launch_spmv_bins(const spcg_csr *A, const T *x, T *y, hipStream_t s);
 
+int runs_mode();
+int build_runs(spcg_csr *h, hipStream_t s);
+bool use_runs(const spcg_csr *A);
+
 // Short-row kernels apply when every row has at most kShortLen entries.
 inline bool uses_short_rows(const spcg_csr *A) {
     return A->n_rows > 0 && A->nnz > 0 && A->max_len <= kShortLen;
 }
 
 inline CsrDev dev_view(const spcg_csr *A) {
-    return CsrDev{A->row_ptr, A->col, A->block_row, A->block_k, (int)A->n_blocks, nullptr};
+    return CsrDev{A->row_ptr, A->col, A->block_row, A->block_k, (int)A->n_blocks, nullptr,
+                  A->run_mask, A->run_base, A->run_col, A->run_chunk};
 }
 
 }  // namespace spcg

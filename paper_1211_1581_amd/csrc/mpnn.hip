@@ -27,6 +27,7 @@
 #include <new>
 
 #include "internal.h"
+#include "scan.h"
 #include "mfma.h"
 
 namespace spcg {
@@ -149,69 +150,6 @@ __global__ void k_rev(int E, const int32_t *__restrict__ rp, const int32_t *__re
         return;
     }
     rev[e] = (rp[j] - j) + (lo - rp[j]) - (lo > dpos[j] ? 1 : 0);
-}
-
-// Exclusive scan of cnt[0..n) into out[0..n] in three steps: chunk sums
-// (k_scan_sums), a one-workgroup scan of the chunk sums (k_scan_top), and a
-// rescan of every chunk from its offset (k_scan_apply).
-constexpr int kScanChunk = 4096;
-
-__global__ void __launch_bounds__(256) k_scan_sums(int n, const int32_t *__restrict__ cnt,
-                                                   int32_t *sums) {
-    __shared__ int red[4];
-    const int base = blockIdx.x * kScanChunk;
-    int s = 0;
-    for (int i = base + threadIdx.x; i < min(n, base + kScanChunk); i += 256) s += cnt[i];
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) sums[blockIdx.x] = s;
-}
-
-__global__ void __launch_bounds__(1024) k_scan_top(int nb, int32_t *sums) {
-    __shared__ int32_t sh[1024];
-    const int T = 1024, t = threadIdx.x;
-    const int per = (nb + T - 1) / T;
-    const int a = min(nb, t * per), b = min(nb, a + per);
-    int32_t s = 0;
-    for (int i = a; i < b; ++i) s += sums[i];
-    sh[t] = s;
-    __syncthreads();
-    for (int o = 1; o < T; o <<= 1) {
-        const int32_t v = t >= o ? sh[t - o] : 0;
-        __syncthreads();
-        sh[t] += v;
-        __syncthreads();
-    }
-    int32_t run = sh[t] - s;
-    for (int i = a; i < b; ++i) {
-        const int32_t c = sums[i];
-        sums[i] = run;
-        run += c;
-    }
-    if (t == T - 1) sums[nb] = sh[T - 1];
-}
-
-__global__ void __launch_bounds__(256) k_scan_apply(int n, const int32_t *__restrict__ cnt,
-                                                    const int32_t *__restrict__ offs, int32_t *out) {
-    __shared__ int32_t sh[256];
-    const int base = blockIdx.x * kScanChunk;
-    const int per = kScanChunk / 256;
-    const int a = min(n, base + threadIdx.x * per), b = min(n, a + per);
-    int32_t s = 0;
-    for (int i = a; i < b; ++i) s += cnt[i];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {
-        const int32_t v = (int)threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
-        __syncthreads();
-        sh[threadIdx.x] += v;
-        __syncthreads();
-    }
-    int32_t run = offs[blockIdx.x] + sh[threadIdx.x] - s;
-    for (int i = a; i < b; ++i) {
-        out[i] = run;
-        run += cnt[i];
-    }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 255) out[n] = offs[gridDim.x];
 }
 
 // G (tril) and G^T (triu) patterns, and the G^T <- G value map

@@ -71,6 +71,9 @@ def lib():
         L.spcg_row_binning.argtypes = [ctypes.c_int]
         L.spcg_row_binning.restype = ctypes.c_int
         L.spcg_csr_bin_counts.argtypes = [P, ctypes.POINTER(i64)]
+        L.spcg_run_columns.argtypes = [ctypes.c_int]
+        L.spcg_run_columns.restype = ctypes.c_int
+        L.spcg_csr_run_info.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.spcg_dot_workspace_bytes.argtypes = [i64]
         L.spcg_dot_workspace_bytes.restype = sz
         L.spcg_dot.argtypes = [i64, P, P, P, P, P]
@@ -108,6 +111,20 @@ def row_binning(mode=None):
     if st < 0:
         raise SpcgError(st, "spcg_row_binning")
     return BINNING_NAME[st]
+
+
+RUNS = {"off": 0, "on": 1}
+RUNS_NAME = {v: k for k, v in RUNS.items()}
+
+
+def run_columns(mode=None):
+    """Run-compressed column policy of spmv_csr (spcg_run_columns): with mode
+    ("off", "on"), set it and return the previous one; without, return the
+    current one."""
+    st = lib().spcg_run_columns(-1 if mode is None else RUNS[mode])
+    if st < 0:
+        raise SpcgError(st, "spcg_run_columns")
+    return RUNS_NAME[st]
 
 
 def last_error() -> str:
@@ -184,6 +201,13 @@ class CsrMatrix:
         c = (ctypes.c_int64 * 8)()
         _check(lib().spcg_csr_bin_counts(self._h, c), "spcg_csr_bin_counts")
         return list(c)
+
+    def run_info(self):
+        """(chunks, run starts) of a handle made with run-compressed columns, or None."""
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        if lib().spcg_csr_run_info(self._h, ctypes.byref(a), ctypes.byref(b)) != OK:
+            return None
+        return a.value, b.value
 
     def close(self):
         if self._h and self._h.value:
