@@ -351,7 +351,7 @@ __device__ __forceinline__ int run_column(const CsrDev &A, int cb, int t) {
 
 template <typename TA>
 struct SpmvSmem {
-    TA slab[kSlab];
+    TA slab[kSlab + 1];  // + a spare slot for the stores of clamped lanes
     int32_t rp[kChunk + 1];
     TA red[kBlock / 64 * 3];  // block sums: up to 3 values per wavefront
     TA last;
@@ -365,29 +365,43 @@ struct SpmvSmem {
 template <int NU, bool KEEP, bool C16, bool RUNS, typename TV, typename TX, typename TA>
 __device__ __forceinline__ void block_products(const CsrDev &A, const TV *__restrict__ vals,
                                                const TX *__restrict__ x, int k0, int cnt, int r0,
-                                               int cb, TA *__restrict__ slab) {
-    const int tid = threadIdx.x;
+                                               int cb, TA *__restrict__ slab, int first = 0) {
+    const int tid = threadIdx.x + first;
+    // the block's streams from bases that are uniform over the workgroup
+    // (scalar registers) plus 32-bit byte offsets per lane: one register per
+    // address instead of a 64-bit pair, so every round's loads stay in
+    // registers at eight wavefronts per SIMD (with 64-bit addresses the
+    // compiler deferred a round until the others had arrived)
+    const char *colb = (const char *)(A.col + k0);
+    const char *offb = (const char *)(A.off16 + (C16 ? k0 : 0));
+    const char *valb = (const char *)(vals + k0);
     int c[NU];
     TV v[NU];
     TX xv[NU];
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
-        const int t = min(tid + u * kBlock, cnt - 1);
+        const uint32_t t = (uint32_t)min(tid + u * kBlock, cnt - 1);
         if constexpr (RUNS) {
-            c[u] = run_column(A, cb, t);
+            c[u] = run_column(A, cb, (int)t);
         } else if constexpr (C16) {
-            c[u] = r0 + (KEEP ? A.off16[k0 + t] : __builtin_nontemporal_load(A.off16 + k0 + t));
+            const int16_t *p = (const int16_t *)(offb + t * 2u);
+            c[u] = r0 + (KEEP ? *p : __builtin_nontemporal_load(p));
         } else {
-            c[u] = KEEP ? A.col[k0 + t] : __builtin_nontemporal_load(A.col + k0 + t);
+            const int32_t *p = (const int32_t *)(colb + t * 4u);
+            c[u] = KEEP ? *p : __builtin_nontemporal_load(p);
         }
-        v[u] = KEEP ? vals[k0 + t] : __builtin_nontemporal_load(vals + k0 + t);
+        const TV *q = (const TV *)(valb + t * (uint32_t)sizeof(TV));
+        v[u] = KEEP ? *q : __builtin_nontemporal_load(q);
     }
 #pragma unroll
     for (int u = 0; u < NU; ++u) xv[u] = x[c[u]];
+    // every lane stores, clamped lanes into the slab's spare slot: a store
+    // under a branch let the compiler sink a round's loads into the branch,
+    // where they waited for all the others
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
         const int t = tid + u * kBlock;
-        if (t < cnt) slab[t] = TA(v[u]) * TA(xv[u]);
+        slab[t < cnt ? t : kSlab] = TA(v[u]) * TA(xv[u]);
     }
 }
 
@@ -444,7 +458,11 @@ __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict
         case 4: block_products<4, KEEP, C16, RUNS>(A, vals, x, k0, cnt, r0, cb, sm.slab); break;
         case 5: block_products<5, KEEP, C16, RUNS>(A, vals, x, k0, cnt, r0, cb, sm.slab); break;
         case 6: block_products<6, KEEP, C16, RUNS>(A, vals, x, k0, cnt, r0, cb, sm.slab); break;
-        case 7: block_products<7, KEEP, C16, RUNS>(A, vals, x, k0, cnt, r0, cb, sm.slab); break;
+        case 7:  // a long last row: two batches, so the registers of six rounds suffice
+            block_products<4, KEEP, C16, RUNS>(A, vals, x, k0, cnt, r0, cb, sm.slab);
+            __builtin_amdgcn_sched_barrier(0);  // keep the batches apart
+            block_products<3, KEEP, C16, RUNS>(A, vals, x, k0, cnt, r0, cb, sm.slab, 4 * kBlock);
+            break;
         default: break;  // only empty rows
     }
     static_assert(kSlab <= 7 * kBlock, "block_products covers at most 7 rounds");
