@@ -321,7 +321,7 @@ def main():
                      "launches": cold["launches"],
                      "timing": ("HIP events on the launch stream around %d back-to-back launches "
                                 "rotating over %d device copies of A (%.0f MB in all, more than the "
-                                "256 MB MALL), after %d warm-up launches"
+                                "256 MB MALL; streaming loads), after %d warm-up launches"
                                 % (cold["launches"], cold["copies"],
                                    cold["copies"] * matrix_mb, cold["warmup"])),
                      "err_vs_oracle": cold["err_vs_oracle"]},
@@ -402,12 +402,27 @@ def copy_rate():
 def cold_spmv(A, x, dtype, launches=60, first=None):
     """Cold standalone SpMV: spmv_csr rotating over enough device copies of A
     that their total exceeds 600 MB (more than twice the 256 MB MALL), so every
-    launch streams the matrix from HBM.  `us` = the average duration of
+    launch streams the matrix from HBM, read with the library's streaming
+    (non-temporal) load policy, spcg_keep_bytes(0), the policy for products
+    whose matrix is not read again soon.  `us` = the average duration of
     `launches` back-to-back launches between two HIP events on the launch
     stream (after warm-up launches); `us_bracketed` = the median of launches
     bracketed one by one (each then also carries the event and launch gaps).
     The last product is compared with the FP64 oracle (FP32: also with the
     oracle's FP64 sum of the same FP32 inputs)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1211_1581_amd import spcg
+    keep = spcg.keep_bytes(0)
+    try:
+        return _cold_spmv(A, x, dtype, launches, first)
+    finally:
+        spcg.keep_bytes(keep)
+
+
+def _cold_spmv(A, x, dtype, launches, first):
     import numpy as np
     import torch
 
@@ -453,7 +468,8 @@ def cold_spmv(A, x, dtype, launches=60, first=None):
     gbs = b / (us * 1e-6) / 1e9
     return {"us": round(us, 2), "us_bracketed": round(us_br, 2), "gbs": round(gbs, 1),
             "pct_peak": round(100 * gbs / PEAK_HBM_GBS, 1), "bytes": b, "copies": ncopy,
-            "launches": launches, "warmup": warm, "err_vs_oracle": err}
+            "launches": launches, "warmup": warm, "load_policy": "non-temporal",
+            "err_vs_oracle": err}
 
 
 SPMV_CASES = ("poisson128_f64", "poisson128_f32", "lognormal_f64", "lognormal_f32",

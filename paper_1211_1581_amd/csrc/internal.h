@@ -433,12 +433,15 @@ __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict
                                            const TX *__restrict__ x, int blk,
                                            SpmvSmem<TA> &sm, Epi &epi, bool more = true) {
     const int tid = threadIdx.x;
+    // all four descriptors requested before any is used: one round trip
     const int r0 = load_uniform(A.block_row, blk);
     const int r1 = load_uniform(A.block_row, blk + 1);
-    if (r0 >= r1) return;  // uniform over the workgroup
     const int k0 = load_uniform(A.block_k, blk);
     const int kend = load_uniform(A.block_k, blk + 1);
     const int cb = RUNS ? load_uniform(A.run_chunk, blk) : 0;
+    // (kend < k0 never holds; testing it keeps the compiler from sinking the
+    // entry descriptors' load below this exit into a second round trip)
+    if (r0 >= r1 || kend < k0) return;  // uniform over the workgroup
     // a block whose entries overflow the slab ends in a long row (every other
     // row of a block has fewer than kChunk entries); that row is reduced below
     const bool long_last = (kend - k0) > kSlab;
