@@ -193,6 +193,8 @@ def main():
                     help="row-length binning policy of the standalone products")
     ap.add_argument("--runs", choices=("on", "off"), default="off",
                     help="run-compressed column policy of the standalone products")
+    ap.add_argument("--panels", choices=("on", "off"), default="off",
+                    help="column-panel policy of the standalone products")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -209,6 +211,7 @@ def main():
     torch.cuda.set_device(dev)
     spcg.row_binning(args.binning)
     spcg.run_columns(args.runs)
+    spcg.column_panels(args.panels)
     if args.calib and args.spmv:
         src = torch.ones(2 ** 25, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -454,6 +457,7 @@ def _cold_spmv(A, x, dtype, launches, first):
     us = e0.elapsed_time(e1) * 1e3 / launches
     us_br = float(np.median([f0.elapsed_time(f1) * 1e3 for f0, f1 in evs]))
     yh = y.cpu().numpy().astype(np.float64)
+    pinfo = copies[0].panel_info() if spcg.column_panels() == "on" else None
     del copies
     if dtype == "f64":
         ref = oracle.spmv(A, x)
@@ -466,10 +470,16 @@ def _cold_spmv(A, x, dtype, launches, first):
         err = {"rel_err_same_fp32_inputs": float(np.linalg.norm(yh - ref32) / np.linalg.norm(ref32)),
                "rel_err_vs_fp64_product": float(np.linalg.norm(yh - ref) / np.linalg.norm(ref))}
     gbs = b / (us * 1e-6) / 1e9
-    return {"us": round(us, 2), "us_bracketed": round(us_br, 2), "gbs": round(gbs, 1),
-            "pct_peak": round(100 * gbs / PEAK_HBM_GBS, 1), "bytes": b, "copies": ncopy,
-            "launches": launches, "warmup": warm, "load_policy": "non-temporal",
-            "err_vs_oracle": err}
+    r = {"us": round(us, 2), "us_bracketed": round(us_br, 2), "gbs": round(gbs, 1),
+         "pct_peak": round(100 * gbs / PEAK_HBM_GBS, 1), "bytes": b, "copies": ncopy,
+         "launches": launches, "warmup": warm, "load_policy": "non-temporal",
+         "err_vs_oracle": err}
+    if pinfo is not None:
+        # the panel copy the kernel streams instead of the CSR arrays: values and
+        # 32-bit keys per entry (padding included); `bytes` stays the CSR figure
+        r["panels"] = {"ranges": pinfo[0], "panels": pinfo[1], "entries": pinfo[2],
+                       "copy_bytes": pinfo[2] * (sv + 4)}
+    return r
 
 
 SPMV_CASES = ("poisson128_f64", "poisson128_f32", "lognormal_f64", "lognormal_f32",
@@ -495,6 +505,7 @@ def spmv_case(name):
     from paper_1211_1581_amd import spcg
     r["row_binning"] = spcg.row_binning()
     r["run_columns"] = spcg.run_columns()
+    r["column_panels"] = spcg.column_panels()
     return r
 
 
@@ -546,6 +557,13 @@ def workloads(A128, x128):
         out["spmv_cold"]["lognormal_f32_row_bins"] = cold_spmv(L, xl, "f32")
     finally:
         spcg.row_binning(old)
+    # and with column panels (x staged in LDS, pieces summed by segmented scans)
+    old = spcg.column_panels("on")
+    try:
+        out["spmv_cold"]["lognormal_f64_panels"] = cold_spmv(L, xl, "f64")
+        out["spmv_cold"]["lognormal_f32_panels"] = cold_spmv(L, xl, "f32")
+    finally:
+        spcg.column_panels(old)
     out["spmv_cold"]["lognormal_workload"] = ("n = 200000, lognormal row lengths (median 48, "
                                               "max 4096), nnz = 15788355, seed 2")
     return out

@@ -171,6 +171,43 @@ int spcg_run_columns(int mode);
 int spcg_csr_run_info(spcg_csr_t A, int64_t *n_chunks, int64_t *n_starts);
 
 /*
+ * Column panels for y = A x, process-wide policy: x staged in LDS, for
+ * matrices whose columns scatter over an x much larger than a CU's LDS (each
+ * gather of such a matrix is otherwise its own vector-L1 miss).  At
+ * spcg_csr_create the library cuts every row into pieces of at most 32
+ * entries, the rows into one range of balanced work per CU and the columns
+ * into panels of 112 KB of x (14336 doubles or 28672 floats), and keeps its own
+ * copy of the values with one 32-bit word per entry (the column in the panel
+ * and the piece's index in its range), ordered by range, panel, piece and
+ * column, padded so that no piece's entries in a panel cross a multiple of 64:
+ * (value size + 4) bytes per entry plus the padding, owned by the handle.
+ * spmv_csr then runs one 1024-thread workgroup per range that walks the panels;
+ * each wavefront sums 64 entries at a time with a segmented scan and adds each
+ * piece's part to an accumulator in LDS; each row adds its pieces at the end.
+ * The order of every addition is fixed by the matrix (results repeat bitwise;
+ * they differ from the row-block kernel's within rounding).  Built only for
+ * rows with strictly increasing columns, n_cols >= 4, at most 1024 panels, at
+ * most 4096 pieces per range and fewer than 65536 entries per (range, panel);
+ * otherwise the handle has no panels and the other kernels run.  Used only
+ * when x is 16-byte aligned.  The copy must be rebuilt (a new handle) if the
+ * values change.
+ *   SPCG_PANELS_OFF (default): no panels;
+ *   SPCG_PANELS_ON: spcg_csr_create builds them and spmv_csr uses them.
+ * The policy at spcg_csr_create decides whether a handle has panels; the
+ * policy at spmv_csr whether they are used.  mode < 0 only returns the current
+ * policy.  Panels take precedence over bins and runs; the CG solver's products
+ * keep the row-block kernel.
+ */
+#define SPCG_PANELS_OFF 0
+#define SPCG_PANELS_ON 1
+int spcg_column_panels(int mode);
+
+/* Row ranges, column panels and entries of the panel copy (padding included)
+ * of a handle built with panels (else SPCG_INVALID_ARG); null pointers are
+ * skipped. */
+int spcg_csr_panel_info(spcg_csr_t A, int64_t *n_ranges, int64_t *n_panels, int64_t *n_entries);
+
+/*
  * y = A x (Sec. 3.2): y_i = sum over the entries k of row i of vals[k] * x[col[k]],
  * for all n_rows rows, overwriting y (an empty row gives 0).  x: n_cols
  * elements, y: n_rows elements, both of the handle's dtype; FP32 matrices

@@ -153,6 +153,7 @@ int launch_spmv(const spcg_csr *A, const T *x, T *y, hipStream_t s) {
         SPCG_LAUNCH_CHECK("k_spmv_short");
         return SPCG_OK;
     }
+    if (use_panels(A) && ((uintptr_t)x & 15) == 0) return launch_spmv_panels<T>(A, x, y, s);
     if (use_bins(A)) return launch_spmv_bins<T>(A, x, y, s);
     const bool keep = matrix_bytes(A->n_rows, A->nnz, sizeof(T)) <= keep_bytes();
     const bool runs = use_runs(A);
@@ -225,9 +226,11 @@ static void release(spcg_csr *h) {
     if (h->block_k) (void)hipFree(h->block_k);
     if (h->flags) (void)hipFree(h->flags);
     if (h->h_pinned) (void)hipHostFree(h->h_pinned);
-    for (int32_t *p : {h->bin_row, h->bin_k, h->bin_len, h->run_base, h->run_col, h->run_chunk})
+    for (int32_t *p : {h->bin_row, h->bin_k, h->bin_len, h->run_base, h->run_col, h->run_chunk,
+                       h->pan_range, h->pan_phase, h->pan_vstart, h->pan_base})
         if (p) (void)hipFree(p);
-    if (h->run_mask) (void)hipFree(h->run_mask);
+    for (void *p : {(void *)h->run_mask, (void *)h->pan_key, h->pan_val})
+        if (p) (void)hipFree(p);
     for (int i = 0; i < h->n_events; ++i) (void)hipEventDestroy(h->events[i]);
     delete[] h->events;
     delete h;
@@ -306,6 +309,13 @@ int spcg_csr_create(spcg_csr_t *out, int32_t n_rows, int32_t n_cols, int64_t nnz
     }
     if (runs_mode() == SPCG_RUNS_ON) {
         const int rc = build_runs(h, stream);
+        if (rc != SPCG_OK) {
+            release(h);
+            return rc;
+        }
+    }
+    if (panels_mode() == SPCG_PANELS_ON) {
+        const int rc = build_panels(h, stream);
         if (rc != SPCG_OK) {
             release(h);
             return rc;

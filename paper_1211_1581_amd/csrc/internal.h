@@ -57,6 +57,14 @@ struct spcg_csr {
     int32_t *run_base = nullptr, *run_col = nullptr, *run_chunk = nullptr;
     int64_t n_chunks = 0, n_heads = 0;
     bool has_runs = false;
+    // column panels (panels.hip), owned; built when the panel policy at
+    // creation asks for them
+    int32_t *pan_range = nullptr, *pan_phase = nullptr, *pan_vstart = nullptr, *pan_base = nullptr;
+    uint32_t *pan_key = nullptr;
+    void *pan_val = nullptr;
+    int pan_P = 0, pan_R = 0, pan_W = 0;
+    int64_t pan_entries = 0;  // entries of the panel copy, padding included
+    bool has_panels = false;
 };
 
 namespace spcg {
@@ -662,6 +670,12 @@ int launch_spmv_bins(const spcg_csr *A, const T *x, T *y, hipStream_t s);
 int runs_mode();
 int build_runs(spcg_csr *h, hipStream_t s);
 bool use_runs(const spcg_csr *A);
+
+int panels_mode();
+int build_panels(spcg_csr *h, hipStream_t s);
+bool use_panels(const spcg_csr *A);
+template <typename T>
+int launch_spmv_panels(const spcg_csr *A, const T *x, T *y, hipStream_t s);
 
 // Short-row kernels apply when every row has at most kShortLen entries.
 inline bool uses_short_rows(const spcg_csr *A) {

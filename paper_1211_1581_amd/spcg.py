@@ -74,6 +74,9 @@ def lib():
         L.spcg_run_columns.argtypes = [ctypes.c_int]
         L.spcg_run_columns.restype = ctypes.c_int
         L.spcg_csr_run_info.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.spcg_column_panels.argtypes = [ctypes.c_int]
+        L.spcg_column_panels.restype = ctypes.c_int
+        L.spcg_csr_panel_info.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.spcg_dot_workspace_bytes.argtypes = [i64]
         L.spcg_dot_workspace_bytes.restype = sz
         L.spcg_dot.argtypes = [i64, P, P, P, P, P]
@@ -125,6 +128,19 @@ def run_columns(mode=None):
     if st < 0:
         raise SpcgError(st, "spcg_run_columns")
     return RUNS_NAME[st]
+
+
+PANELS = {"off": 0, "on": 1}
+PANELS_NAME = {v: k for k, v in PANELS.items()}
+
+
+def column_panels(mode=None):
+    """Column-panel policy of spmv_csr (spcg_column_panels): with mode ("off",
+    "on"), set it and return the previous one; without, return the current one."""
+    st = lib().spcg_column_panels(-1 if mode is None else PANELS[mode])
+    if st < 0:
+        raise SpcgError(st, "spcg_column_panels")
+    return PANELS_NAME[st]
 
 
 def last_error() -> str:
@@ -208,6 +224,14 @@ class CsrMatrix:
         if lib().spcg_csr_run_info(self._h, ctypes.byref(a), ctypes.byref(b)) != OK:
             return None
         return a.value, b.value
+
+    def panel_info(self):
+        """(row ranges, column panels, entries of the panel copy with its
+        padding) of a handle made with column panels, or None."""
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        if lib().spcg_csr_panel_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)) != OK:
+            return None
+        return a.value, b.value, c.value
 
     def close(self):
         if self._h and self._h.value:

@@ -1,0 +1,162 @@
+"""GPU parity of the column-panel product y = A x (x staged in LDS by
+panels of 112 KB, rows cut into pieces of at most 32 entries, summed by
+segmented scans): bit-exact against the oracle on integer data, within the
+dot-product bound on float data, bitwise repeatable, with ragged panels, empty
+rows and panels, and the fallbacks (unsorted columns, a misaligned x, ranges
+with too many pieces) that keep the row-block kernel."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1211_1581_amd import inputs as I
+from gpu_util import U32, check_f64, dense_abs_product, gamma, spcg, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def with_panels(A, dtype=torch.float64):
+    S = spcg()
+    old = S.column_panels("on")
+    try:
+        M = S.CsrMatrix.from_host(A, dtype=dtype)
+    finally:
+        S.column_panels(old)
+    return M
+
+
+def product(M, x, dtype=torch.float64, mode="on"):
+    S = spcg()
+    old = S.column_panels(mode)
+    try:
+        y = S.spmv_csr(M, to_dev(x, dtype))
+        torch.cuda.synchronize()
+    finally:
+        S.column_panels(old)
+    return y.cpu().numpy()
+
+
+def width(dtype):
+    return 14336 if dtype == torch.float64 else 28672
+
+
+@pytest.mark.parametrize("seed", range(3))
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("nc", [70001, 28672, 5000])
+def test_panels_integer_bit_exact(seed, dtype, nc):
+    # sorted columns over n_cols that is ragged against the panel width (and
+    # odd: the last 16-byte unit of x is partial), a multiple of it, or below
+    # it (one panel); empty rows, rows of one entry, long rows
+    A, x = I.random_csr_small(6000, nc, seed, max_len=60, integer=True,
+                              long_rows=[(7, 3000), (5999, 2000)])
+    M = with_panels(A, dtype)
+    info = M.panel_info()
+    assert info is not None and info[1] == -(-nc // width(dtype))
+    # each padding fills less of a 64-entry round than the segment it moves
+    assert A.nnz <= info[2] < 2 * A.nnz
+    y = product(M, x, dtype)
+    assert np.array_equal(y.astype(np.float64), oracle.spmv(A, x))
+    # the row-block kernel on the same handle agrees exactly on integer data
+    assert np.array_equal(product(M, x, dtype, "off"), y)
+
+
+def test_panels_empty_panels_and_rows():
+    # columns only in panels 0 and 3 of 5, and a run of empty rows
+    rng = np.random.default_rng(4)
+    W = width(torch.float64)
+    n, nc = 3000, 4 * W + 123
+    lens = rng.integers(0, 30, n)
+    lens[1000:1500] = 0
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum(lens, out=rp[1:])
+    pool = np.concatenate([np.arange(0, W), np.arange(3 * W, 4 * W)])
+    col = np.concatenate([np.sort(rng.choice(pool, l, replace=False)) for l in lens]).astype(np.int32)
+    A = I.CSR(n, nc, rp.astype(np.int32), col, rng.integers(-4, 5, rp[-1]).astype(np.float64))
+    x = rng.integers(-4, 5, nc).astype(np.float64)
+    M = with_panels(A)
+    assert M.panel_info()[1] == 5
+    assert np.array_equal(product(M, x), oracle.spmv(A, x))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_panels_lognormal_float_and_repeatable(dtype):
+    A, x = I.lognormal_irregular(n=50000, seed=9)
+    M = with_panels(A, dtype)
+    assert M.panel_info() is not None
+    ys = [product(M, x, dtype) for _ in range(3)]
+    assert all(np.array_equal(ys[0], y) for y in ys[1:])
+    if dtype == torch.float64:
+        check_f64(ys[0], oracle.spmv(A, x), A, x, "panels")
+    else:
+        v32, x32 = A.vals.astype(np.float32), x.astype(np.float32)
+        ref = oracle.spmv_f32in(A, v32, x32)
+        absax = dense_abs_product(I.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col,
+                                        v32.astype(np.float64)), x32)
+        lens = np.diff(A.row_ptr).astype(np.float64)
+        bound = gamma(lens + 1, U32) * absax * 1.0001 + 1e-30
+        assert np.all(np.abs(ys[0].astype(np.float64) - ref) <= bound)
+
+
+def test_panels_full_size_lognormal():
+    A, x = I.lognormal_irregular()
+    M = with_panels(A)
+    y = product(M, x)
+    check_f64(y, oracle.spmv(A, x), A, x, "lognormal panels")
+    M32 = with_panels(A, torch.float32)
+    y32 = product(M32, x, torch.float32)
+    ref64 = oracle.spmv(A, x)
+    assert np.linalg.norm(y32 - ref64) / np.linalg.norm(ref64) < 1e-5
+
+
+def test_panels_fallbacks():
+    S = spcg()
+    # unsorted columns: no panels; the product still runs (row blocks)
+    A, x = I.random_csr_small(3000, 30000, 2, max_len=40, integer=True, unsorted=True)
+    M = with_panels(A)
+    assert M.panel_info() is None
+    assert np.array_equal(product(M, x), oracle.spmv(A, x))
+    # a misaligned x (8 bytes past a 16-byte boundary): row blocks, same values
+    B, xb = I.random_csr_small(3000, 30000, 3, max_len=40, integer=True)
+    MB = with_panels(B)
+    assert MB.panel_info() is not None
+    buf = to_dev(np.concatenate([[0.0], xb]))
+    old = S.column_panels("on")
+    try:
+        y = S.spmv_csr(MB, buf[1:])
+        torch.cuda.synchronize()
+    finally:
+        S.column_panels(old)
+    assert np.array_equal(y.cpu().numpy(), oracle.spmv(B, xb))
+
+
+def test_panels_not_built_for_crowded_ranges():
+    # 3 M rows of one entry: every range holds far more than 4096 rows, so the
+    # panels are not built and the product keeps the row-block kernel
+    rng = np.random.default_rng(11)
+    n = 3 << 20
+    rp = np.arange(n + 1, dtype=np.int32)
+    col = rng.integers(0, n, n).astype(np.int32)
+    A = I.CSR(n, n, rp, col, rng.integers(-3, 4, n).astype(np.float64))
+    x = rng.integers(-3, 4, n).astype(np.float64)
+    M = with_panels(A)
+    assert M.panel_info() is None
+    assert np.array_equal(product(M, x), x[col] * A.vals)
+
+
+def test_panels_padded_segments_banded():
+    # rows of 41 consecutive columns: pieces of 32 and 9 entries, most of them
+    # in one panel, so segments often reach a multiple of 64 and are padded
+    A = I.banded_spd(20000, 41)
+    x = np.random.default_rng(5).integers(-4, 5, A.n_cols).astype(np.float64)
+    M = with_panels(A)
+    info = M.panel_info()
+    assert info is not None and info[2] > A.nnz  # some padding
+    assert np.array_equal(product(M, x), oracle.spmv(A, x))
+
+
+def test_panels_not_built_for_narrow_x():
+    # x narrower than one 16-byte unit of FP32: no panels
+    A, x = I.random_csr_small(50, 3, 1, max_len=3, integer=True)
+    M = with_panels(A, torch.float32)
+    assert M.panel_info() is None
+    assert np.array_equal(product(M, x, torch.float32).astype(np.float64), oracle.spmv(A, x))
