@@ -557,13 +557,6 @@ def workloads(A128, x128):
         out["spmv_cold"]["lognormal_f32_row_bins"] = cold_spmv(L, xl, "f32")
     finally:
         spcg.row_binning(old)
-    # and with column panels (x staged in LDS, pieces summed by segmented scans)
-    old = spcg.column_panels("on")
-    try:
-        out["spmv_cold"]["lognormal_f64_panels"] = cold_spmv(L, xl, "f64")
-        out["spmv_cold"]["lognormal_f32_panels"] = cold_spmv(L, xl, "f32")
-    finally:
-        spcg.column_panels(old)
     out["spmv_cold"]["lognormal_workload"] = ("n = 200000, lognormal row lengths (median 48, "
                                               "max 4096), nnz = 15788355, seed 2")
     return out

@@ -135,11 +135,12 @@ k_pan_counts(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ 
 // One workgroup per range, one thread per panel: the start of every virtual
 // row's segment in the panel's block (uint16, padded so that no segment crosses
 // a multiple of 64), then the start of every panel in the range (a scan over the
-// panels).  flags[0] |= 2 if a block holds 65536 entries or more.
+// panels) and the range's entry count (tot[r]).  flags[0] |= 2 if a block holds
+// 65536 entries or more.
 __global__ void __launch_bounds__(kPanelThreads)
 k_pan_layout(int P, const int32_t *__restrict__ range, const int32_t *__restrict__ vstart,
              const uint16_t *__restrict__ cnt, uint16_t *__restrict__ seg,
-             int32_t *__restrict__ phase, int32_t *flags) {
+             int32_t *__restrict__ phase, int32_t *__restrict__ tot, int32_t *flags) {
     __shared__ int sh[kPanelThreads];
     const int r = blockIdx.x, p = threadIdx.x;
     const int a = vstart[range[r]], rows = vstart[range[r + 1]] - a;  // the range's virtual rows
@@ -164,7 +165,10 @@ k_pan_layout(int P, const int32_t *__restrict__ range, const int32_t *__restrict
         __syncthreads();
     }
     if (p < P) phase[(size_t)r * (P + 1) + p] = sh[p] - pos;
-    if (p == 0) phase[(size_t)r * (P + 1) + P] = sh[kPanelThreads - 1];
+    if (p == 0) {
+        phase[(size_t)r * (P + 1) + P] = sh[kPanelThreads - 1];
+        tot[r] = sh[kPanelThreads - 1];
+    }
 }
 
 // The panel-ordered copy: values and keys (panel column | virtual row << 16)
@@ -456,13 +460,15 @@ int build_panels(spcg_csr *h, hipStream_t s) {
     hipLaunchKernelGGL(k_pan_zero, dim3(1), dim3(64), 0, s, h->flags);
     hipLaunchKernelGGL(k_pan_counts, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, h->row_ptr, h->col,
                        (const int32_t *)h->pan_vstart, W, P, cnt, h->flags);
+    // each range's entry count (padding included, into pan_base for now) -> the
+    // ranges' first entries
     hipLaunchKernelGGL(k_pan_layout, dim3(R), dim3(kPanelThreads), 0, s, P, (const int32_t *)h->pan_range,
-                       (const int32_t *)h->pan_vstart, (const uint16_t *)cnt, seg, h->pan_phase, h->flags);
-    // each range's entry count (padding included) -> the ranges' first entries
+                       (const int32_t *)h->pan_vstart, (const uint16_t *)cnt, seg, h->pan_phase,
+                       h->pan_base, h->flags);
     std::vector<int32_t> tot((size_t)R);
     if ((e = hipGetLastError()) != hipSuccess ||
-        (e = hipMemcpy2DAsync(tot.data(), sizeof(int32_t), h->pan_phase + P, sizeof(int32_t) * (P + 1),
-                              sizeof(int32_t), R, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(tot.data(), h->pan_base, sizeof(int32_t) * R, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
         (e = hipMemcpyAsync(hp, h->flags, sizeof(int32_t), hipMemcpyDeviceToHost, s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess)
         return fail(e, "panel layout");
