@@ -89,14 +89,25 @@ def kernel_source_hash(files=None):
 def measured_traffic(kernel, workload, sources):
     """HBM bytes per launch from committed rocprofv3 counter summaries, if they
     were taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
+    return traffic_record(kernel, workload, sources)["bytes_per_launch"]
+
+
+def traffic_record(kernel, workload, sources):
+    """Which counter summary exists for the kernel and whether it applies:
+    its file, the source hash it was taken on, the current hash, and its bytes
+    per launch (None unless the two hashes agree)."""
+    rel = os.path.join("profiles", f"traffic_{kernel}_{workload}.txt")
+    path = os.path.join(ROOT, rel)
+    cur = kernel_source_hash(sources)
     if not os.path.exists(path):
-        return None
+        return {"file": None, "taken_on_hash": None, "current_hash": cur, "bytes_per_launch": None}
     with open(path) as f:
         d = json.load(f)
-    if d.get("source_hash") != kernel_source_hash(sources):
-        return None
-    return d.get("bytes_per_launch")
+    ok = d.get("source_hash") == cur
+    return {"file": rel, "taken_on_hash": d.get("source_hash"), "current_hash": cur,
+            "bytes_per_launch": d.get("bytes_per_launch") if ok else None,
+            "bytes_per_launch_then": d.get("bytes_per_launch"),
+            "ratio_to_algorithmic_then": d.get("ratio_to_algorithmic")}
 
 
 def _oracle_jpcg_sample(A, b, seconds, full_passes):
@@ -327,9 +338,13 @@ def main():
                                 "256 MB MALL; streaming loads), after %d warm-up launches"
                                 % (cold["launches"], cold["copies"],
                                    cold["copies"] * matrix_mb, cold["warmup"])),
-                     "err_vs_oracle": cold["err_vs_oracle"]},
+                     "err_vs_oracle": cold["err_vs_oracle"],
+                     # the counter summary behind `traffic` (null while the
+                     # kernel sources differ from those it was taken on)
+                     "traffic_source": traffic_record("k_spmv", "poisson128", SPMV_SOURCES)},
         "roofline_in_cg": {"bound": "mall", "achieved": round(achieved, 1), "unit": "GB/s",
                            "traffic": traffic_cg,
+                           "traffic_source": traffic_record("k_cg_q", "poisson128", CG_SOURCES),
                            "kernel": "k_cg_q (q = A p with p.q partials, inside the Jacobi-PCG pass)",
                            "bytes_per_launch": b_spmv, "avg_launch_us": round(avg_us, 2),
                            "launches": spmv_calls,
