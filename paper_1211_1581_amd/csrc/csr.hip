@@ -229,7 +229,7 @@ static void release(spcg_csr *h) {
     for (int32_t *p : {h->bin_row, h->bin_k, h->bin_len, h->run_base, h->run_col, h->run_chunk,
                        h->pan_range, h->pan_phase, h->pan_vstart, h->pan_base})
         if (p) (void)hipFree(p);
-    for (void *p : {(void *)h->run_mask, (void *)h->pan_key, h->pan_val})
+    for (void *p : {(void *)h->run_mask, (void *)h->pan_key, h->pan_val, h->pan_part})
         if (p) (void)hipFree(p);
     for (int i = 0; i < h->n_events; ++i) (void)hipEventDestroy(h->events[i]);
     delete[] h->events;

@@ -62,6 +62,7 @@ struct spcg_csr {
     int32_t *pan_range = nullptr, *pan_phase = nullptr, *pan_vstart = nullptr, *pan_base = nullptr;
     uint32_t *pan_key = nullptr;
     void *pan_val = nullptr;
+    void *pan_part = nullptr;  // [column groups][n_rows] partial products of spmv_csr
     int pan_P = 0, pan_R = 0, pan_W = 0;
     int64_t pan_entries = 0;  // entries of the panel copy, padding included
     bool has_panels = false;

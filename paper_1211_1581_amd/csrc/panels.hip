@@ -5,25 +5,28 @@
 //
 // Layout (built once per matrix, on request): every row is cut into pieces of
 // at most kPiece consecutive entries ("virtual rows", one for an empty row), the
-// rows into R ranges of balanced work (merge coordinate, one range per CU), the
-// columns into panels of W entries of x (112 KB: 14336 doubles or 28672 floats).
-// The library keeps its own copy of the values, ordered by range, then panel,
-// then virtual row, then column, and per entry one 32-bit word: the column in
-// the panel (low 16 bits) and the virtual row's index in its range (high 16).
-// A virtual row's entries in one panel form a segment (rows hold sorted
-// columns); within each (range, panel) block no segment crosses a multiple of
-// 64 entries: where one would, padding entries (value 0, virtual row 0xFFFF)
-// fill the rest of the 64.
+// rows into R ranges of balanced work (merge coordinate, one range per
+// kPanelGroups CUs), the columns into panels of W entries of x (48 KB of
+// doubles, 112 KB of floats).  The library keeps its own copy of the values,
+// ordered by range, then panel, then virtual row, then column, and per entry
+// one 32-bit word: the column in the panel (low 16 bits) and the virtual row's
+// index in its range (high 16).  A virtual row's entries in one panel form a
+// segment (rows hold sorted columns); within each (range, panel) block no
+// segment crosses a multiple of 64 entries: where one would, padding entries
+// (value 0, virtual row 0xFFFF) fill the rest of the 64.
 //
-// The product: one 1024-thread workgroup per range walks the panels in order;
-// each of its wavefronts takes 256 of every 4096 entries of a panel's block, in
-// rounds of 64: products (value x LDS slice of x), a segmented scan across the
-// lanes (a fixed tree in each segment), and each segment's sum added to its
-// virtual row's accumulator in LDS.  A virtual row has one segment per panel,
-// so the additions of one panel never meet, and no barrier is needed between
-// its rounds.  The next panel's slice of x is loaded into registers while the
-// current panel is used and written to LDS at the switch; two chunks of entries
-// are in flight per wavefront.  At the end each row adds its pieces in order.
+// The product: kPanelGroups 1024-thread workgroups per range, one per column
+// group (a contiguous quarter of the panels), so each range reads x once in
+// all.  A workgroup walks its panels in order; each of its wavefronts takes
+// 256 of every 4096 entries of a panel's block, in rounds of 64: products
+// (value x LDS slice of x), a segmented scan across the lanes (a fixed tree in
+// each segment), and each segment's sum added to its virtual row's accumulator
+// in LDS.  A virtual row has one segment per panel, so the additions of one
+// panel never meet, and no barrier is needed between its rounds.  The next
+// panel's slice of x is loaded into registers while the current panel is used
+// and written to LDS at the switch; two chunks of entries are in flight per
+// wavefront.  At the end each row adds its pieces in order into the group's
+// partial vector, and a second kernel adds the groups' parts in group order.
 // The order of every addition depends only on the matrix.
 #include <algorithm>
 #include <atomic>
@@ -39,16 +42,21 @@ static std::atomic<int> g_panels{SPCG_PANELS_OFF};
 int panels_mode() { return g_panels.load(std::memory_order_relaxed); }
 
 constexpr int kPanelThreads = 1024;
-constexpr int kPanelMaxRows = 4096;  // virtual rows per range (accumulators in LDS)
-constexpr int kPanelBytes = 112 * 1024;  // one slice of x (7 16-byte units per thread)
+constexpr int kPanelMaxRows = 10240;    // virtual rows per range (accumulators in LDS)
+constexpr int kPanelGroups = 4;         // column groups: workgroups per range
 constexpr int kPanelU = 4;              // entries per thread and chunk (rounds of 64 per wavefront)
 constexpr int kPanelChunk = kPanelThreads * kPanelU;
-constexpr int kPanelMaxP = 1024;        // panels (so n_cols <= 8 M doubles)
+constexpr int kPanelMaxP = 1024;        // panels
 constexpr int kPiece = 32;              // entries per virtual row (at most one lane round)
 constexpr uint32_t kPadRow = 0xFFFFu;   // the virtual row of a padding entry
 
+// One slice of x by value size: 48 KB of doubles (3 16-byte units per thread;
+// with 80 KB of accumulators), 112 KB of floats (7 units; 40 KB of
+// accumulators), the sizes measured fastest on the lognormal matrix.
+constexpr int panel_bytes(int esz) { return esz == 8 ? 48 * 1024 : 112 * 1024; }
+
 template <typename T>
-constexpr int panel_width() { return kPanelBytes / (int)sizeof(T); }
+constexpr int panel_width() { return panel_bytes((int)sizeof(T)) / (int)sizeof(T); }
 
 struct PanelDev {
     const int32_t *__restrict__ base;    // [R + 1] first entry of each range
@@ -57,7 +65,8 @@ struct PanelDev {
     const int32_t *__restrict__ phase;   // [R][P + 1] entry offset of each panel in its range
     const void *__restrict__ val;        // [nnz] panel-ordered values
     const uint32_t *__restrict__ key;    // [nnz] panel column | virtual row in the range << 16
-    int P, n_cols;
+    void *__restrict__ part;             // [kPanelGroups][n_rows] the groups' partial products
+    int P, n_cols, n_rows;
 };
 
 // s[b] + ... + s[e - 1] added to part in index order, eight independent LDS
@@ -208,7 +217,7 @@ k_pan_scatter(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__
 // ---------------------------------------------------------------- product --
 
 // Slice p of x (elements [p W, min((p + 1) W, n_cols))) as 16-byte units,
-// kPanelBytes / 16 / kPanelThreads per thread; elements past n_cols are zero.
+// panel_bytes / 16 / kPanelThreads per thread; elements past n_cols are zero.
 // Every unit is one 16-byte load with no branch: a unit that reaches past
 // n_cols reads the last E elements of x instead (n_cols >= E; an address that
 // is not 16-byte aligned is served by the unaligned access mode), and the
@@ -216,7 +225,7 @@ k_pan_scatter(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__
 template <typename T>
 struct Slice {
     static constexpr int E = 16 / sizeof(T);  // elements per unit
-    static constexpr int U = kPanelBytes / 16 / kPanelThreads;
+    static constexpr int U = panel_bytes((int)sizeof(T)) / 16 / kPanelThreads;
     uint4 u[U];
     int p;
     __device__ __forceinline__ void load(const T *__restrict__ x, int n_cols, int p_) {
@@ -263,7 +272,7 @@ __device__ __forceinline__ T shfl_up_t(T v, int o) {
 
 template <typename T>
 __global__ void __launch_bounds__(kPanelThreads)
-k_spmv_panels(PanelDev D, const T *__restrict__ x, T *__restrict__ y) {
+k_spmv_panels(PanelDev D, const T *__restrict__ x) {
     constexpr int W = panel_width<T>();
     __shared__ __align__(16) T xs[W];      // the panel's slice of x; at the end the pieces' sums
     __shared__ T vacc[kPanelMaxRows];      // every virtual row's running sum
@@ -271,15 +280,17 @@ k_spmv_panels(PanelDev D, const T *__restrict__ x, T *__restrict__ y) {
     const int tid = threadIdx.x, lane = tid & 63;
     const int wbase = (tid >> 6) * (kPanelChunk / (kPanelThreads / 64));  // the wavefront's entries
     const unsigned long long below = (1ull << lane) - 1ull;
-    const int r = blockIdx.x;
+    // workgroup -> (range r, column group grp); the group walks panels [p0, P)
+    const int r = blockIdx.x / kPanelGroups, grp = blockIdx.x % kPanelGroups;
     const int a = D.range[r], rows = D.range[r + 1] - a;
     if (rows <= 0) return;  // uniform
     const int va = D.vstart[a], vrows = D.vstart[a + rows] - va;
-    const int P = D.P;
+    const int PT = D.P, per = (PT + kPanelGroups - 1) / kPanelGroups;
+    const int p0 = min(grp * per, PT), P = min(p0 + per, PT);
     const int base = D.base[r];
     const T *__restrict__ val = (const T *)D.val + base;
     const uint32_t *__restrict__ key = D.key + base;
-    for (int p = tid; p <= P; p += kPanelThreads) ph[p] = D.phase[(size_t)r * (P + 1) + p];
+    for (int p = tid; p <= PT; p += kPanelThreads) ph[p] = D.phase[(size_t)r * (PT + 1) + p];
     for (int j = tid; j < vrows; j += kPanelThreads) vacc[j] = T(0);
     __syncthreads();
 
@@ -308,7 +319,7 @@ k_spmv_panels(PanelDev D, const T *__restrict__ x, T *__restrict__ y) {
         }
     };
 
-    const int first = next_panel(-1);
+    const int first = next_panel(p0 - 1);
     if (first < P) {
         // the first panel's slice now, the next panel's in flight
         {
@@ -378,9 +389,23 @@ k_spmv_panels(PanelDev D, const T *__restrict__ x, T *__restrict__ y) {
             if (pc < P) step(B);
         } while (pc < P);
     }
+    // every row of the range: the group's part, its pieces' sums in order
     __syncthreads();
+    T *__restrict__ yp = (T *)D.part + (size_t)grp * D.n_rows;
     for (int i = tid; i < rows; i += kPanelThreads)
-        y[a + i] = add_run(T(0), vacc, D.vstart[a + i] - va, D.vstart[a + i + 1] - va);
+        yp[a + i] = add_run(T(0), vacc, D.vstart[a + i] - va, D.vstart[a + i + 1] - va);
+}
+
+// y_i = the column groups' parts of row i added in group order
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_pan_combine(int n, const T *__restrict__ part, T *__restrict__ y) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    T s = part[i];
+#pragma unroll
+    for (int g = 1; g < kPanelGroups; ++g) s += part[(size_t)g * n + i];
+    y[i] = s;
 }
 
 // ------------------------------------------------------------------ host --
@@ -397,12 +422,12 @@ int build_panels(spcg_csr *h, hipStream_t s) {
     const int n = h->n_rows;
     if (n == 0 || h->nnz == 0) return SPCG_OK;
     const int esz = h->dtype == SPCG_F64 ? 8 : 4;
-    const int W = kPanelBytes / esz;
+    const int W = panel_bytes(esz) / esz;
     const int64_t P64 = ((int64_t)h->n_cols + W - 1) / W;
     if (P64 > kPanelMaxP || h->n_cols < 4) return SPCG_OK;  // x too wide for the panel table, or
                                                               // narrower than a 16-byte unit: not built
     const int P = (int)std::max<int64_t>(P64, 1);
-    const int R = std::max(1, std::min(device_cus(), n));
+    const int R = std::max(1, std::min(device_cus() / kPanelGroups, n));  // one range per kPanelGroups CUs
     uint16_t *cnt = nullptr, *seg = nullptr;  // analysis only
     int32_t *pcs = nullptr, *sums = nullptr;
     auto release = [&]() {
@@ -419,11 +444,11 @@ int build_panels(spcg_csr *h, hipStream_t s) {
         release();
         for (int32_t *q : {h->pan_range, h->pan_vstart, h->pan_phase, h->pan_base})
             if (q) (void)hipFree(q);
-        for (void *q : {(void *)h->pan_key, h->pan_val})
+        for (void *q : {(void *)h->pan_key, h->pan_val, h->pan_part})
             if (q) (void)hipFree(q);
         h->pan_range = h->pan_vstart = h->pan_phase = h->pan_base = nullptr;
         h->pan_key = nullptr;
-        h->pan_val = nullptr;
+        h->pan_val = h->pan_part = nullptr;
         return SPCG_OK;
     };
     hipError_t e;
@@ -485,6 +510,7 @@ int build_panels(spcg_csr *h, hipStream_t s) {
                             s)) != hipSuccess ||
         (e = hipMalloc(&h->pan_val, (size_t)esz * std::max<int64_t>(total, 1))) != hipSuccess ||
         (e = hipMalloc(&h->pan_key, sizeof(uint32_t) * std::max<int64_t>(total, 1))) != hipSuccess ||
+        (e = hipMalloc(&h->pan_part, (size_t)esz * kPanelGroups * n)) != hipSuccess ||
         (e = hipMemsetAsync(h->pan_val, 0, (size_t)esz * total, s)) != hipSuccess ||
         (e = hipMemsetD32Async((hipDeviceptr_t)h->pan_key, (int)(kPadRow << 16), (size_t)total, s)) != hipSuccess)
         return fail(e, "hipMalloc(panels)");
@@ -516,8 +542,10 @@ bool use_panels(const spcg_csr *A) { return A->has_panels && panels_mode() == SP
 template <typename T>
 int launch_spmv_panels(const spcg_csr *A, const T *x, T *y, hipStream_t s) {
     const PanelDev D{A->pan_base, A->pan_vstart, A->pan_range, A->pan_phase, A->pan_val,
-                     A->pan_key, A->pan_P, A->n_cols};
-    hipLaunchKernelGGL(k_spmv_panels<T>, dim3(A->pan_R), dim3(kPanelThreads), 0, s, D, x, y);
+                     A->pan_key, A->pan_part, A->pan_P, A->n_cols, A->n_rows};
+    hipLaunchKernelGGL(k_spmv_panels<T>, dim3(A->pan_R * kPanelGroups), dim3(kPanelThreads), 0, s, D, x);
+    hipLaunchKernelGGL(k_pan_combine<T>, dim3((A->n_rows + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                       A->n_rows, (const T *)A->pan_part, y);
     SPCG_LAUNCH_CHECK("k_spmv_panels");
     return SPCG_OK;
 }

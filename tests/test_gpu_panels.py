@@ -1,9 +1,11 @@
 """GPU parity of the column-panel product y = A x (x staged in LDS by
-panels of 112 KB, rows cut into pieces of at most 32 entries, summed by
-segmented scans): bit-exact against the oracle on integer data, within the
-dot-product bound on float data, bitwise repeatable, with ragged panels, empty
-rows and panels, and the fallbacks (unsorted columns, a misaligned x, ranges
-with too many pieces) that keep the row-block kernel."""
+panels of 48 KB of doubles or 112 KB of floats, rows cut into pieces of at
+most 32 entries, summed by segmented scans, four column groups per row range
+added in order): bit-exact against the oracle on integer data, within the
+dot-product bound on float data, bitwise repeatable, with ragged panels, fewer
+panels than groups, empty rows and panels, and the fallbacks (unsorted
+columns, a misaligned x, ranges with too many pieces) that keep the row-block
+kernel."""
 import numpy as np
 import pytest
 import torch
@@ -37,7 +39,7 @@ def product(M, x, dtype=torch.float64, mode="on"):
 
 
 def width(dtype):
-    return 14336 if dtype == torch.float64 else 28672
+    return 6144 if dtype == torch.float64 else 28672
 
 
 @pytest.mark.parametrize("seed", range(3))
@@ -130,8 +132,8 @@ def test_panels_fallbacks():
 
 
 def test_panels_not_built_for_crowded_ranges():
-    # 3 M rows of one entry: every range holds far more than 4096 rows, so the
-    # panels are not built and the product keeps the row-block kernel
+    # 3 M rows of one entry: every range holds far more than 10240 pieces, so
+    # the panels are not built and the product keeps the row-block kernel
     rng = np.random.default_rng(11)
     n = 3 << 20
     rp = np.arange(n + 1, dtype=np.int32)
