@@ -572,6 +572,17 @@ def workloads(A128, x128):
         out["spmv_cold"]["lognormal_f32_row_bins"] = cold_spmv(L, xl, "f32")
     finally:
         spcg.row_binning(old)
+    # and with column panels (x staged in LDS by panels, four column groups per
+    # row range); an error here is recorded instead of ending the bench
+    old = spcg.column_panels("on")
+    try:
+        for dt in ("f64", "f32"):
+            try:
+                out["spmv_cold"][f"lognormal_{dt}_panels"] = cold_spmv(L, xl, dt)
+            except Exception as e:  # noqa: BLE001 - the line must still print
+                out["spmv_cold"][f"lognormal_{dt}_panels"] = {"error": repr(e)[:300]}
+    finally:
+        spcg.column_panels(old)
     out["spmv_cold"]["lognormal_workload"] = ("n = 200000, lognormal row lengths (median 48, "
                                               "max 4096), nnz = 15788355, seed 2")
     return out
