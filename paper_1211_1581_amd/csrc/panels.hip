@@ -19,9 +19,9 @@
 // group (a contiguous quarter of the panels), so each range reads x once in
 // all.  A workgroup walks its panels in order; each of its wavefronts takes
 // 256 of every 4096 entries of a panel's block, in rounds of 64: products
-// (value x LDS slice of x), a segmented scan across the lanes (a fixed tree in
-// each segment), and each segment's sum added to its virtual row's accumulator
-// in LDS.  A virtual row has one segment per panel, so the additions of one
+// (value x LDS slice of x), a segmented scan across the lanes by DPP moves (a
+// fixed tree in each segment), and each segment's sum added to its virtual
+// row's accumulator in LDS.  A virtual row has one segment per panel, so the additions of one
 // panel never meet, and no barrier is needed between its rounds.  The next
 // panel's slice of x is loaded into registers while the current panel is used
 // and written to LDS at the switch; two chunks of entries are in flight per
@@ -265,9 +265,52 @@ struct Entries {
     uint32_t k[kPanelU];
 };
 
+// v moved across lanes by DPP control CTRL (a VALU operand modifier, no LDS
+// round trip) in the rows of 16 lanes that ROWS selects; lanes of other rows,
+// and lanes whose source leaves the row, read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp0(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, true);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp0(float v) {
+    return __int_as_float(dpp0<CTRL, ROWS>(__float_as_int(v)));
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp0(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp0<CTRL, ROWS>((int)b), hi = dpp0<CTRL, ROWS>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+constexpr int kDppRowShr = 0x110;   // + n: lane l <- lane l - n within its row of 16
+constexpr int kDppWaveShr1 = 0x138;  // lane l <- lane l - 1 across the wavefront
+constexpr int kDppBcast15 = 0x142;   // rows 1 and 3 <- lanes 15 and 47 (row mask 0xA)
+constexpr int kDppBcast31 = 0x143;   // rows 2 and 3 <- lane 31 (row mask 0xC)
+
+// Inclusive scan of s over each segment of lanes [start, lane] (a segment
+// spans at most 32 lanes, so at most three rows of 16): prefix sums inside the
+// rows by four row shifts, then the rows' carries, rows 1 and 3 from lanes 15
+// and 47 and rows 2 and 3 from lane 31 (which holds its segment's sum from the
+// start by then).  Every lane runs every step; a fixed tree per segment.
 template <typename T>
-__device__ __forceinline__ T shfl_up_t(T v, int o) {
-    return __shfl_up(v, (unsigned)o, 64);
+__device__ __forceinline__ T segmented_scan(T s, int lane, int start) {
+    T t;
+    t = dpp0<kDppRowShr + 1, 0xF>(s);
+    if (lane - 1 >= start && (lane & 15) >= 1) s += t;
+    t = dpp0<kDppRowShr + 2, 0xF>(s);
+    if (lane - 2 >= start && (lane & 15) >= 2) s += t;
+    t = dpp0<kDppRowShr + 4, 0xF>(s);
+    if (lane - 4 >= start && (lane & 15) >= 4) s += t;
+    t = dpp0<kDppRowShr + 8, 0xF>(s);
+    if (lane - 8 >= start && (lane & 15) >= 8) s += t;
+    t = dpp0<kDppBcast15, 0xA>(s);
+    if (((lane >> 4) & 1) && start < (lane & ~15)) s += t;
+    t = dpp0<kDppBcast31, 0xC>(s);
+    if (lane >= 32 && start < 32) s += t;
+    return s;
 }
 
 template <typename T>
@@ -370,15 +413,10 @@ k_spmv_panels(PanelDev D, const T *__restrict__ x) {
             // each segment's last lane adds the sum to its virtual row
 #pragma unroll
             for (int u = 0; u < kPanelU; ++u) {
-                const int prev = __shfl_up(id[u], 1u, 64);
+                const int prev = dpp0<kDppWaveShr1, 0xF>(id[u]);
                 const unsigned long long heads = __ballot(lane == 0 || prev != id[u]);
                 const int start = 63 - __clzll(heads & (below | (1ull << lane)));
-                T s = pr[u];
-#pragma unroll
-                for (int o = 1; o < kPiece; o <<= 1) {
-                    const T t = shfl_up_t(s, o);
-                    if (lane - o >= start) s += t;
-                }
+                const T s = segmented_scan(pr[u], lane, start);
                 const bool tail = lane == 63 || ((heads >> (lane + 1)) & 1ull);
                 if (tail && id[u] != (int)kPadRow) vacc[id[u]] += s;
             }
