@@ -188,9 +188,10 @@ int spcg_csr_run_info(spcg_csr_t A, int64_t *n_chunks, int64_t *n_starts);
  * pieces into its group's partial vector, and a second kernel adds the four
  * parts in order.  The order of every addition is fixed by the matrix
  * (results repeat bitwise; they differ from the row-block kernel's within
- * rounding).  The partial buffer makes such a handle's products
- * non-reentrant: products on one handle with panels must not overlap (calls
- * on one stream are fine).  Built only for rows with strictly increasing
+ * rounding).  Products of one handle share its partial buffer, so they are
+ * serialized: a product issued on another stream than the handle's last one
+ * waits for that one to finish (hipStreamWaitEvent; host calls on one handle
+ * take a lock).  Built only for rows with strictly increasing
  * columns, n_cols >= 4, at most 1024 panels, at most 10240 pieces per range
  * and fewer than 65536 entries per (range, panel); otherwise the handle has
  * no panels and the other kernels run.  Used only when x is 16-byte aligned.

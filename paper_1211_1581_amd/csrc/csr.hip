@@ -231,6 +231,7 @@ static void release(spcg_csr *h) {
         if (p) (void)hipFree(p);
     for (void *p : {(void *)h->run_mask, (void *)h->pan_key, h->pan_val, h->pan_part})
         if (p) (void)hipFree(p);
+    if (h->pan_done) (void)hipEventDestroy(h->pan_done);
     for (int i = 0; i < h->n_events; ++i) (void)hipEventDestroy(h->events[i]);
     delete[] h->events;
     delete h;

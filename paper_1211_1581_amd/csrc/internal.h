@@ -26,6 +26,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "spcg.h"
 
 struct spcg_csr {
@@ -63,6 +65,12 @@ struct spcg_csr {
     uint32_t *pan_key = nullptr;
     void *pan_val = nullptr;
     void *pan_part = nullptr;  // [column groups][n_rows] partial products of spmv_csr
+    // the last panel product's stream and completion: a product on another
+    // stream waits for it, so products sharing pan_part never overlap
+    hipEvent_t pan_done = nullptr;
+    hipStream_t pan_last = nullptr;
+    bool pan_any = false;
+    std::mutex pan_mu;
     int pan_P = 0, pan_R = 0, pan_W = 0;
     int64_t pan_entries = 0;  // entries of the panel copy, padding included
     bool has_panels = false;

@@ -549,6 +549,7 @@ int build_panels(spcg_csr *h, hipStream_t s) {
         (e = hipMalloc(&h->pan_val, (size_t)esz * std::max<int64_t>(total, 1))) != hipSuccess ||
         (e = hipMalloc(&h->pan_key, sizeof(uint32_t) * std::max<int64_t>(total, 1))) != hipSuccess ||
         (e = hipMalloc(&h->pan_part, (size_t)esz * kPanelGroups * n)) != hipSuccess ||
+        (!h->pan_done && (e = hipEventCreateWithFlags(&h->pan_done, hipEventDisableTiming)) != hipSuccess) ||
         (e = hipMemsetAsync(h->pan_val, 0, (size_t)esz * total, s)) != hipSuccess ||
         (e = hipMemsetD32Async((hipDeviceptr_t)h->pan_key, (int)(kPadRow << 16), (size_t)total, s)) != hipSuccess)
         return fail(e, "hipMalloc(panels)");
@@ -579,12 +580,21 @@ bool use_panels(const spcg_csr *A) { return A->has_panels && panels_mode() == SP
 
 template <typename T>
 int launch_spmv_panels(const spcg_csr *A, const T *x, T *y, hipStream_t s) {
+    // products share the handle's partial vectors: one on another stream than
+    // the last waits for the last one's completion (on one stream, the order of
+    // the stream already does)
+    spcg_csr *H = const_cast<spcg_csr *>(A);
+    std::lock_guard<std::mutex> lock(H->pan_mu);
+    if (H->pan_any && H->pan_last != s) SPCG_TRY(hipStreamWaitEvent(s, H->pan_done, 0));
     const PanelDev D{A->pan_base, A->pan_vstart, A->pan_range, A->pan_phase, A->pan_val,
                      A->pan_key, A->pan_part, A->pan_P, A->n_cols, A->n_rows};
     hipLaunchKernelGGL(k_spmv_panels<T>, dim3(A->pan_R * kPanelGroups), dim3(kPanelThreads), 0, s, D, x);
     hipLaunchKernelGGL(k_pan_combine<T>, dim3((A->n_rows + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
                        A->n_rows, (const T *)A->pan_part, y);
     SPCG_LAUNCH_CHECK("k_spmv_panels");
+    SPCG_TRY(hipEventRecord(H->pan_done, s));
+    H->pan_last = s;
+    H->pan_any = true;
     return SPCG_OK;
 }
 

@@ -162,3 +162,30 @@ def test_panels_not_built_for_narrow_x():
     M = with_panels(A, torch.float32)
     assert M.panel_info() is None
     assert np.array_equal(product(M, x, torch.float32).astype(np.float64), oracle.spmv(A, x))
+
+
+def test_panels_products_on_two_streams():
+    # products of one panel handle on two streams share its partial vectors:
+    # the second waits for the first, so both results are right
+    S = spcg()
+    A, x1 = I.random_csr_small(20000, 60000, 5, max_len=80, integer=True)
+    x2 = -x1[::-1].copy()
+    M = with_panels(A)
+    assert M.panel_info() is not None
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    xd1, xd2 = to_dev(x1), to_dev(x2)
+    y1 = torch.empty(A.n_rows, dtype=torch.float64, device="cuda")
+    y2 = torch.empty_like(y1)
+    torch.cuda.synchronize()
+    old = S.column_panels("on")
+    try:
+        for _ in range(5):
+            with torch.cuda.stream(s1):
+                S.spmv_csr(M, xd1, y1)
+            with torch.cuda.stream(s2):
+                S.spmv_csr(M, xd2, y2)
+        torch.cuda.synchronize()
+    finally:
+        S.column_panels(old)
+    assert np.array_equal(y1.cpu().numpy(), oracle.spmv(A, x1))
+    assert np.array_equal(y2.cpu().numpy(), oracle.spmv(A, x2))
