@@ -189,3 +189,18 @@ def test_panels_products_on_two_streams():
         S.column_panels(old)
     assert np.array_equal(y1.cpu().numpy(), oracle.spmv(A, x1))
     assert np.array_equal(y2.cpu().numpy(), oracle.spmv(A, x2))
+
+
+def test_panels_not_built_for_oversized_blocks():
+    # 1000 dense rows over 6000 columns (one FP64 panel): each range's block
+    # holds about 94 000 entries, more than the 16-bit layout offsets reach,
+    # so the panels are not built and the row-block kernel runs
+    rng = np.random.default_rng(12)
+    n, nc = 1000, 6000
+    rp = (np.arange(n + 1, dtype=np.int64) * nc).astype(np.int32)
+    col = np.tile(np.arange(nc, dtype=np.int32), n)
+    A = I.CSR(n, nc, rp, col, rng.integers(-3, 4, n * nc).astype(np.float64))
+    x = rng.integers(-3, 4, nc).astype(np.float64)
+    M = with_panels(A)
+    assert M.panel_info() is None
+    assert np.array_equal(product(M, x), oracle.spmv(A, x))
