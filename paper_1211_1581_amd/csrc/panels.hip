@@ -41,19 +41,22 @@ static std::atomic<int> g_panels{SPCG_PANELS_OFF};
 
 int panels_mode() { return g_panels.load(std::memory_order_relaxed); }
 
-constexpr int kPanelThreads = 1024;
-constexpr int kPanelMaxRows = 10240;    // virtual rows per range (accumulators in LDS)
-constexpr int kPanelGroups = 4;         // column groups: workgroups per range
-constexpr int kPanelU = 4;              // entries per thread and chunk (rounds of 64 per wavefront)
+constexpr int kPanelThreads = 1024;  // = the lanes of a (range, panel) block
+constexpr int kPanelMaxRows = 10240;  // virtual rows per range (accumulators in LDS)
+constexpr int kPanelGroups = 4;       // column groups: workgroups per range
+constexpr int kPanelU = 4;            // rounds per chunk (each lane's entries per chunk)
 constexpr int kPanelChunk = kPanelThreads * kPanelU;
-constexpr int kPanelMaxP = 1024;        // panels
-constexpr int kPiece = 32;              // entries per virtual row (at most one lane round)
-constexpr uint32_t kPadRow = 0xFFFFu;   // the virtual row of a padding entry
+constexpr int kPanelMaxP = 1024;      // panels
+constexpr int kPiece = 32;            // entries per virtual row
+constexpr uint32_t kKeyPad = 1u << 30;   // a padding entry: no product
+constexpr uint32_t kKeyLast = 1u << 31;  // the last entry of its segment: flush the lane's sum
+constexpr uint32_t kKeyRow = 0x3fffu;    // the virtual row field, after the shift by 16
+static_assert(kPanelMaxRows <= (1 << 14), "the key's virtual row field has 14 bits");
 
-// One slice of x by value size: 48 KB of doubles (3 16-byte units per thread;
+// One slice of x by value size: 64 KB of doubles (4 16-byte units per thread;
 // with 80 KB of accumulators), 112 KB of floats (7 units; 40 KB of
-// accumulators), the sizes measured fastest on the lognormal matrix.
-constexpr int panel_bytes(int esz) { return esz == 8 ? 48 * 1024 : 112 * 1024; }
+// accumulators).
+constexpr int panel_bytes(int esz) { return esz == 8 ? 64 * 1024 : 112 * 1024; }
 
 template <typename T>
 constexpr int panel_width() { return panel_bytes((int)sizeof(T)) / (int)sizeof(T); }
@@ -63,8 +66,8 @@ struct PanelDev {
     const int32_t *__restrict__ vstart;  // [n + 1] first virtual row of each row
     const int32_t *__restrict__ range;   // [R + 1] first row of each range
     const int32_t *__restrict__ phase;   // [R][P + 1] entry offset of each panel in its range
-    const void *__restrict__ val;        // [nnz] panel-ordered values
-    const uint32_t *__restrict__ key;    // [nnz] panel column | virtual row in the range << 16
+    const void *__restrict__ val;        // panel-ordered values
+    const uint32_t *__restrict__ key;    // panel column | virtual row in the range << 16 | flags
     void *__restrict__ part;             // [kPanelGroups][n_rows] the groups' partial products
     int P, n_cols, n_rows;
 };
@@ -86,6 +89,17 @@ __device__ __forceinline__ T add_run(T part, const T *s, int b, int e) {
 
 // virtual rows of a row of len entries
 __device__ __forceinline__ int pieces(int len) { return len > 0 ? (len + kPiece - 1) / kPiece : 1; }
+
+// the row holding virtual row v: the last i with vstart[i] <= v
+__device__ __forceinline__ int row_of(int n, const int32_t *__restrict__ vstart, int v) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (vstart[mid] <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
 
 // ------------------------------------------------------------- analysis --
 
@@ -112,105 +126,182 @@ k_pan_ranges(int n, const int32_t *__restrict__ rp, int R, int64_t M, int32_t *_
     range[r] = lo;
 }
 
-// Virtual rows per row (pieces of at most kPiece entries, one for an empty row)
+// Virtual rows per row (one for an empty row); flags[0] |= 1 for a row whose
+// columns are not strictly increasing
 __global__ void __launch_bounds__(kBlock)
-k_pan_pieces(int n, const int32_t *__restrict__ rp, int32_t *__restrict__ cnt) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) cnt[i] = pieces(rp[i + 1] - rp[i]);
-}
-
-// Per virtual row: entries in each panel (cnt[v * P + p]); flags[0] |= 1 for a
-// row whose columns are not strictly increasing
-__global__ void __launch_bounds__(kBlock)
-k_pan_counts(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-             const int32_t *__restrict__ vstart, int W, int P, uint16_t *__restrict__ cnt,
-             int32_t *flags) {
+k_pan_pieces(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+             int32_t *__restrict__ cnt, int32_t *flags) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    const int a = rp[i], b = rp[i + 1], v0 = vstart[i];
-    uint16_t *c0 = cnt + (size_t)v0 * P;
-    for (int q = 0; q < pieces(b - a) * P; ++q) c0[q] = 0;
-    int prev = -1, bad = 0;
-    for (int k = a; k < b; ++k) {
-        const int cc = col[k];
-        bad |= cc <= prev;
-        prev = cc;
-        uint16_t *c = cnt + ((size_t)v0 + (k - a) / kPiece) * P + cc / W;
-        *c = (uint16_t)(*c + 1);
-    }
+    const int a = rp[i], b = rp[i + 1];
+    cnt[i] = pieces(b - a);
+    int bad = 0;
+    for (int k = a + 1; k < b; ++k) bad |= col[k] <= col[k - 1];
     if (bad) atomicOr(&flags[0], 1);
 }
 
-// One workgroup per range, one thread per panel: the start of every virtual
-// row's segment in the panel's block (uint16, padded so that no segment crosses
-// a multiple of 64), then the start of every panel in the range (a scan over the
-// panels) and the range's entry count (tot[r]).  flags[0] |= 2 if a block holds
-// 65536 entries or more.
-__global__ void __launch_bounds__(kPanelThreads)
-k_pan_layout(int P, const int32_t *__restrict__ range, const int32_t *__restrict__ vstart,
-             const uint16_t *__restrict__ cnt, uint16_t *__restrict__ seg,
-             int32_t *__restrict__ phase, int32_t *__restrict__ tot, int32_t *flags) {
-    __shared__ int sh[kPanelThreads];
-    const int r = blockIdx.x, p = threadIdx.x;
-    const int a = vstart[range[r]], rows = vstart[range[r + 1]] - a;  // the range's virtual rows
-    int pos = 0;
-    if (p < P) {
-        uint16_t *sp = seg + (size_t)P * (a + r) + (size_t)p * (rows + 1);
-        for (int j = 0; j < rows; ++j) {
-            const int c = cnt[(size_t)(a + j) * P + p];
-            if (c > 0 && (pos & 63) + c > 64) pos = (pos + 63) & ~63;
-            sp[j] = (uint16_t)min(pos, 65535);
-            pos += c;
-        }
-        sp[rows] = (uint16_t)min(pos, 65535);
-        if (pos > 65535) atomicOr(&flags[0], 2);
-    }
-    sh[p] = pos;
+// Virtual row j of a row of np takes the row's entries j, j + np, j + 2 np, ...
+// (strided, so every virtual row spreads over the row's columns and its
+// segments, its entries in one panel, stay short).  One thread per virtual
+// row: its entries per panel (cnt[v * P + p], zeroed before).
+__global__ void __launch_bounds__(kBlock)
+k_pan_counts(int n, int V, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+             const int32_t *__restrict__ vstart, int W, int P, uint32_t *__restrict__ cnt) {
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    if (v >= V) return;
+    const int i = row_of(n, vstart, v);
+    const int np = vstart[i + 1] - vstart[i];
+    uint32_t *c0 = cnt + (size_t)v * P;
+    for (int k = rp[i] + (v - vstart[i]); k < rp[i + 1]; k += np) ++c0[col[k] / W];
+}
+
+// One wavefront per (range r, panel p) block: the segments (the block's
+// virtual rows' entries in the panel, at most kPiece each) are packed into
+// kPanelThreads lanes of equal height H, lane l's rounds 0..H-1 at entries
+// l, l + kPanelThreads, ...; the block holds kPanelThreads * H entries.  Lane
+// by lane, each lane takes the longest remaining segment that fits its rest
+// (H = max(ceil(entries / lanes), longest segment), raised by one until all
+// fit; the segments of one length are taken in virtual-row order).  Each
+// count cnt[v * P + p] is then replaced by its segment's place: lane | first
+// round << 10.  blk_h[r * P + p] = H; flags[0] |= 2 if none fits (never
+// expected: from H = entries / lanes + kPiece on every segment fits).
+__global__ void __launch_bounds__(64)
+k_pan_pack(int P, const int32_t *__restrict__ range, const int32_t *__restrict__ vstart,
+           uint32_t *__restrict__ cnt, int32_t *__restrict__ blk_h, int32_t *flags) {
+    __shared__ uint32_t take[kPanelMaxRows];           // places, grouped by segment length
+    __shared__ int hist[kPiece + 1], off[kPiece + 1], nxt[kPiece + 1];
+    const int r = blockIdx.x / P, p = blockIdx.x % P, lane = threadIdx.x;
+    const int a = vstart[range[r]], rows = vstart[range[r + 1]] - a;
+    uint32_t *cp = cnt + (size_t)a * P + p;
+    if (lane <= kPiece) hist[lane] = 0;
     __syncthreads();
-    for (int o = 1; o < kPanelThreads; o <<= 1) {  // inclusive scan of the block sizes
-        const int t = p >= o ? sh[p - o] : 0;
-        __syncthreads();
-        sh[p] += t;
-        __syncthreads();
+    int ent = 0, longest = 0;
+    for (int j = lane; j < rows; j += 64) {
+        const int c = (int)cp[(size_t)j * P];
+        if (c > 0) atomicAdd(&hist[c], 1);
+        ent += c;
+        longest = max(longest, c);
     }
-    if (p < P) phase[(size_t)r * (P + 1) + p] = sh[p] - pos;
-    if (p == 0) {
-        phase[(size_t)r * (P + 1) + P] = sh[kPanelThreads - 1];
-        tot[r] = sh[kPanelThreads - 1];
+    for (int o = 32; o > 0; o >>= 1) {
+        ent += __shfl_xor(ent, o);
+        longest = max(longest, __shfl_xor(longest, o));
+    }
+    __syncthreads();
+    if (lane == 0) {
+        int o = 0;
+        for (int c = kPiece; c >= 1; --c) {
+            off[c] = o;
+            o += hist[c];
+        }
+        int H = ent == 0 ? 0 : max((ent + kPanelThreads - 1) / kPanelThreads, longest);
+        bool fits = ent == 0;
+        for (int tries = 0; !fits && tries <= kPiece + 1; ++tries, ++H) {
+            uint32_t mask = 0;  // bit c - 1: segments of length c remain
+            for (int c = 1; c <= kPiece; ++c) {
+                nxt[c] = off[c];
+                if (hist[c] > 0) mask |= 1u << (c - 1);
+            }
+            for (int l = 0; l < kPanelThreads && mask; ++l) {
+                int cap = H, pos = 0;
+                while (cap > 0) {
+                    const uint32_t m = mask & (cap >= 32 ? 0xffffffffu : (1u << cap) - 1u);
+                    if (!m) break;
+                    const int c = 32 - __clz(m);
+                    const int idx = nxt[c], end = off[c] + hist[c];
+                    const int k = min(cap / c, end - idx);
+                    for (int q = 0; q < k; ++q) take[idx + q] = (uint32_t)l | (uint32_t)(pos + q * c) << 10;
+                    nxt[c] = idx + k;
+                    pos += k * c;
+                    cap -= k * c;
+                    if (idx + k == end) mask &= ~(1u << (c - 1));
+                }
+            }
+            if (!mask) {
+                fits = true;
+                break;
+            }
+        }
+        if (!fits) atomicOr(&flags[0], 2);
+        blk_h[blockIdx.x] = fits ? H : 0;
+        for (int c = 1; c <= kPiece; ++c) nxt[c] = off[c];  // cursors of the placement pass
+    }
+    __syncthreads();
+    // places in virtual-row order, 64 rows at a time: the rows of one length
+    // ranked by ballot (lanes of a wavefront run in lockstep; nxt[] is read and
+    // advanced by the whole wavefront at once)
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int j0 = 0; j0 < rows; j0 += 64) {
+        const int j = j0 + lane;
+        const int c = j < rows ? (int)cp[(size_t)j * P] : 0;
+        bool pending = c > 0;
+        while (true) {
+            const unsigned long long pend = __ballot(pending);
+            if (!pend) break;
+            const int c0 = __shfl(c, __ffsll((long long)pend) - 1);
+            const unsigned long long m = __ballot(pending && c == c0);
+            const int base = nxt[c0];
+            if (pending && c == c0) {
+                cp[(size_t)j * P] = take[base + __popcll(m & below)];
+                pending = false;
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (lane == 0) nxt[c0] = base + __popcll(m);
+            __builtin_amdgcn_wave_barrier();
+        }
     }
 }
 
-// The panel-ordered copy: values and keys (panel column | virtual row << 16)
+// Per range (one thread each): every panel's first entry in the range and the
+// range's entry count (into tot[r]); flags[0] |= 4 if that count overflows int32
+__global__ void __launch_bounds__(kBlock)
+k_pan_phase(int R, int P, const int32_t *__restrict__ blk_h, int32_t *__restrict__ phase,
+            int32_t *__restrict__ tot, int32_t *flags) {
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= R) return;
+    int64_t o = 0;
+    for (int p = 0; p < P; ++p) {
+        phase[(size_t)r * (P + 1) + p] = (int32_t)min(o, (int64_t)INT32_MAX);
+        o += (int64_t)kPanelThreads * blk_h[(size_t)r * P + p];
+    }
+    phase[(size_t)r * (P + 1) + P] = (int32_t)min(o, (int64_t)INT32_MAX);
+    tot[r] = (int32_t)min(o, (int64_t)INT32_MAX);
+    if (o > INT32_MAX) atomicOr(&flags[0], 4);
+}
+
+// The panel-ordered copy, one thread per virtual row: entry q of a segment
+// placed at (lane l, first round h0) goes to the block's entry
+// (h0 + q) * kPanelThreads + l, with key panel column | virtual row in the
+// range << 16 | kKeyLast on the segment's last entry
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_pan_scatter(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+k_pan_scatter(int n, int V, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
               const T *__restrict__ vals, int W, int P, int R, const int32_t *__restrict__ range,
-              const int32_t *__restrict__ vstart, const uint16_t *__restrict__ seg,
+              const int32_t *__restrict__ vstart, const uint32_t *__restrict__ place,
               const int32_t *__restrict__ phase, const int32_t *__restrict__ rbase,
               T *__restrict__ pval, uint32_t *__restrict__ pkey) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    int lo = 0, hi = R;  // the last range r with range[r] <= i
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    if (v >= V) return;
+    const int i = row_of(n, vstart, v);
+    int lo = 0, hi = R - 1;  // the last range r with range[r] <= i
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (range[mid] <= i) lo = mid;
         else hi = mid - 1;
     }
-    const int r = lo, va = vstart[range[r]], vrows = vstart[range[r + 1]] - va;
-    const uint16_t *sr = seg + (size_t)P * (va + r);
-    const int base = rbase[r], a = rp[i], v0 = vstart[i] - va;
+    const int r = lo, vl = v - vstart[range[r]], np = vstart[i + 1] - vstart[i], b = rp[i + 1];
     int prev = -1, pos = 0;
-    for (int k = a; k < rp[i + 1]; ++k) {
-        const int c = col[k];
-        const int p = c / W, v = v0 + (k - a) / kPiece;
-        const int key = v * P + p;  // (piece, panel) changes together
-        if (key != prev) {
-            pos = base + phase[(size_t)r * (P + 1) + p] + sr[(size_t)p * (vrows + 1) + v];
-            prev = key;
+    for (int k = rp[i] + (v - vstart[i]); k < b; k += np) {
+        const int c = col[k], p = c / W;
+        if (p != prev) {
+            const uint32_t pl = place[(size_t)v * P + p];
+            pos = rbase[r] + phase[(size_t)r * (P + 1) + p] + (int)(pl >> 10) * kPanelThreads +
+                  (int)(pl & (kPanelThreads - 1));
+            prev = p;
         }
+        const bool last = k + np >= b || col[k + np] / W != p;
         pval[pos] = vals[k];
-        pkey[pos] = (uint32_t)(c - p * W) | (uint32_t)v << 16;
-        ++pos;
+        pkey[pos] = (uint32_t)(c - p * W) | (uint32_t)vl << 16 | (last ? kKeyLast : 0u);
+        pos += kPanelThreads;
     }
 }
 
@@ -257,85 +348,48 @@ struct Slice {
     }
 };
 
-// A wavefront's share of a chunk in registers: round u, lane l holds entry
-// 256 w + 64 u + l of the chunk (w the wavefront)
+// A thread's entries of a chunk in registers: round u of lane t is the
+// block's entry (4 c + u) kPanelThreads + t for chunk c
 template <typename T>
 struct Entries {
     T v[kPanelU];
     uint32_t k[kPanelU];
 };
 
-// v moved across lanes by DPP control CTRL (a VALU operand modifier, no LDS
-// round trip) in the rows of 16 lanes that ROWS selects; lanes of other rows,
-// and lanes whose source leaves the row, read 0.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ int dpp0(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, true);
-}
-
-template <int CTRL, int ROWS>
-__device__ __forceinline__ float dpp0(float v) {
-    return __int_as_float(dpp0<CTRL, ROWS>(__float_as_int(v)));
-}
-
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp0(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = dpp0<CTRL, ROWS>((int)b), hi = dpp0<CTRL, ROWS>((int)(b >> 32));
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-constexpr int kDppRowShr = 0x110;   // + n: lane l <- lane l - n within its row of 16
-constexpr int kDppWaveShr1 = 0x138;  // lane l <- lane l - 1 across the wavefront
-constexpr int kDppBcast15 = 0x142;   // rows 1 and 3 <- lanes 15 and 47 (row mask 0xA)
-constexpr int kDppBcast31 = 0x143;   // rows 2 and 3 <- lane 31 (row mask 0xC)
-
-// Inclusive scan of s over each segment of lanes [start, lane] (a segment
-// spans at most 32 lanes, so at most three rows of 16): prefix sums inside the
-// rows by four row shifts, then the rows' carries, rows 1 and 3 from lanes 15
-// and 47 and rows 2 and 3 from lane 31 (which holds its segment's sum from the
-// start by then).  Every lane runs every step; a fixed tree per segment.
-template <typename T>
-__device__ __forceinline__ T segmented_scan(T s, int lane, int start) {
-    T t;
-    t = dpp0<kDppRowShr + 1, 0xF>(s);
-    if (lane - 1 >= start && (lane & 15) >= 1) s += t;
-    t = dpp0<kDppRowShr + 2, 0xF>(s);
-    if (lane - 2 >= start && (lane & 15) >= 2) s += t;
-    t = dpp0<kDppRowShr + 4, 0xF>(s);
-    if (lane - 4 >= start && (lane & 15) >= 4) s += t;
-    t = dpp0<kDppRowShr + 8, 0xF>(s);
-    if (lane - 8 >= start && (lane & 15) >= 8) s += t;
-    t = dpp0<kDppBcast15, 0xA>(s);
-    if (((lane >> 4) & 1) && start < (lane & ~15)) s += t;
-    t = dpp0<kDppBcast31, 0xC>(s);
-    if (lane >= 32 && start < 32) s += t;
-    return s;
-}
-
 template <typename T>
 __global__ void __launch_bounds__(kPanelThreads)
 k_spmv_panels(PanelDev D, const T *__restrict__ x) {
     constexpr int W = panel_width<T>();
-    __shared__ __align__(16) T xs[W];      // the panel's slice of x; at the end the pieces' sums
+    __shared__ __align__(16) T xs[W];      // the panel's slice of x
     __shared__ T vacc[kPanelMaxRows];      // every virtual row's running sum
     __shared__ int ph[kPanelMaxP + 1];
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wbase = (tid >> 6) * (kPanelChunk / (kPanelThreads / 64));  // the wavefront's entries
-    const unsigned long long below = (1ull << lane) - 1ull;
-    // workgroup -> (range r, column group grp); the group walks panels [p0, P)
+    const int tid = threadIdx.x;
+    // workgroup -> (range r, column group grp)
     const int r = blockIdx.x / kPanelGroups, grp = blockIdx.x % kPanelGroups;
     const int a = D.range[r], rows = D.range[r + 1] - a;
     if (rows <= 0) return;  // uniform
     const int va = D.vstart[a], vrows = D.vstart[a + rows] - va;
-    const int PT = D.P, per = (PT + kPanelGroups - 1) / kPanelGroups;
-    const int p0 = min(grp * per, PT), P = min(p0 + per, PT);
+    const int PT = D.P;
     const int base = D.base[r];
     const T *__restrict__ val = (const T *)D.val + base;
     const uint32_t *__restrict__ key = D.key + base;
     for (int p = tid; p <= PT; p += kPanelThreads) ph[p] = D.phase[(size_t)r * (PT + 1) + p];
     for (int j = tid; j < vrows; j += kPanelThreads) vacc[j] = T(0);
     __syncthreads();
+    // the group's panels [p0, P): a quarter of the range's entries (the first
+    // panel p with ph[p] >= g / kPanelGroups of them starts group g)
+    auto split = [&](int g) {
+        if (g >= kPanelGroups) return PT;
+        const int64_t t = (int64_t)ph[PT] * g / kPanelGroups;
+        int lo = 0, hi = PT;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (ph[mid] >= t) hi = mid;
+            else lo = mid + 1;
+        }
+        return lo;
+    };
+    const int p0 = grp == 0 ? 0 : split(grp), P = split(grp + 1);
 
     auto next_panel = [&](int p) {  // the first non-empty panel after p (P if none)
         ++p;
@@ -356,7 +410,7 @@ k_spmv_panels(PanelDev D, const T *__restrict__ x) {
         const int e0 = p < P ? ph[p] + c : ph[P] - 1, last = ph[min(p + 1, P)] - 1;
 #pragma unroll
         for (int u = 0; u < kPanelU; ++u) {
-            const int e = min(e0 + wbase + 64 * u + lane, last);
+            const int e = min(e0 + kPanelThreads * u + tid, last);
             E.v[u] = __builtin_nontemporal_load(val + e);
             E.k[u] = __builtin_nontemporal_load(key + e);
         }
@@ -382,6 +436,7 @@ k_spmv_panels(PanelDev D, const T *__restrict__ x) {
         advance(pf, cf);
         __syncthreads();
         int pc = first, cc = 0;  // the chunk being summed
+        T acc = T(0);            // the lane's sum of its current segment
         auto step = [&](Entries<T> &E) {
             if (cc == 0 && pc != first) {
                 // a new panel: every wavefront is done with the last slice; the
@@ -392,33 +447,32 @@ k_spmv_panels(PanelDev D, const T *__restrict__ x) {
                 sn.load(x, D.n_cols, pnext < P ? pnext : pc);
                 __syncthreads();
             }
-            // products and virtual rows (padding and entries past the chunk: row
-            // kPadRow, product 0), then E refilled with the chunk after the other
-            // set's (kept after the products, so the refill lands in E's own
-            // registers instead of copies that wait for every load in flight)
-            const int cnt = min(kPanelChunk, ph[pc + 1] - ph[pc] - cc);
+            // products (a padding entry, or a round past the block: none), then
+            // E refilled with the chunk after the other set's (kept after the
+            // products, so the refill lands in E's own registers instead of
+            // copies that wait for every load in flight)
+            const int rounds = min(kPanelU, (ph[pc + 1] - ph[pc] - cc) / kPanelThreads);
             T pr[kPanelU];
-            int id[kPanelU];
+            uint32_t kk[kPanelU];
 #pragma unroll
             for (int u = 0; u < kPanelU; ++u) {
-                const bool in = wbase + 64 * u + lane < cnt;
-                id[u] = in ? (int)(E.k[u] >> 16) : (int)kPadRow;
-                const T t = E.v[u] * xs[E.k[u] & 0xffffu];
-                pr[u] = id[u] != (int)kPadRow ? t : T(0);
+                kk[u] = u < rounds ? E.k[u] : kKeyPad;
+                const T t = E.v[u] * xs[kk[u] & 0xffffu];
+                pr[u] = (kk[u] & kKeyPad) ? T(0) : t;
             }
             __builtin_amdgcn_sched_barrier(0);
             fetch(E, pf, cf);
             advance(pf, cf);
-            // per round: a segmented scan (segments of at most kPiece lanes), then
-            // each segment's last lane adds the sum to its virtual row
+            // the lane's segments, entry by entry: at a segment's last entry its
+            // sum goes to its virtual row (a virtual row has one segment per
+            // panel, so no two lanes add to one row within a panel)
 #pragma unroll
             for (int u = 0; u < kPanelU; ++u) {
-                const int prev = dpp0<kDppWaveShr1, 0xF>(id[u]);
-                const unsigned long long heads = __ballot(lane == 0 || prev != id[u]);
-                const int start = 63 - __clzll(heads & (below | (1ull << lane)));
-                const T s = segmented_scan(pr[u], lane, start);
-                const bool tail = lane == 63 || ((heads >> (lane + 1)) & 1ull);
-                if (tail && id[u] != (int)kPadRow) vacc[id[u]] += s;
+                acc += pr[u];
+                if (kk[u] & kKeyLast) {
+                    vacc[(kk[u] >> 16) & kKeyRow] += acc;
+                    acc = T(0);
+                }
             }
             advance(pc, cc);
         };
@@ -466,13 +520,14 @@ int build_panels(spcg_csr *h, hipStream_t s) {
                                                               // narrower than a 16-byte unit: not built
     const int P = (int)std::max<int64_t>(P64, 1);
     const int R = std::max(1, std::min(device_cus() / kPanelGroups, n));  // one range per kPanelGroups CUs
-    uint16_t *cnt = nullptr, *seg = nullptr;  // analysis only
-    int32_t *pcs = nullptr, *sums = nullptr;
+    uint32_t *cnt = nullptr;  // analysis only: counts, then places, per (virtual row, panel)
+    int32_t *pcs = nullptr, *sums = nullptr, *blk = nullptr;
     auto release = [&]() {
-        for (uint16_t *q : {cnt, seg})
+        if (cnt) (void)hipFree(cnt);
+        for (int32_t *q : {pcs, sums, blk})
             if (q) (void)hipFree(q);
-        for (int32_t *q : {pcs, sums})
-            if (q) (void)hipFree(q);
+        cnt = nullptr;
+        pcs = sums = blk = nullptr;
     };
     auto fail = [&](hipError_t e, const char *what) {
         release();
@@ -490,15 +545,19 @@ int build_panels(spcg_csr *h, hipStream_t s) {
         return SPCG_OK;
     };
     hipError_t e;
-    // ranges of rows, then the virtual rows of every row (vstart[n] = all of them)
+    int32_t *hp = (int32_t *)h->h_pinned;
+    // ranges of rows, then the virtual rows of every row (vstart[n] = all of
+    // them) and the sorted-columns check
     if ((e = hipMalloc(&h->pan_range, sizeof(int32_t) * ((size_t)R + 1))) != hipSuccess ||
         (e = hipMalloc(&h->pan_vstart, sizeof(int32_t) * ((size_t)n + 1))) != hipSuccess ||
         (e = hipMalloc(&pcs, sizeof(int32_t) * (size_t)n)) != hipSuccess ||
         (e = hipMalloc(&sums, sizeof(int32_t) * (size_t)scan_sums_slots(n))) != hipSuccess)
         return fail(e, "hipMalloc(panel ranges)");
+    hipLaunchKernelGGL(k_pan_zero, dim3(1), dim3(64), 0, s, h->flags);
     hipLaunchKernelGGL(k_pan_ranges, dim3((R + kBlock) / kBlock), dim3(kBlock), 0, s, n, h->row_ptr, R,
                        (int64_t)h->nnz + n, h->pan_range);
-    hipLaunchKernelGGL(k_pan_pieces, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, h->row_ptr, pcs);
+    hipLaunchKernelGGL(k_pan_pieces, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, h->row_ptr, h->col,
+                       pcs, h->flags);
     exclusive_scan(n, pcs, sums, h->pan_vstart, s);
     std::vector<int32_t> rr((size_t)R + 1), vs((size_t)n + 1);
     if ((e = hipGetLastError()) != hipSuccess ||
@@ -506,28 +565,30 @@ int build_panels(spcg_csr *h, hipStream_t s) {
             hipSuccess ||
         (e = hipMemcpyAsync(vs.data(), h->pan_vstart, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost,
                             s)) != hipSuccess ||
+        (e = hipMemcpyAsync(hp, h->flags, sizeof(int32_t), hipMemcpyDeviceToHost, s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess)
         return fail(e, "panel ranges");
+    if (hp[0] != 0) return done();  // a row with unsorted columns
     for (int32_t *q : {pcs, sums}) (void)hipFree(q);
     pcs = sums = nullptr;
     for (int r = 0; r < R; ++r)
         if (vs[rr[r + 1]] - vs[rr[r]] > kPanelMaxRows) return done();  // too many for a workgroup
-    const size_t V = (size_t)vs[n];
-    int32_t *hp = (int32_t *)h->h_pinned;
-    // entries per (virtual row, panel) -> padded segment starts and panel starts
-    if ((e = hipMalloc(&cnt, sizeof(uint16_t) * V * P)) != hipSuccess ||
-        (e = hipMalloc(&seg, sizeof(uint16_t) * (size_t)P * (V + R))) != hipSuccess ||
+    const int V = vs[n];
+    // entries per (virtual row, panel), then the segments packed into lanes
+    // (each count replaced by its place) and the blocks' heights, then the
+    // panels' first entries and each range's entry count (into pan_base for now)
+    if ((e = hipMalloc(&cnt, sizeof(uint32_t) * (size_t)V * P)) != hipSuccess ||
+        (e = hipMalloc(&blk, sizeof(int32_t) * (size_t)R * P)) != hipSuccess ||
         (e = hipMalloc(&h->pan_phase, sizeof(int32_t) * (size_t)R * (P + 1))) != hipSuccess ||
-        (e = hipMalloc(&h->pan_base, sizeof(int32_t) * ((size_t)R + 1))) != hipSuccess)
+        (e = hipMalloc(&h->pan_base, sizeof(int32_t) * ((size_t)R + 1))) != hipSuccess ||
+        (e = hipMemsetAsync(cnt, 0, sizeof(uint32_t) * (size_t)V * P, s)) != hipSuccess)
         return fail(e, "hipMalloc(panel layout)");
-    hipLaunchKernelGGL(k_pan_zero, dim3(1), dim3(64), 0, s, h->flags);
-    hipLaunchKernelGGL(k_pan_counts, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, h->row_ptr, h->col,
-                       (const int32_t *)h->pan_vstart, W, P, cnt, h->flags);
-    // each range's entry count (padding included, into pan_base for now) -> the
-    // ranges' first entries
-    hipLaunchKernelGGL(k_pan_layout, dim3(R), dim3(kPanelThreads), 0, s, P, (const int32_t *)h->pan_range,
-                       (const int32_t *)h->pan_vstart, (const uint16_t *)cnt, seg, h->pan_phase,
-                       h->pan_base, h->flags);
+    hipLaunchKernelGGL(k_pan_counts, dim3((V + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, V, h->row_ptr,
+                       h->col, (const int32_t *)h->pan_vstart, W, P, cnt);
+    hipLaunchKernelGGL(k_pan_pack, dim3(R * P), dim3(64), 0, s, P, (const int32_t *)h->pan_range,
+                       (const int32_t *)h->pan_vstart, cnt, blk, h->flags);
+    hipLaunchKernelGGL(k_pan_phase, dim3((R + kBlock - 1) / kBlock), dim3(kBlock), 0, s, R, P,
+                       (const int32_t *)blk, h->pan_phase, h->pan_base, h->flags);
     std::vector<int32_t> tot((size_t)R);
     if ((e = hipGetLastError()) != hipSuccess ||
         (e = hipMemcpyAsync(tot.data(), h->pan_base, sizeof(int32_t) * R, hipMemcpyDeviceToHost, s)) !=
@@ -535,7 +596,7 @@ int build_panels(spcg_csr *h, hipStream_t s) {
         (e = hipMemcpyAsync(hp, h->flags, sizeof(int32_t), hipMemcpyDeviceToHost, s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess)
         return fail(e, "panel layout");
-    if (hp[0] != 0) return done();  // unsorted rows or an oversized (range, panel) block
+    if (hp[0] != 0) return done();  // no packing found, or a range beyond int32 entries
     std::vector<int32_t> rb((size_t)R + 1, 0);
     int64_t total = 0;
     for (int r = 0; r < R; ++r) {
@@ -543,6 +604,8 @@ int build_panels(spcg_csr *h, hipStream_t s) {
         total += tot[r];
         if (total > INT32_MAX) return done();  // too many entries with the padding
     }
+    // blocks so sparse that their lanes are mostly padding: the row blocks do better
+    if (total > 2 * (int64_t)h->nnz + (int64_t(1) << 24)) return done();
     rb[R] = (int32_t)total;
     if ((e = hipMemcpyAsync(h->pan_base, rb.data(), sizeof(int32_t) * ((size_t)R + 1), hipMemcpyHostToDevice,
                             s)) != hipSuccess ||
@@ -551,18 +614,18 @@ int build_panels(spcg_csr *h, hipStream_t s) {
         (e = hipMalloc(&h->pan_part, (size_t)esz * kPanelGroups * n)) != hipSuccess ||
         (!h->pan_done && (e = hipEventCreateWithFlags(&h->pan_done, hipEventDisableTiming)) != hipSuccess) ||
         (e = hipMemsetAsync(h->pan_val, 0, (size_t)esz * total, s)) != hipSuccess ||
-        (e = hipMemsetD32Async((hipDeviceptr_t)h->pan_key, (int)(kPadRow << 16), (size_t)total, s)) != hipSuccess)
+        (e = hipMemsetD32Async((hipDeviceptr_t)h->pan_key, (int)kKeyPad, (size_t)total, s)) != hipSuccess)
         return fail(e, "hipMalloc(panels)");
     if (esz == 8)
-        hipLaunchKernelGGL(k_pan_scatter<double>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n,
+        hipLaunchKernelGGL(k_pan_scatter<double>, dim3((V + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, V,
                            h->row_ptr, h->col, (const double *)h->vals, W, P, R, (const int32_t *)h->pan_range,
-                           (const int32_t *)h->pan_vstart, (const uint16_t *)seg,
+                           (const int32_t *)h->pan_vstart, (const uint32_t *)cnt,
                            (const int32_t *)h->pan_phase, (const int32_t *)h->pan_base, (double *)h->pan_val,
                            h->pan_key);
     else
-        hipLaunchKernelGGL(k_pan_scatter<float>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n,
+        hipLaunchKernelGGL(k_pan_scatter<float>, dim3((V + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, V,
                            h->row_ptr, h->col, (const float *)h->vals, W, P, R, (const int32_t *)h->pan_range,
-                           (const int32_t *)h->pan_vstart, (const uint16_t *)seg,
+                           (const int32_t *)h->pan_vstart, (const uint32_t *)cnt,
                            (const int32_t *)h->pan_phase, (const int32_t *)h->pan_base, (float *)h->pan_val,
                            h->pan_key);
     if ((e = hipGetLastError()) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess)

@@ -1,11 +1,12 @@
 """GPU parity of the column-panel product y = A x (x staged in LDS by
-panels of 48 KB of doubles or 112 KB of floats, rows cut into pieces of at
-most 32 entries, summed by segmented scans, four column groups per row range
-added in order): bit-exact against the oracle on integer data, within the
-dot-product bound on float data, bitwise repeatable, with ragged panels, fewer
-panels than groups, empty rows and panels, and the fallbacks (unsorted
-columns, a misaligned x, ranges with too many pieces) that keep the row-block
-kernel."""
+panels of 64 KB of doubles or 112 KB of floats, rows cut into strided pieces of
+at most 32 entries, each piece's entries in a panel summed serially by one
+lane, four column groups per row range added in order): bit-exact against the
+oracle on integer data, within the dot-product bound on float data, bitwise
+repeatable, with ragged panels, fewer panels than groups, empty rows and
+panels, long segments, large blocks, and the fallbacks (unsorted columns, a
+misaligned x, ranges with too many pieces, blocks that would be mostly
+padding) that keep the row-block kernel."""
 import numpy as np
 import pytest
 import torch
@@ -39,7 +40,7 @@ def product(M, x, dtype=torch.float64, mode="on"):
 
 
 def width(dtype):
-    return 6144 if dtype == torch.float64 else 28672
+    return 8192 if dtype == torch.float64 else 28672
 
 
 @pytest.mark.parametrize("seed", range(3))
@@ -54,8 +55,8 @@ def test_panels_integer_bit_exact(seed, dtype, nc):
     M = with_panels(A, dtype)
     info = M.panel_info()
     assert info is not None and info[1] == -(-nc // width(dtype))
-    # each padding fills less of a 64-entry round than the segment it moves
-    assert A.nnz <= info[2] < 2 * A.nnz
+    # blocks of whole rounds of 1024 lanes, padding within the build limit
+    assert A.nnz <= info[2] <= 2 * A.nnz + (1 << 24) and info[2] % 1024 == 0
     y = product(M, x, dtype)
     assert np.array_equal(y.astype(np.float64), oracle.spmv(A, x))
     # the row-block kernel on the same handle agrees exactly on integer data
@@ -145,9 +146,10 @@ def test_panels_not_built_for_crowded_ranges():
     assert np.array_equal(product(M, x), x[col] * A.vals)
 
 
-def test_panels_padded_segments_banded():
-    # rows of 41 consecutive columns: pieces of 32 and 9 entries, most of them
-    # in one panel, so segments often reach a multiple of 64 and are padded
+def test_panels_long_segments_banded():
+    # rows of 41 consecutive columns: two pieces of 21 and 20 entries, each in
+    # one or two panels, so segments are long and the lanes' height is set by
+    # them (padding)
     A = I.banded_spd(20000, 41)
     x = np.random.default_rng(5).integers(-4, 5, A.n_cols).astype(np.float64)
     M = with_panels(A)
@@ -191,15 +193,31 @@ def test_panels_products_on_two_streams():
     assert np.array_equal(y2.cpu().numpy(), oracle.spmv(A, x2))
 
 
-def test_panels_not_built_for_oversized_blocks():
+def test_panels_large_blocks():
     # 1000 dense rows over 6000 columns (one FP64 panel): each range's block
-    # holds about 94 000 entries, more than the 16-bit layout offsets reach,
-    # so the panels are not built and the row-block kernel runs
+    # holds about 94 000 entries (92 rounds of 1024 lanes, every segment 32
+    # entries long)
     rng = np.random.default_rng(12)
     n, nc = 1000, 6000
     rp = (np.arange(n + 1, dtype=np.int64) * nc).astype(np.int32)
     col = np.tile(np.arange(nc, dtype=np.int32), n)
     A = I.CSR(n, nc, rp, col, rng.integers(-3, 4, n * nc).astype(np.float64))
+    x = rng.integers(-3, 4, nc).astype(np.float64)
+    M = with_panels(A)
+    info = M.panel_info()
+    assert info is not None and info[1] == 1 and info[2] >= A.nnz
+    assert np.array_equal(product(M, x), oracle.spmv(A, x))
+
+
+def test_panels_not_built_for_sparse_blocks():
+    # 100 000 rows of two entries over 8 M columns (977 FP64 panels): a block
+    # holds a few entries but takes a round of 1024 lanes, so the padded copy
+    # would exceed twice the entries plus 2^24 and the panels are not built
+    rng = np.random.default_rng(13)
+    n, nc = 100_000, 8_000_000
+    rp = (np.arange(n + 1, dtype=np.int64) * 2).astype(np.int32)
+    col = np.sort(rng.integers(0, nc // 2, (n, 2)) * 2 + np.array([0, 1]), axis=1).astype(np.int32).ravel()
+    A = I.CSR(n, nc, rp, col, rng.integers(-3, 4, 2 * n).astype(np.float64))
     x = rng.integers(-3, 4, nc).astype(np.float64)
     M = with_panels(A)
     assert M.panel_info() is None
