@@ -44,8 +44,6 @@ int panels_mode() { return g_panels.load(std::memory_order_relaxed); }
 constexpr int kPanelThreads = 1024;  // = the lanes of a (range, panel) block
 constexpr int kPanelMaxRows = 10240;  // virtual rows per range (accumulators in LDS)
 constexpr int kPanelGroups = 4;       // column groups: workgroups per range
-constexpr int kPanelU = 4;            // rounds per chunk (each lane's entries per chunk)
-constexpr int kPanelChunk = kPanelThreads * kPanelU;
 constexpr int kPanelMaxP = 1024;      // panels
 constexpr int kPiece = 32;            // entries per virtual row
 constexpr uint32_t kKeyPad = 1u << 30;   // a padding entry: no product
@@ -60,6 +58,13 @@ constexpr int panel_bytes(int esz) { return esz == 8 ? 64 * 1024 : 112 * 1024; }
 
 template <typename T>
 constexpr int panel_width() { return panel_bytes((int)sizeof(T)) / (int)sizeof(T); }
+
+// Rounds per chunk (each lane's entries per chunk, two chunks in flight): a
+// chunk runs all its rounds, so the short FP64 blocks (lognormal: 4 to 11
+// rounds of 1024 lanes) waste fewer with 2, the FP32 blocks (about 35 rounds)
+// keep more loads in flight with 4.
+template <typename T>
+constexpr int panel_rounds() { return sizeof(T) == 8 ? 2 : 4; }
 
 struct PanelDev {
     const int32_t *__restrict__ base;    // [R + 1] first entry of each range
@@ -352,14 +357,15 @@ struct Slice {
 // block's entry (4 c + u) kPanelThreads + t for chunk c
 template <typename T>
 struct Entries {
-    T v[kPanelU];
-    uint32_t k[kPanelU];
+    T v[panel_rounds<T>()];
+    uint32_t k[panel_rounds<T>()];
 };
 
 template <typename T>
 __global__ void __launch_bounds__(kPanelThreads)
 k_spmv_panels(PanelDev D, const T *__restrict__ x) {
     constexpr int W = panel_width<T>();
+    constexpr int kPanelU = panel_rounds<T>(), kPanelChunk = kPanelThreads * kPanelU;
     __shared__ __align__(16) T xs[W];      // the panel's slice of x
     __shared__ T vacc[kPanelMaxRows];      // every virtual row's running sum
     __shared__ int ph[kPanelMaxP + 1];
@@ -396,8 +402,10 @@ k_spmv_panels(PanelDev D, const T *__restrict__ x) {
         while (p < P && ph[p + 1] == ph[p]) ++p;
         return p;
     };
-    // chunks are walked in order: panel by panel, kPanelChunk entries at a time
+    // chunks are walked in order: panel by panel, kPanelChunk entries at a
+    // time; past the group's last panel the position stays at P
     auto advance = [&](int &p, int &c) {
+        if (p >= P) return;
         c += kPanelChunk;
         if (c >= ph[p + 1] - ph[p]) {
             c = 0;
@@ -438,7 +446,7 @@ k_spmv_panels(PanelDev D, const T *__restrict__ x) {
         int pc = first, cc = 0;  // the chunk being summed
         T acc = T(0);            // the lane's sum of its current segment
         auto step = [&](Entries<T> &E) {
-            if (cc == 0 && pc != first) {
+            if (pc < P && cc == 0 && pc != first) {
                 // a new panel: every wavefront is done with the last slice; the
                 // new one arrived during the last panel
                 __syncthreads();
@@ -447,38 +455,37 @@ k_spmv_panels(PanelDev D, const T *__restrict__ x) {
                 sn.load(x, D.n_cols, pnext < P ? pnext : pc);
                 __syncthreads();
             }
-            // products (a padding entry, or a round past the block: none), then
-            // E refilled with the chunk after the other set's (kept after the
-            // products, so the refill lands in E's own registers instead of
-            // copies that wait for every load in flight)
-            const int rounds = min(kPanelU, (ph[pc + 1] - ph[pc] - cc) / kPanelThreads);
-            T pr[kPanelU];
-            uint32_t kk[kPanelU];
+            // products (a padding entry, or a round past the block: none) and
+            // the lane's segments, entry by entry: at a segment's last entry its
+            // sum goes to its virtual row (a virtual row has one segment per
+            // panel, so no two lanes add to one row within a panel).  E is
+            // consumed whole before it is refilled with the chunk after the
+            // other set's, so the refill lands in E's own registers (values
+            // still live across the refill made the compiler load into other
+            // registers and copy them at the loop's end, waiting for the loads)
+            const int rounds = pc < P ? min(kPanelU, (ph[pc + 1] - ph[pc] - cc) / kPanelThreads) : 0;
 #pragma unroll
             for (int u = 0; u < kPanelU; ++u) {
-                kk[u] = u < rounds ? E.k[u] : kKeyPad;
-                const T t = E.v[u] * xs[kk[u] & 0xffffu];
-                pr[u] = (kk[u] & kKeyPad) ? T(0) : t;
+                const uint32_t k = u < rounds ? E.k[u] : kKeyPad;
+                const T t = E.v[u] * xs[k & 0xffffu];
+                acc += (k & kKeyPad) ? T(0) : t;
+                if (k & kKeyLast) {
+                    vacc[(k >> 16) & kKeyRow] += acc;
+                    acc = T(0);
+                }
             }
             __builtin_amdgcn_sched_barrier(0);
             fetch(E, pf, cf);
             advance(pf, cf);
-            // the lane's segments, entry by entry: at a segment's last entry its
-            // sum goes to its virtual row (a virtual row has one segment per
-            // panel, so no two lanes add to one row within a panel)
-#pragma unroll
-            for (int u = 0; u < kPanelU; ++u) {
-                acc += pr[u];
-                if (kk[u] & kKeyLast) {
-                    vacc[(kk[u] >> 16) & kKeyRow] += acc;
-                    acc = T(0);
-                }
-            }
             advance(pc, cc);
         };
+        // A and B on every trip (B past the last chunk sums nothing): with no
+        // path that loops back after A alone, the compiler sees the other
+        // set's loads as the newer ones at each step and waits only for the
+        // set it sums (an exit between the two made it wait for every load)
         do {
             step(A);
-            if (pc < P) step(B);
+            step(B);
         } while (pc < P);
     }
     // every row of the range: the group's part, its pieces' sums in order
