@@ -175,26 +175,29 @@ int spcg_csr_run_info(spcg_csr_t A, int64_t *n_chunks, int64_t *n_starts);
  * matrices whose columns scatter over an x much larger than a CU's LDS (each
  * gather of such a matrix is otherwise its own vector-L1 miss).  At
  * spcg_csr_create the library cuts every row into pieces of at most 32
- * entries, the rows into one range of balanced work per 4 CUs and the columns
- * into panels of 48 KB of doubles or 112 KB of floats (6144 or 28672
- * elements), and keeps its own copy of the values with one 32-bit word per
- * entry (the column in the panel and the piece's index in its range), ordered
- * by range, panel, piece and column, padded so that no piece's entries in a
- * panel cross a multiple of 64: (value size + 4) bytes per entry plus the
- * padding, and a partial-product buffer of 4 x n_rows values, owned by the
+ * entries taken with a stride (piece j of a row of np pieces holds its entries
+ * j, j + np, ...), the rows into one range of balanced work per 4 CUs and the
+ * columns into panels of 64 KB of doubles or 112 KB of floats (8192 or 28672
+ * elements).  A piece's entries in one panel form a segment; the segments of
+ * each (range, panel) block are packed into 1024 lanes of equal height, and
+ * the library keeps its own copy of the values in that order with one 32-bit
+ * word per entry (the column in the panel, the piece's index in its range, a
+ * padding flag and a segment-end flag): (value size + 4) bytes per entry plus
+ * the padding, and a partial-product buffer of 4 x n_rows values, owned by the
  * handle.  spmv_csr then runs 4 workgroups of 1024 threads per range, one per
- * quarter of the panels; each wavefront sums 64 entries at a time with a
- * segmented scan into LDS accumulators of the pieces, each row adds its
- * pieces into its group's partial vector, and a second kernel adds the four
- * parts in order.  The order of every addition is fixed by the matrix
- * (results repeat bitwise; they differ from the row-block kernel's within
- * rounding).  Products of one handle share its partial buffer, so they are
- * serialized: a product issued on another stream than the handle's last one
- * waits for that one to finish (hipStreamWaitEvent; host calls on one handle
- * take a lock).  Built only for rows with strictly increasing
- * columns, n_cols >= 4, at most 1024 panels, at most 10240 pieces per range
- * and fewer than 65536 entries per (range, panel); otherwise the handle has
- * no panels and the other kernels run.  Used only when x is 16-byte aligned.
+ * group of panels holding a quarter of the range's entries; each thread sums
+ * its lane's segments serially into LDS accumulators of the pieces, each row
+ * adds its pieces into its group's partial vector, and a second kernel adds
+ * the four parts in order.  The order of every addition is fixed by the
+ * matrix (results repeat bitwise; they differ from the row-block kernel's
+ * within rounding).  Products of one handle share its partial buffer, so they
+ * are serialized: a product issued on another stream than the handle's last
+ * one waits for that one to finish (hipStreamWaitEvent; host calls on one
+ * handle take a lock).  Built only for rows with strictly increasing columns,
+ * n_cols >= 4, at most 1024 panels, at most 10240 pieces per range and a
+ * padded copy of at most 2 nnz + 2^24 entries (blocks too sparse to fill their
+ * lanes are not worth it); otherwise the handle has no panels and the other
+ * kernels run.  Used only when x is 16-byte aligned.
  * The copy must be rebuilt (a new handle) if the values change.
  *   SPCG_PANELS_OFF (default): no panels;
  *   SPCG_PANELS_ON: spcg_csr_create builds them and spmv_csr uses them.

@@ -3,29 +3,31 @@
 // row-wise product, regrouped so that each gather reads LDS instead of
 // missing the vector L1).
 //
-// Layout (built once per matrix, on request): every row is cut into pieces of
-// at most kPiece consecutive entries ("virtual rows", one for an empty row), the
+// Layout (built once per matrix, on request): every row is cut into pieces
+// ("virtual rows", one for an empty row) of at most kPiece entries taken with a
+// stride (piece j of a row of np pieces holds its entries j, j + np, ...), the
 // rows into R ranges of balanced work (merge coordinate, one range per
-// kPanelGroups CUs), the columns into panels of W entries of x (48 KB of
-// doubles, 112 KB of floats).  The library keeps its own copy of the values,
-// ordered by range, then panel, then virtual row, then column, and per entry
-// one 32-bit word: the column in the panel (low 16 bits) and the virtual row's
-// index in its range (high 16).  A virtual row's entries in one panel form a
-// segment (rows hold sorted columns); within each (range, panel) block no
-// segment crosses a multiple of 64 entries: where one would, padding entries
-// (value 0, virtual row 0xFFFF) fill the rest of the 64.
+// kPanelGroups CUs), the columns into panels of W entries of x (64 KB of
+// doubles, 112 KB of floats).  A piece's entries in one panel form a segment,
+// short because the stride spreads the piece over the row's columns.  Within
+// each (range, panel) block the segments are packed into kPanelThreads lanes
+// of equal height H (a lane holds whole segments one after another; the block
+// stores round h of lane l at entry h kPanelThreads + l, padding where a lane
+// is shorter).  The library keeps its own copy of the values in that order and
+// per entry one 32-bit word: the column in the panel (bits 0-15), the piece's
+// index in its range (bits 16-29), a padding flag (bit 30) and a flag on each
+// segment's last entry (bit 31).
 //
 // The product: kPanelGroups 1024-thread workgroups per range, one per column
-// group (a contiguous quarter of the panels), so each range reads x once in
-// all.  A workgroup walks its panels in order; each of its wavefronts takes
-// 256 of every 4096 entries of a panel's block, in rounds of 64: products
-// (value x LDS slice of x), a segmented scan across the lanes by DPP moves (a
-// fixed tree in each segment), and each segment's sum added to its virtual
-// row's accumulator in LDS.  A virtual row has one segment per panel, so the additions of one
-// panel never meet, and no barrier is needed between its rounds.  The next
-// panel's slice of x is loaded into registers while the current panel is used
-// and written to LDS at the switch; two chunks of entries are in flight per
-// wavefront.  At the end each row adds its pieces in order into the group's
+// group (the panels holding a quarter of the range's entries), so each range
+// reads x once in all.  A workgroup walks its panels in order; thread t sums
+// lane t of each block serially (value x LDS slice of x) and, at an entry
+// flagged as a segment's last, adds the sum to the piece's accumulator in LDS.
+// A piece has one segment per panel, in one lane, so no two additions of one
+// panel meet and no barrier is needed between its rounds.  The next panel's
+// slice of x is loaded into registers while the current panel is used and
+// written to LDS at the switch; two chunks of entries are in flight per
+// thread.  At the end each row adds its pieces in order into the group's
 // partial vector, and a second kernel adds the groups' parts in group order.
 // The order of every addition depends only on the matrix.
 #include <algorithm>
@@ -353,8 +355,8 @@ struct Slice {
     }
 };
 
-// A thread's entries of a chunk in registers: round u of lane t is the
-// block's entry (4 c + u) kPanelThreads + t for chunk c
+// A thread's entries of a chunk in registers: with U rounds per chunk, round
+// u of lane t in chunk c is the block's entry (U c + u) kPanelThreads + t
 template <typename T>
 struct Entries {
     T v[panel_rounds<T>()];
