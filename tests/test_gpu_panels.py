@@ -193,6 +193,25 @@ def test_panels_products_on_two_streams():
     assert np.array_equal(y2.cpu().numpy(), oracle.spmv(A, x2))
 
 
+def test_panels_packing_retry():
+    # 1536 rows of two entries per range, all in panel 0: each (range, panel)
+    # block holds 3072 entries, so the lanes start at height 3, where a lane
+    # fits one two-entry segment and 512 segments are left over; the packing
+    # retries at height 4 and every block takes 4 rounds of 1024 lanes
+    R = torch.cuda.get_device_properties(0).multi_processor_count // 4
+    rng = np.random.default_rng(14)
+    n, nc = 1536 * R, width(torch.float64)
+    rp = (np.arange(n + 1, dtype=np.int64) * 2).astype(np.int32)
+    col = np.sort(rng.integers(0, nc // 2, (n, 2)) * 2 + np.array([0, 1]), axis=1).astype(np.int32).ravel()
+    A = I.CSR(n, nc, rp, col, rng.integers(-3, 4, 2 * n).astype(np.float64))
+    x = rng.integers(-3, 4, nc).astype(np.float64)
+    M = with_panels(A)
+    info = M.panel_info()
+    assert info is not None and info[0] == R and info[1] == 1
+    assert info[2] == R * 4 * 1024
+    assert np.array_equal(product(M, x), oracle.spmv(A, x))
+
+
 def test_panels_large_blocks():
     # 1000 dense rows over 6000 columns (one FP64 panel): each range's block
     # holds about 94 000 entries (92 rounds of 1024 lanes, every segment 32
