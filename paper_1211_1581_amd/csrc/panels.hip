@@ -47,7 +47,7 @@ constexpr int kPanelThreads = 1024;  // = the lanes of a (range, panel) block
 constexpr int kPanelMaxRows = 10240;  // virtual rows per range (accumulators in LDS)
 constexpr int kPanelGroups = 4;       // column groups: workgroups per range
 constexpr int kPanelMaxP = 1024;      // panels
-constexpr int kPiece = 32;            // entries per virtual row
+constexpr int kPiece = 32;            // entries per virtual row, at most
 constexpr uint32_t kKeyPad = 1u << 30;   // a padding entry: no product
 constexpr uint32_t kKeyLast = 1u << 31;  // the last entry of its segment: flush the lane's sum
 constexpr uint32_t kKeyRow = 0x3fffu;    // the virtual row field, after the shift by 16
