@@ -422,6 +422,58 @@ __device__ __forceinline__ void block_products(const CsrDev &A, const TV *__rest
     }
 }
 
+// Products of NR rounds of kBlock lanes times V consecutive entries (V kBlock
+// entries a round) starting at k0, with cnt >= V: each lane loads its V values
+// as one 16-byte vector and its V columns as one vector, so a round takes two
+// stream instructions per V entries instead of two per entry.  A lane whose
+// group reaches past the block reads the block's last V entries instead and
+// stores only those from its own first entry on (the others into the spare
+// slot).  The loads need not be aligned to their size (the unaligned access
+// mode serves them).
+template <int V, int NR, bool KEEP, bool C16, typename TV, typename TX, typename TA>
+__device__ __forceinline__ void block_products_vec(const CsrDev &A, const TV *__restrict__ vals,
+                                                   const TX *__restrict__ x, int k0, int cnt, int r0,
+                                                   TA *__restrict__ slab, int first = 0) {
+    typedef TV vals_t __attribute__((ext_vector_type(V)));
+    typedef int32_t cols_t __attribute__((ext_vector_type(V)));
+    typedef int16_t offs_t __attribute__((ext_vector_type(V)));
+    const int tid = threadIdx.x + first;
+    const char *colb = (const char *)(A.col + k0);
+    const char *offb = (const char *)(A.off16 + (C16 ? k0 : 0));
+    const char *valb = (const char *)(vals + k0);
+    int c[NR][V];
+    vals_t v[NR];
+    TX xv[NR][V];
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+        const uint32_t t0 = (uint32_t)min(V * (tid + u * kBlock), cnt - V);
+        if constexpr (C16) {
+            const offs_t *p = (const offs_t *)(offb + t0 * 2u);
+            const offs_t o = KEEP ? *p : __builtin_nontemporal_load(p);
+#pragma unroll
+            for (int q = 0; q < V; ++q) c[u][q] = r0 + o[q];
+        } else {
+            const cols_t *p = (const cols_t *)(colb + t0 * 4u);
+            const cols_t o = KEEP ? *p : __builtin_nontemporal_load(p);
+#pragma unroll
+            for (int q = 0; q < V; ++q) c[u][q] = o[q];
+        }
+        const vals_t *q = (const vals_t *)(valb + t0 * (uint32_t)sizeof(TV));
+        v[u] = KEEP ? *q : __builtin_nontemporal_load(q);
+    }
+#pragma unroll
+    for (int u = 0; u < NR; ++u)
+#pragma unroll
+        for (int q = 0; q < V; ++q) xv[u][q] = x[c[u][q]];
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+        const int s0 = V * (tid + u * kBlock), t0 = min(s0, cnt - V);
+#pragma unroll
+        for (int q = 0; q < V; ++q)
+            slab[(t0 + q >= s0 && t0 + q < cnt) ? t0 + q : kSlab] = TA(v[u][q]) * TA(xv[u][q]);
+    }
+}
+
 // Per-row operand of an epilogue that needs none.
 struct NoOperand {};
 
@@ -471,7 +523,28 @@ __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict
     // own column index and all of them are in flight together.
     const int rv = A.row_ptr[r0 + min(tid, nr)];
     const auto pre = epi.load(r0 + min(tid, nr - 1));  // the epilogue's operand of row r0 + tid
-    switch ((cnt + kBlock - 1) / kBlock) {
+    // 16-byte value loads, V = 16 / sizeof(TV) consecutive entries per lane:
+    // FP32 blocks always; FP64 blocks of short rows (blocks of long scattered
+    // rows gathered slower from pairs, so they keep one entry per lane)
+    constexpr int V = 16 / (int)sizeof(TV);
+    bool vec = false;
+    if constexpr (!RUNS && (V == 2 || V == 4)) {
+        vec = cnt >= V && (V == 4 || cnt < 8 * nr);
+        if (vec) {
+            static_assert(kSlab <= 8 * kBlock, "four rounds of pairs or two of quads cover kSlab");
+            switch ((cnt + V * kBlock - 1) / (V * kBlock)) {
+                case 1: block_products_vec<V, 1, KEEP, C16>(A, vals, x, k0, cnt, r0, sm.slab); break;
+                case 2: block_products_vec<V, 2, KEEP, C16>(A, vals, x, k0, cnt, r0, sm.slab); break;
+                case 3: block_products_vec<V, 3, KEEP, C16>(A, vals, x, k0, cnt, r0, sm.slab); break;
+                default:  // four rounds of pairs: two batches, so the registers of two rounds suffice
+                    block_products_vec<V, 2, KEEP, C16>(A, vals, x, k0, cnt, r0, sm.slab);
+                    __builtin_amdgcn_sched_barrier(0);
+                    block_products_vec<V, 2, KEEP, C16>(A, vals, x, k0, cnt, r0, sm.slab, 2 * kBlock);
+                    break;
+            }
+        }
+    }
+    if (!vec) switch ((cnt + kBlock - 1) / kBlock) {
         case 1: block_products<1, KEEP, C16, RUNS>(A, vals, x, k0, cnt, r0, cb, sm.slab); break;
         case 2: block_products<2, KEEP, C16, RUNS>(A, vals, x, k0, cnt, r0, cb, sm.slab); break;
         case 3: block_products<3, KEEP, C16, RUNS>(A, vals, x, k0, cnt, r0, cb, sm.slab); break;
