@@ -10,7 +10,8 @@
 //  * A 256-thread workgroup handles a contiguous range of row blocks (one
 //    block per workgroup up to kMaxGrid blocks; 8 resident per CU).  Phase 1
 //    streams the block's contiguous values and column indices with coalesced
-//    loads (cache-allocating or non-temporal, see keep_bytes), gathers x and
+//    loads (cache-allocating or non-temporal, see keep_bytes; 16-byte value
+//    vectors of consecutive entries per lane where that pays), gathers x and
 //    writes the products into LDS.  Phase 2 reduces each row
 //    from LDS with a group of L lanes (L ~ the block's mean row length) and a
 //    wavefront butterfly.  The summation order depends only on the matrix,
