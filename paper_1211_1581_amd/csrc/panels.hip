@@ -11,9 +11,11 @@
 // doubles, 112 KB of floats).  A piece's entries in one panel form a segment,
 // short because the stride spreads the piece over the row's columns.  Within
 // each (range, panel) block the segments are packed into kPanelThreads lanes
-// of equal height H (a lane holds whole segments one after another; the block
-// stores round h of lane l at entry h kPanelThreads + l, padding where a lane
-// is shorter).  The library keeps its own copy of the values in that order and
+// of equal height H (a lane holds whole segments one after another, padding
+// where a lane is shorter).  The block is stored chunk by chunk, a chunk being
+// U rounds of all lanes (fewer in a block's last chunk), each lane's entries of
+// a chunk side by side, so a lane loads them as one vector.  The library keeps
+// its own copy of the values in that order and
 // per entry one 32-bit word: the column in the panel (bits 0-15), the piece's
 // index in its range (bits 16-29), a padding flag (bit 30) and a flag on each
 // segment's last entry (bit 31).
@@ -67,6 +69,10 @@ constexpr int panel_width() { return panel_bytes((int)sizeof(T)) / (int)sizeof(T
 // keep more loads in flight with 4.
 template <typename T>
 constexpr int panel_rounds() { return sizeof(T) == 8 ? 2 : 4; }
+
+// padding entries after the copy: a lane's vector load in a block's last,
+// shorter chunk reaches up to this many entries past the block
+constexpr int kPanelPad = 4;
 
 struct PanelDev {
     const int32_t *__restrict__ base;    // [R + 1] first entry of each range
@@ -164,8 +170,8 @@ k_pan_counts(int n, int V, const int32_t *__restrict__ rp, const int32_t *__rest
 
 // One wavefront per (range r, panel p) block: the segments (the block's
 // virtual rows' entries in the panel, at most kPiece each) are packed into
-// kPanelThreads lanes of equal height H, lane l's rounds 0..H-1 at entries
-// l, l + kPanelThreads, ...; the block holds kPanelThreads * H entries.  Lane
+// kPanelThreads lanes of equal height H (rounds 0..H-1 of each lane); the
+// block holds kPanelThreads * H entries.  Lane
 // by lane, each lane takes the longest remaining segment that fits its rest
 // (H = max(ceil(entries / lanes), longest segment), raised by one until all
 // fit; the segments of one length are taken in virtual-row order).  Each
@@ -296,19 +302,26 @@ k_pan_scatter(int n, int V, const int32_t *__restrict__ rp, const int32_t *__res
         else hi = mid - 1;
     }
     const int r = lo, vl = v - vstart[range[r]], np = vstart[i + 1] - vstart[i], b = rp[i + 1];
-    int prev = -1, pos = 0;
-    for (int k = rp[i] + (v - vstart[i]); k < b; k += np) {
+    constexpr int U = panel_rounds<T>();
+    int prev = -1, blk = 0, H = 0, lane = 0, h = 0;
+    for (int k = rp[i] + (v - vstart[i]); k < b; k += np, ++h) {
         const int c = col[k], p = c / W;
         if (p != prev) {
             const uint32_t pl = place[(size_t)v * P + p];
-            pos = rbase[r] + phase[(size_t)r * (P + 1) + p] + (int)(pl >> 10) * kPanelThreads +
-                  (int)(pl & (kPanelThreads - 1));
+            const size_t ph = (size_t)r * (P + 1) + p;
+            blk = rbase[r] + phase[ph];
+            H = (phase[ph + 1] - phase[ph]) / kPanelThreads;
+            lane = (int)(pl & (kPanelThreads - 1));
+            h = (int)(pl >> 10);
             prev = p;
         }
+        // round h of the lane: chunk h / U holds rc = min(U, H - its first round)
+        // rounds, each lane's rc entries side by side
+        const int ch = h / U, rc = min(U, H - ch * U);
+        const int pos = blk + ch * U * kPanelThreads + lane * rc + (h - ch * U);
         const bool last = k + np >= b || col[k + np] / W != p;
         pval[pos] = vals[k];
         pkey[pos] = (uint32_t)(c - p * W) | (uint32_t)vl << 16 | (last ? kKeyLast : 0u);
-        pos += kPanelThreads;
     }
 }
 
@@ -355,8 +368,9 @@ struct Slice {
     }
 };
 
-// A thread's entries of a chunk in registers: with U rounds per chunk, round
-// u of lane t in chunk c is the block's entry (U c + u) kPanelThreads + t
+// A thread's entries of a chunk in registers: with U rounds per chunk and rc
+// of them in chunk c (rc = U but in a block's last chunk), round u of lane t
+// is the block's entry c U kPanelThreads + t rc + u
 template <typename T>
 struct Entries {
     T v[panel_rounds<T>()];
@@ -414,15 +428,23 @@ k_spmv_panels(PanelDev D, const T *__restrict__ x) {
             p = next_panel(p);
         }
     };
-    // issued even past the last chunk (then of the range's last entry), so the
-    // number of loads in flight after each set is the same on every path
+    // a lane's kPanelU entries of a chunk lie side by side (rc of them in a
+    // block's last chunk of rc rounds; the load then also takes the next
+    // lane's, which the round mask discards): one vector of values and one of
+    // keys.  Issued even past the last chunk (then of the range's last
+    // entries), so the number of loads in flight after each set is the same
+    // on every path
+    typedef T vals_t __attribute__((ext_vector_type(kPanelU)));
+    typedef uint32_t keys_t __attribute__((ext_vector_type(kPanelU)));
     auto fetch = [&](Entries<T> &E, int p, int c) {
-        const int e0 = p < P ? ph[p] + c : ph[P] - 1, last = ph[min(p + 1, P)] - 1;
+        const int rc = p < P ? min(kPanelU, (ph[p + 1] - ph[p] - c) / kPanelThreads) : 0;
+        const int e = p < P ? ph[p] + c + tid * rc : ph[P] - kPanelU;
+        const vals_t vv = __builtin_nontemporal_load((const vals_t *)(val + e));
+        const keys_t kk = __builtin_nontemporal_load((const keys_t *)(key + e));
 #pragma unroll
         for (int u = 0; u < kPanelU; ++u) {
-            const int e = min(e0 + kPanelThreads * u + tid, last);
-            E.v[u] = __builtin_nontemporal_load(val + e);
-            E.k[u] = __builtin_nontemporal_load(key + e);
+            E.v[u] = vv[u];
+            E.k[u] = kk[u];
         }
     };
 
@@ -618,12 +640,13 @@ int build_panels(spcg_csr *h, hipStream_t s) {
     rb[R] = (int32_t)total;
     if ((e = hipMemcpyAsync(h->pan_base, rb.data(), sizeof(int32_t) * ((size_t)R + 1), hipMemcpyHostToDevice,
                             s)) != hipSuccess ||
-        (e = hipMalloc(&h->pan_val, (size_t)esz * std::max<int64_t>(total, 1))) != hipSuccess ||
-        (e = hipMalloc(&h->pan_key, sizeof(uint32_t) * std::max<int64_t>(total, 1))) != hipSuccess ||
+        (e = hipMalloc(&h->pan_val, (size_t)esz * (total + kPanelPad))) != hipSuccess ||
+        (e = hipMalloc(&h->pan_key, sizeof(uint32_t) * (total + kPanelPad))) != hipSuccess ||
         (e = hipMalloc(&h->pan_part, (size_t)esz * kPanelGroups * n)) != hipSuccess ||
         (!h->pan_done && (e = hipEventCreateWithFlags(&h->pan_done, hipEventDisableTiming)) != hipSuccess) ||
-        (e = hipMemsetAsync(h->pan_val, 0, (size_t)esz * total, s)) != hipSuccess ||
-        (e = hipMemsetD32Async((hipDeviceptr_t)h->pan_key, (int)kKeyPad, (size_t)total, s)) != hipSuccess)
+        (e = hipMemsetAsync(h->pan_val, 0, (size_t)esz * (total + kPanelPad), s)) != hipSuccess ||
+        (e = hipMemsetD32Async((hipDeviceptr_t)h->pan_key, (int)kKeyPad, (size_t)(total + kPanelPad), s)) !=
+            hipSuccess)
         return fail(e, "hipMalloc(panels)");
     if (esz == 8)
         hipLaunchKernelGGL(k_pan_scatter<double>, dim3((V + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, V,
