@@ -80,6 +80,9 @@ const char *spcg_last_error(void);
  *   d_row_ptr int32[n_rows+1], d_col int32[nnz], d_vals (F64: double[nnz],
  *   F32: float[nnz]); all borrowed: they must stay alive and unchanged until
  *   spcg_csr_destroy.  Columns need not be sorted; duplicates are summed.
+ *   The products read d_col and d_vals as vectors of up to 16 bytes starting at
+ *   any element (the unaligned access mode, ROCm's default, serves them), never
+ *   past nnz; the arrays need only their element alignment.
  * The structure is validated on the device (row_ptr[0] = 0, non-decreasing,
  * row_ptr[n] = nnz, 0 <= col < n_cols) -> SPCG_INVALID_CSR.  Then the row
  * analysis runs: a partition of the rows into blocks of bounded work (and the
