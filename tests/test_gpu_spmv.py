@@ -302,6 +302,35 @@ def test_rows_at_the_lds_slab_size(L, dtype):
         assert np.array_equal(y.astype(np.float64), oracle.spmv(A, x))
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_arrays_at_odd_element_offsets(dtype):
+    # the row-block product reads a lane's consecutive entries as one 16-byte
+    # vector of values and one of columns: CSR arrays that start one element
+    # past an aligned address (views into larger buffers) make those loads
+    # misaligned; the products equal the aligned handle's bit for bit
+    S = spcg()
+
+    def shifted(a, dt):
+        t = torch.as_tensor(a).to(dt)
+        buf = torch.zeros(t.numel() + 1, dtype=dt, device="cuda")
+        buf[1:] = t.to("cuda")
+        return buf[1:]
+
+    mats = [I.poisson3d(24), I.random_csr_small(20000, 30000, 5, max_len=40, integer=True)[0]]
+    for A in mats:
+        x = np.random.default_rng(A.nnz).integers(-3, 4, A.n_cols).astype(np.float64)
+        M = S.CsrMatrix(shifted(A.row_ptr, torch.int32), shifted(A.col, torch.int32),
+                        shifted(A.vals, dtype), n_cols=A.n_cols)
+        assert M.col.data_ptr() % 16 != 0 and M.vals.data_ptr() % 16 != 0
+        aligned = S.CsrMatrix.from_host(A, dtype=dtype)
+        xd = to_dev(x, dtype)
+        y1 = S.spmv_csr(M, xd)
+        y0 = S.spmv_csr(aligned, xd)
+        torch.cuda.synchronize()
+        assert np.array_equal(y1.cpu().numpy(), y0.cpu().numpy())
+        assert np.array_equal(y1.cpu().numpy().astype(np.float64), oracle.spmv(A, x))
+
+
 def test_maximum_size():
     # nnz = 2^31 - 2^16 - 8 (the handle's limit is 2^31 - 2^16 - 1): 268M rows
     # of 8 entries and a last row of 6000 (reduced outside the LDS slab, at the
