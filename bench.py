@@ -204,8 +204,9 @@ def main():
                     help="row-length binning policy of the standalone products")
     ap.add_argument("--runs", choices=("on", "off"), default="off",
                     help="run-compressed column policy of the standalone products")
-    ap.add_argument("--panels", choices=("on", "off"), default="off",
-                    help="column-panel policy of the standalone products")
+    ap.add_argument("--panels", choices=("auto", "on", "off"), default="auto",
+                    help="column-panel policy of the standalone products (auto: the "
+                         "library's default, panels for matrices of long rows spread over x)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -472,7 +473,7 @@ def _cold_spmv(A, x, dtype, launches, first):
     us = e0.elapsed_time(e1) * 1e3 / launches
     us_br = float(np.median([f0.elapsed_time(f1) * 1e3 for f0, f1 in evs]))
     yh = y.cpu().numpy().astype(np.float64)
-    pinfo = copies[0].panel_info() if spcg.column_panels() == "on" else None
+    pinfo = copies[0].panel_info() if spcg.column_panels() != "off" else None
     del copies
     if dtype == "f64":
         ref = oracle.spmv(A, x)
@@ -562,8 +563,16 @@ def workloads(A128, x128):
     del M, bt
     out["spmv_cold"] = {"poisson128_f32": cold_spmv(A128, x128, "f32")}
     L, xl = I.lognormal_irregular()
+    # under the library's default panel policy (auto: this matrix gets column
+    # panels, reported in each row's "panels"), then with the row-block kernel
     out["spmv_cold"]["lognormal_f64"] = cold_spmv(L, xl, "f64")
     out["spmv_cold"]["lognormal_f32"] = cold_spmv(L, xl, "f32")
+    old = spcg.column_panels("off")
+    try:
+        out["spmv_cold"]["lognormal_f64_row_blocks"] = cold_spmv(L, xl, "f64")
+        out["spmv_cold"]["lognormal_f32_row_blocks"] = cold_spmv(L, xl, "f32")
+    finally:
+        spcg.column_panels(old)
     # the same products with row-length bins (per-bin lane groups) instead of
     # the row-block kernel
     old = spcg.row_binning("on")

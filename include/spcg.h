@@ -202,15 +202,25 @@ int spcg_csr_run_info(spcg_csr_t A, int64_t *n_chunks, int64_t *n_starts);
  * lanes are not worth it); otherwise the handle has no panels and the other
  * kernels run.  Used only when x is 16-byte aligned.
  * The copy must be rebuilt (a new handle) if the values change.
- *   SPCG_PANELS_OFF (default): no panels;
- *   SPCG_PANELS_ON: spcg_csr_create builds them and spmv_csr uses them.
+ *   SPCG_PANELS_OFF: no panels;
+ *   SPCG_PANELS_ON: spcg_csr_create builds them (within the limits above) and
+ *     spmv_csr uses them;
+ *   SPCG_PANELS_AUTO (default): spcg_csr_create builds them only while the
+ *     row-binning and run policies are off, for matrices whose rows gather
+ *     from across a wide x: at least 65536 rows, at least 16 entries per row
+ *     on average, and a median span (last column - first column) of 4096
+ *     sampled rows above a quarter of n_cols; spmv_csr uses the panels a
+ *     handle has.  Banded, stencil and other local-column matrices keep the
+ *     row-block kernel (their x comes from the caches), so does every matrix
+ *     of short rows.
  * The policy at spcg_csr_create decides whether a handle has panels; the
- * policy at spmv_csr whether they are used.  mode < 0 only returns the current
- * policy.  Panels take precedence over bins and runs; the CG solver's products
- * keep the row-block kernel.
+ * policy at spmv_csr whether they are used (under ON and AUTO).  mode < 0 only
+ * returns the current policy.  Panels take precedence over bins and runs; the
+ * CG solver's products keep the row-block kernel.
  */
 #define SPCG_PANELS_OFF 0
 #define SPCG_PANELS_ON 1
+#define SPCG_PANELS_AUTO 2
 int spcg_column_panels(int mode);
 
 /* Row ranges, column panels and entries of the panel copy (padding included)

@@ -315,7 +315,15 @@ int spcg_csr_create(spcg_csr_t *out, int32_t n_rows, int32_t n_cols, int64_t nnz
             return rc;
         }
     }
-    if (panels_mode() == SPCG_PANELS_ON) {
+    bool panels = panels_mode() == SPCG_PANELS_ON;
+    if (panels_mode() == SPCG_PANELS_AUTO && binning_mode() == SPCG_BINNING_OFF && runs_mode() == SPCG_RUNS_OFF) {
+        const int rc = panels_pay(h, stream, &panels);
+        if (rc != SPCG_OK) {
+            release(h);
+            return rc;
+        }
+    }
+    if (panels) {
         const int rc = build_panels(h, stream);
         if (rc != SPCG_OK) {
             release(h);

@@ -757,6 +757,7 @@ bool use_runs(const spcg_csr *A);
 int panels_mode();
 int build_panels(spcg_csr *h, hipStream_t s);
 bool use_panels(const spcg_csr *A);
+int panels_pay(const spcg_csr *h, hipStream_t s, bool *pay);
 template <typename T>
 int launch_spmv_panels(const spcg_csr *A, const T *x, T *y, hipStream_t s);
 

@@ -41,7 +41,7 @@
 
 namespace spcg {
 
-static std::atomic<int> g_panels{SPCG_PANELS_OFF};
+static std::atomic<int> g_panels{SPCG_PANELS_AUTO};
 
 int panels_mode() { return g_panels.load(std::memory_order_relaxed); }
 
@@ -115,6 +115,18 @@ __device__ __forceinline__ int row_of(int n, const int32_t *__restrict__ vstart,
 }
 
 // ------------------------------------------------------------- analysis --
+
+// Policy SPCG_PANELS_AUTO: the span (last column - first column) of sampled
+// rows i = j * stride, j < m (0 for rows of fewer than two entries)
+__global__ void __launch_bounds__(kBlock)
+k_pan_spans(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t stride, int m,
+            int32_t *__restrict__ span) {
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= m) return;
+    const int i = (int)min((int64_t)j * stride, (int64_t)n - 1);
+    const int a = rp[i], b = rp[i + 1];
+    span[j] = b - a >= 2 ? col[b - 1] - col[a] : 0;
+}
 
 __global__ void k_pan_zero(int32_t *flags) {
     if (threadIdx.x == 0) flags[0] = 0;
@@ -671,7 +683,40 @@ int build_panels(spcg_csr *h, hipStream_t s) {
     return SPCG_OK;
 }
 
-bool use_panels(const spcg_csr *A) { return A->has_panels && panels_mode() == SPCG_PANELS_ON; }
+bool use_panels(const spcg_csr *A) { return A->has_panels && panels_mode() != SPCG_PANELS_OFF; }
+
+// Policy SPCG_PANELS_AUTO: panels pay for matrices whose rows gather from
+// across a wide x: at least kAutoRows rows, kAutoLen entries per row on
+// average, and sampled rows spanning more than a quarter of the columns at
+// the median (the lognormal input: 96 %; a band or a stencil: a few per cent
+// or less, and their rows are short or local, so x comes from the caches)
+constexpr int kAutoRows = 1 << 16;
+constexpr int kAutoLen = 16;
+constexpr int kAutoSamples = 4096;
+
+int panels_pay(const spcg_csr *h, hipStream_t s, bool *pay) {
+    *pay = false;
+    const int n = h->n_rows;
+    if (n < kAutoRows || h->nnz < (int64_t)kAutoLen * n) return SPCG_OK;
+    const int m = std::min(n, kAutoSamples);
+    const int64_t stride = n / m;
+    int32_t *d = nullptr;
+    std::vector<int32_t> span((size_t)m);
+    hipError_t e;
+    if ((e = hipMalloc(&d, sizeof(int32_t) * m)) != hipSuccess) return hip_status(e, "hipMalloc(panel spans)");
+    hipLaunchKernelGGL(k_pan_spans, dim3((m + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, h->row_ptr, h->col,
+                       stride, m, d);
+    if ((e = hipGetLastError()) != hipSuccess ||
+        (e = hipMemcpyAsync(span.data(), d, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess) {
+        (void)hipFree(d);
+        return hip_status(e, "panel spans");
+    }
+    (void)hipFree(d);
+    std::nth_element(span.begin(), span.begin() + m / 2, span.end());
+    *pay = (int64_t)span[m / 2] * 4 > (int64_t)h->n_cols;
+    return SPCG_OK;
+}
 
 template <typename T>
 int launch_spmv_panels(const spcg_csr *A, const T *x, T *y, hipStream_t s) {
@@ -702,7 +747,7 @@ extern "C" {
 
 int spcg_column_panels(int mode) {
     if (mode < 0) return spcg::g_panels.load();
-    if (mode > SPCG_PANELS_ON) return SPCG_INVALID_ARG;
+    if (mode > SPCG_PANELS_AUTO) return SPCG_INVALID_ARG;
     return spcg::g_panels.exchange(mode);
 }
 

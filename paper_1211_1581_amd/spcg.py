@@ -130,13 +130,14 @@ def run_columns(mode=None):
     return RUNS_NAME[st]
 
 
-PANELS = {"off": 0, "on": 1}
+PANELS = {"off": 0, "on": 1, "auto": 2}
 PANELS_NAME = {v: k for k, v in PANELS.items()}
 
 
 def column_panels(mode=None):
     """Column-panel policy of spmv_csr (spcg_column_panels): with mode ("off",
-    "on"), set it and return the previous one; without, return the current one."""
+    "on", "auto"), set it and return the previous one; without, return the
+    current one."""
     st = lib().spcg_column_panels(-1 if mode is None else PANELS[mode])
     if st < 0:
         raise SpcgError(st, "spcg_column_panels")

@@ -241,3 +241,25 @@ def test_panels_not_built_for_sparse_blocks():
     M = with_panels(A)
     assert M.panel_info() is None
     assert np.array_equal(product(M, x), oracle.spmv(A, x))
+
+
+def test_panels_auto_policy():
+    # the default policy builds panels only for long rows spread over a wide
+    # x: the lognormal matrix (100 000 rows, 79 entries per row on average);
+    # not for a stencil (short rows), a band (local columns), a matrix below
+    # 65 536 rows, nor while row binning is on; products stay correct
+    S = spcg()
+    assert S.column_panels() == "auto"
+    A, x = I.lognormal_irregular(n=100_000, seed=15)
+    M = S.CsrMatrix.from_host(A)
+    assert M.panel_info() is not None
+    y = S.spmv_csr(M, to_dev(x))
+    torch.cuda.synchronize()
+    check_f64(y.cpu().numpy(), oracle.spmv(A, x), A, x, "auto panels")
+    for B in (I.poisson3d(48), I.banded_spd(100_000, 41), I.lognormal_irregular(n=50_000, seed=16)[0]):
+        assert S.CsrMatrix.from_host(B).panel_info() is None
+    old = S.row_binning("on")
+    try:
+        assert S.CsrMatrix.from_host(A).panel_info() is None
+    finally:
+        S.row_binning(old)

@@ -14,16 +14,20 @@ pytestmark = pytest.mark.gpu
 
 
 def run(A, x, dtype=torch.float64, binning=None):
-    """y = A x on the device.  binning: the row-binning policy in force while
-    the handle is made and the product runs ("off": row-block kernel, "on":
-    row-length bins), restored afterwards; None keeps the default (off)."""
+    """y = A x on the device with the column panels off (these tests are of
+    the row-block, short-row and binned kernels; test_gpu_panels.py covers the
+    panels).  binning: the row-binning policy in force while the handle is made
+    and the product runs ("off": row-block kernel, "on": row-length bins),
+    restored afterwards; None keeps the default (off)."""
     S = spcg()
     old = S.row_binning(binning) if binning is not None else None
+    old_p = S.column_panels("off")
     try:
         M = S.CsrMatrix.from_host(A, dtype=dtype)
         y = S.spmv_csr(M, to_dev(x, dtype))
         torch.cuda.synchronize()
     finally:
+        S.column_panels(old_p)
         if old is not None:
             S.row_binning(old)
     return y.cpu().numpy(), M
