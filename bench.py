@@ -499,7 +499,7 @@ def _cold_spmv(A, x, dtype, launches, first):
 
 
 SPMV_CASES = ("poisson128_f64", "poisson128_f32", "lognormal_f64", "lognormal_f32",
-              "banded1m_f64")
+              "banded1m_f64", "banded1m_f32")
 
 
 def spmv_case(name):

@@ -81,16 +81,16 @@ k_validate(int n, int ncols, int64_t nnz, const int32_t *__restrict__ rp,
     }
 }
 
-// block_row[b] = first row i with row_ptr[i] + i >= b * kChunk (b < nb),
+// block_row[b] = first row i with row_ptr[i] + i >= b * chunk (b < nb),
 // block_row[nb] = n; block_k[b] = row_ptr[block_row[b]]
 __global__ void __launch_bounds__(kBlock)
-k_partition(int n, const int32_t *__restrict__ rp, int64_t nb, int32_t *block_row,
+k_partition(int n, const int32_t *__restrict__ rp, int64_t nb, int chunk, int32_t *block_row,
             int32_t *block_k) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b > nb) return;
     int lo = n;
     if (b < nb) {
-        const int64_t target = b * kChunk;
+        const int64_t target = b * chunk;
         lo = 0;
         int hi = n;  // answer in [lo, hi]
         while (lo < hi) {
@@ -121,11 +121,12 @@ struct EpiStore {
     __device__ __forceinline__ void row(int i, T s, NoOperand) { y[i] = s; }
 };
 
-// RUNS: columns of the LDS-staged entries from the run-compressed layout
-template <typename T, bool KEEP, bool RUNS = false>
+// RUNS: columns of the LDS-staged entries from the run-compressed layout.
+// CH: span of A's partition (kChunk, or kChunkWide for FP32 handles).
+template <typename T, bool KEEP, bool RUNS = false, int CH = kChunk>
 SPCG_ROWBLOCK_KERNEL
 k_spmv(CsrDev A, const T *__restrict__ vals, const T *__restrict__ x, T *__restrict__ y) {
-    __shared__ SpmvSmem<T> sm;
+    __shared__ SpmvSmem<T, CH> sm;
     int bs, be;
     block_range(A.n_blocks, bs, be);
     EpiStore<T> epi{y};
@@ -157,6 +158,15 @@ int launch_spmv(const spcg_csr *A, const T *x, T *y, hipStream_t s) {
     if (use_bins(A)) return launch_spmv_bins<T>(A, x, y, s);
     const bool keep = matrix_bytes(A->n_rows, A->nnz, sizeof(T)) <= keep_bytes();
     const bool runs = use_runs(A);
+    if constexpr (sizeof(T) == 4) {
+        if (!runs && A->wblock_row) {
+            auto kern = keep ? k_spmv<T, true, false, kChunkWide> : k_spmv<T, false, false, kChunkWide>;
+            hipLaunchKernelGGL(kern, dim3(spmv_grid(A->n_wblocks)), dim3(kBlock), 0, s,
+                               dev_view_wide(A), (const T *)A->vals, x, y);
+            SPCG_LAUNCH_CHECK("k_spmv");
+            return SPCG_OK;
+        }
+    }
     auto kern = runs ? (keep ? k_spmv<T, true, true> : k_spmv<T, false, true>)
                      : (keep ? k_spmv<T, true> : k_spmv<T, false>);
     hipLaunchKernelGGL(kern, dim3(spmv_grid(A->n_blocks)), dim3(kBlock), 0, s, dev_view(A),
@@ -224,6 +234,8 @@ static void release(spcg_csr *h) {
     if (!h) return;
     if (h->block_row) (void)hipFree(h->block_row);
     if (h->block_k) (void)hipFree(h->block_k);
+    if (h->wblock_row) (void)hipFree(h->wblock_row);
+    if (h->wblock_k) (void)hipFree(h->wblock_k);
     if (h->flags) (void)hipFree(h->flags);
     if (h->h_pinned) (void)hipHostFree(h->h_pinned);
     for (int32_t *p : {h->bin_row, h->bin_k, h->bin_len, h->run_base, h->run_col, h->run_chunk,
@@ -289,7 +301,7 @@ int spcg_csr_create(spcg_csr_t *out, int32_t n_rows, int32_t n_cols, int64_t nnz
     {
         const unsigned grid = (unsigned)((h->n_blocks + 1 + kBlock - 1) / kBlock);
         hipLaunchKernelGGL(k_partition, dim3(grid), dim3(kBlock), 0, stream, n_rows, d_row_ptr,
-                           h->n_blocks, h->block_row, h->block_k);
+                           h->n_blocks, kChunk, h->block_row, h->block_k);
         CREATE_TRY(hipGetLastError());
         if (h->n_blocks > 0) {
             const unsigned g2 = (unsigned)((h->n_blocks + kBlock - 1) / kBlock);
@@ -297,6 +309,15 @@ int spcg_csr_create(spcg_csr_t *out, int32_t n_rows, int32_t n_cols, int64_t nnz
                                h->block_row, h->n_blocks, h->flags);
             CREATE_TRY(hipGetLastError());
         }
+    }
+    if (dtype == SPCG_F32 && n_rows > 0) {
+        h->n_wblocks = n_row_blocks(n_rows, nnz, kChunkWide);
+        CREATE_TRY(hipMalloc(&h->wblock_row, sizeof(int32_t) * (h->n_wblocks + 1)));
+        CREATE_TRY(hipMalloc(&h->wblock_k, sizeof(int32_t) * (h->n_wblocks + 1)));
+        const unsigned grid = (unsigned)((h->n_wblocks + 1 + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(k_partition, dim3(grid), dim3(kBlock), 0, stream, n_rows, d_row_ptr,
+                           h->n_wblocks, kChunkWide, h->wblock_row, h->wblock_k);
+        CREATE_TRY(hipGetLastError());
     }
     CREATE_TRY(hipMemcpyAsync(hf, h->flags, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
     CREATE_TRY(hipStreamSynchronize(stream));
@@ -347,6 +368,12 @@ int spcg_csr_info(spcg_csr_t A, int64_t *n_blocks, int64_t *n_long_rows, int64_t
     if (n_blocks) *n_blocks = A->n_blocks;
     if (n_long_rows) *n_long_rows = A->n_long;
     if (max_row_len) *max_row_len = A->max_len;
+    return SPCG_OK;
+}
+
+int spcg_csr_wide_blocks(spcg_csr_t A, int64_t *n_wide_blocks) {
+    if (!A || !n_wide_blocks) return SPCG_INVALID_ARG;
+    *n_wide_blocks = A->wblock_row ? A->n_wblocks : 0;
     return SPCG_OK;
 }
 

@@ -42,6 +42,10 @@ struct spcg_csr {
     int32_t *block_row = nullptr;  // [n_blocks + 1], owned
     int32_t *block_k = nullptr;    // [n_blocks + 1], owned
     int64_t n_blocks = 0;
+    // FP32 values only: the wide partition (span kChunkWide) of the standalone product
+    int32_t *wblock_row = nullptr;  // [n_wblocks + 1], owned
+    int32_t *wblock_k = nullptr;    // [n_wblocks + 1], owned
+    int64_t n_wblocks = 0;
     int64_t n_long = 0;            // blocks whose last row is reduced separately
     int64_t max_len = 0;
     int32_t *flags = nullptr;      // small device scratch for the analysis, owned
@@ -81,7 +85,15 @@ namespace spcg {
 
 constexpr int kBlock = 256;              // threads per workgroup of the streaming kernels
 constexpr int kChunk = 1536;             // merge-coordinate span of one row block
-constexpr int kSlab = 1776;              // LDS products per row block (>= kChunk; longer last rows go strided)
+constexpr int kSlabExtra = 240;          // slab slots beyond the span (a moderately long last row stays in LDS)
+constexpr int kSlab = kChunk + kSlabExtra;  // LDS products per row block (longer last rows go strided)
+// Span of the second ("wide") partition that handles with FP32 values keep
+// for the standalone product: its LDS (slab of floats and row pointers, 17.4 KB)
+// still leaves room for 8 workgroups per CU, and a block carries a third
+// more entries through the same chain of dependent loads (128^3 FP32 product
+// 29.9 -> 28.9 us, a 2^20-row band of width 63 120.5 -> 106 us).  Every other
+// kernel, including those that read FP32 values with FP64 sums, uses kChunk.
+constexpr int kChunkWide = 2048;
 constexpr int kMaxGrid = 32768;          // workgroups of a row-block kernel (each walks a range)
 
 // Load policy of the matrix streams (col, vals).  The MI355X keeps a 256 MB
@@ -120,9 +132,9 @@ int hip_status(hipError_t e, const char *what);
 
 #define SPCG_LAUNCH_CHECK(name) SPCG_TRY(hipGetLastError())
 
-inline int64_t n_row_blocks(int64_t n_rows, int64_t nnz) {
+inline int64_t n_row_blocks(int64_t n_rows, int64_t nnz, int chunk = kChunk) {
     if (n_rows == 0) return 0;
-    return (nnz + n_rows + kChunk - 1) / kChunk;
+    return (nnz + n_rows + chunk - 1) / chunk;
 }
 
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -367,10 +379,12 @@ __device__ __forceinline__ int run_column(const CsrDev &A, int cb, int t) {
     return A.run_col[A.run_base[cb + j] + nh - 1] + (l - hl);
 }
 
-template <typename TA>
+// LDS of a row-block kernel for partitions of span at most CH
+template <typename TA, int CH = kChunk>
 struct SpmvSmem {
-    TA slab[kSlab + 1];  // + a spare slot for the stores of clamped lanes
-    int32_t rp[kChunk + 1];
+    static constexpr int kSl = CH + kSlabExtra;
+    TA slab[kSl + 1];  // + a spare slot for the stores of clamped lanes
+    int32_t rp[CH + 1];
     TA red[kBlock / 64 * 3];  // block sums: up to 3 values per wavefront
     TA last;
 };
@@ -380,7 +394,7 @@ struct SpmvSmem {
 // ordinary loads of col/vals (see keep_bytes), else non-temporal ones.  C16:
 // columns from A.off16 relative to the block's first row r0.  RUNS: columns
 // from the run-compressed layout, the block's chunks starting at cb.
-template <int NU, bool KEEP, bool C16, bool RUNS, typename TV, typename TX, typename TA>
+template <int NU, bool KEEP, bool C16, bool RUNS, int SPARE, typename TV, typename TX, typename TA>
 __device__ __forceinline__ void block_products(const CsrDev &A, const TV *__restrict__ vals,
                                                const TX *__restrict__ x, int k0, int cnt, int r0,
                                                int cb, TA *__restrict__ slab, int first = 0) {
@@ -419,7 +433,7 @@ __device__ __forceinline__ void block_products(const CsrDev &A, const TV *__rest
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
         const int t = tid + u * kBlock;
-        slab[t < cnt ? t : kSlab] = TA(v[u]) * TA(xv[u]);
+        slab[t < cnt ? t : SPARE] = TA(v[u]) * TA(xv[u]);
     }
 }
 
@@ -431,7 +445,7 @@ __device__ __forceinline__ void block_products(const CsrDev &A, const TV *__rest
 // stores only those from its own first entry on (the others into the spare
 // slot).  The loads need not be aligned to their size (the unaligned access
 // mode serves them).
-template <int V, int NR, bool KEEP, bool C16, typename TV, typename TX, typename TA>
+template <int V, int NR, bool KEEP, bool C16, int SPARE, typename TV, typename TX, typename TA>
 __device__ __forceinline__ void block_products_vec(const CsrDev &A, const TV *__restrict__ vals,
                                                    const TX *__restrict__ x, int k0, int cnt, int r0,
                                                    TA *__restrict__ slab, int first = 0) {
@@ -471,7 +485,7 @@ __device__ __forceinline__ void block_products_vec(const CsrDev &A, const TV *__
         const int s0 = V * (tid + u * kBlock), t0 = min(s0, cnt - V);
 #pragma unroll
         for (int q = 0; q < V; ++q)
-            slab[(t0 + q >= s0 && t0 + q < cnt) ? t0 + q : kSlab] = TA(v[u][q]) * TA(xv[u][q]);
+            slab[(t0 + q >= s0 && t0 + q < cnt) ? t0 + q : SPARE] = TA(v[u][q]) * TA(xv[u][q]);
     }
 }
 
@@ -496,12 +510,14 @@ __device__ __forceinline__ int32_t load_uniform(const int32_t *p, int i) {
 // workgroup's last block) leaves out the closing barrier: the caller's
 // store_block_partials, or the end of the kernel, follows.  KEEP selects the
 // load policy of the matrix streams (keep_bytes); C16 reads the compact
-// columns A.off16.
+// columns A.off16.  CH (taken from sm) is the largest partition span the LDS
+// holds: A's blocks must come from a partition of span at most CH.
 template <typename TV, typename TX, typename TA, bool KEEP = false, bool C16 = false,
-          bool RUNS = false, class Epi>
+          bool RUNS = false, int CH = kChunk, class Epi>
 __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict__ vals,
                                            const TX *__restrict__ x, int blk,
-                                           SpmvSmem<TA> &sm, Epi &epi, bool more = true) {
+                                           SpmvSmem<TA, CH> &sm, Epi &epi, bool more = true) {
+    constexpr int kSl = SpmvSmem<TA, CH>::kSl;
     const int tid = threadIdx.x;
     // all four descriptors requested before any is used: one round trip
     const int r0 = load_uniform(A.block_row, blk);
@@ -514,8 +530,8 @@ __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict
     if (r0 >= r1 || kend < k0) return;  // uniform over the workgroup
     // a block whose entries overflow the slab ends in a long row (every other
     // row of a block has fewer than kChunk entries); that row is reduced below
-    const bool long_last = (kend - k0) > kSlab;
-    const int cnt = min(kend - k0, kSlab);
+    const bool long_last = (kend - k0) > kSl;
+    const int cnt = min(kend - k0, kSl);
     const int nr = r1 - r0;
 
     // phase 1: coalesced streams of col/vals, then the gather of x, products
@@ -532,34 +548,47 @@ __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict
     if constexpr (!RUNS && (V == 2 || V == 4)) {
         vec = cnt >= V && (V == 4 || cnt < 8 * nr);
         if (vec) {
-            static_assert(kSlab <= 8 * kBlock, "four rounds of pairs or two of quads cover kSlab");
+            static_assert(kSl <= 4 * V * kBlock, "four rounds of pairs or quads cover the slab");
             switch ((cnt + V * kBlock - 1) / (V * kBlock)) {
-                case 1: block_products_vec<V, 1, KEEP, C16>(A, vals, x, k0, cnt, r0, sm.slab); break;
-                case 2: block_products_vec<V, 2, KEEP, C16>(A, vals, x, k0, cnt, r0, sm.slab); break;
-                case 3: block_products_vec<V, 3, KEEP, C16>(A, vals, x, k0, cnt, r0, sm.slab); break;
-                default:  // four rounds of pairs: two batches, so the registers of two rounds suffice
-                    block_products_vec<V, 2, KEEP, C16>(A, vals, x, k0, cnt, r0, sm.slab);
+                case 1: block_products_vec<V, 1, KEEP, C16, kSl>(A, vals, x, k0, cnt, r0, sm.slab); break;
+                case 2: block_products_vec<V, 2, KEEP, C16, kSl>(A, vals, x, k0, cnt, r0, sm.slab); break;
+                case 3:
+                    if constexpr (V == 2) {
+                        block_products_vec<V, 3, KEEP, C16, kSl>(A, vals, x, k0, cnt, r0, sm.slab);
+                    } else {  // quads (wide partition): 2 + 1, within 64 VGPRs
+                        block_products_vec<V, 2, KEEP, C16, kSl>(A, vals, x, k0, cnt, r0, sm.slab);
+                        __builtin_amdgcn_sched_barrier(0);
+                        block_products_vec<V, 1, KEEP, C16, kSl>(A, vals, x, k0, cnt, r0, sm.slab, 2 * kBlock);
+                    }
+                    break;
+                default:  // four rounds: two batches, so the registers of two rounds suffice
+                    block_products_vec<V, 2, KEEP, C16, kSl>(A, vals, x, k0, cnt, r0, sm.slab);
                     __builtin_amdgcn_sched_barrier(0);
-                    block_products_vec<V, 2, KEEP, C16>(A, vals, x, k0, cnt, r0, sm.slab, 2 * kBlock);
+                    block_products_vec<V, 2, KEEP, C16, kSl>(A, vals, x, k0, cnt, r0, sm.slab, 2 * kBlock);
                     break;
             }
         }
     }
     if (!vec) switch ((cnt + kBlock - 1) / kBlock) {
-        case 1: block_products<1, KEEP, C16, RUNS>(A, vals, x, k0, cnt, r0, cb, sm.slab); break;
-        case 2: block_products<2, KEEP, C16, RUNS>(A, vals, x, k0, cnt, r0, cb, sm.slab); break;
-        case 3: block_products<3, KEEP, C16, RUNS>(A, vals, x, k0, cnt, r0, cb, sm.slab); break;
-        case 4: block_products<4, KEEP, C16, RUNS>(A, vals, x, k0, cnt, r0, cb, sm.slab); break;
-        case 5: block_products<5, KEEP, C16, RUNS>(A, vals, x, k0, cnt, r0, cb, sm.slab); break;
-        case 6: block_products<6, KEEP, C16, RUNS>(A, vals, x, k0, cnt, r0, cb, sm.slab); break;
+        case 1: block_products<1, KEEP, C16, RUNS, kSl>(A, vals, x, k0, cnt, r0, cb, sm.slab); break;
+        case 2: block_products<2, KEEP, C16, RUNS, kSl>(A, vals, x, k0, cnt, r0, cb, sm.slab); break;
+        case 3: block_products<3, KEEP, C16, RUNS, kSl>(A, vals, x, k0, cnt, r0, cb, sm.slab); break;
+        case 4: block_products<4, KEEP, C16, RUNS, kSl>(A, vals, x, k0, cnt, r0, cb, sm.slab); break;
+        case 5: block_products<5, KEEP, C16, RUNS, kSl>(A, vals, x, k0, cnt, r0, cb, sm.slab); break;
+        case 6: block_products<6, KEEP, C16, RUNS, kSl>(A, vals, x, k0, cnt, r0, cb, sm.slab); break;
         case 7:  // a long last row: two batches, so the registers of six rounds suffice
-            block_products<4, KEEP, C16, RUNS>(A, vals, x, k0, cnt, r0, cb, sm.slab);
+            block_products<4, KEEP, C16, RUNS, kSl>(A, vals, x, k0, cnt, r0, cb, sm.slab);
             __builtin_amdgcn_sched_barrier(0);  // keep the batches apart
-            block_products<3, KEEP, C16, RUNS>(A, vals, x, k0, cnt, r0, cb, sm.slab, 4 * kBlock);
+            block_products<3, KEEP, C16, RUNS, kSl>(A, vals, x, k0, cnt, r0, cb, sm.slab, 4 * kBlock);
             break;
-        default: break;  // only empty rows
+        case 0: break;  // only empty rows
+        default:  // wide partition only: batches of four rounds
+            for (int b = 0; b < cnt; b += 4 * kBlock) {
+                block_products<4, KEEP, C16, RUNS, kSl>(A, vals, x, k0, cnt, r0, cb, sm.slab, b);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            break;
     }
-    static_assert(kSlab <= 7 * kBlock, "block_products covers at most 7 rounds");
     if (tid <= nr) sm.rp[tid] = rv - k0;
     for (int t = tid + kBlock; t <= nr; t += kBlock) sm.rp[t] = A.row_ptr[r0 + t] - k0;
     __syncthreads();
@@ -769,6 +798,12 @@ inline bool uses_short_rows(const spcg_csr *A) {
 inline CsrDev dev_view(const spcg_csr *A) {
     return CsrDev{A->row_ptr, A->col, A->block_row, A->block_k, (int)A->n_blocks, nullptr,
                   A->run_mask, A->run_base, A->run_col, A->run_chunk};
+}
+
+// The same matrix over the wide partition (no runs: those follow kChunk's blocks)
+inline CsrDev dev_view_wide(const spcg_csr *A) {
+    return CsrDev{A->row_ptr, A->col, A->wblock_row, A->wblock_k, (int)A->n_wblocks, nullptr,
+                  nullptr, nullptr, nullptr, nullptr};
 }
 
 }  // namespace spcg

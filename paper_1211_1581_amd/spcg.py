@@ -67,6 +67,7 @@ def lib():
         L.spcg_csr_destroy.argtypes = [P]
         L.spcg_csr_info.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                     ctypes.POINTER(i64)]
+        L.spcg_csr_wide_blocks.argtypes = [P, ctypes.POINTER(i64)]
         L.spmv_csr.argtypes = [P, P, P, P]
         L.spcg_row_binning.argtypes = [ctypes.c_int]
         L.spcg_row_binning.restype = ctypes.c_int
@@ -207,7 +208,9 @@ class CsrMatrix:
         a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(lib().spcg_csr_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
                "spcg_csr_info")
-        return dict(n_blocks=a.value, n_long=b.value, max_row_len=c.value)
+        w = ctypes.c_int64()
+        _check(lib().spcg_csr_wide_blocks(self._h, ctypes.byref(w)), "spcg_csr_wide_blocks")
+        return dict(n_blocks=a.value, n_long=b.value, max_row_len=c.value, n_wide_blocks=w.value)
 
     def has_bins(self) -> bool:
         c = (ctypes.c_int64 * 8)()

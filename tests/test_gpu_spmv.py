@@ -286,12 +286,14 @@ def test_dot_deterministic_and_bounded():
         assert abs(d1 - ref) <= bound + 1e-300
 
 
-@pytest.mark.parametrize("L", [1535, 1536, 1537, 1775, 1776, 1777, 1792, 1793])
+@pytest.mark.parametrize("L", [1535, 1536, 1537, 1775, 1776, 1777, 1792, 1793,
+                               2047, 2048, 2049, 2287, 2288, 2289])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_rows_at_the_lds_slab_size(L, dtype):
     # each row of L entries opens its own row block: lengths around the
-    # merge-coordinate span (1536) and the LDS slab (1776), below and above,
-    # then short rows after them
+    # merge-coordinate span (1536) and the LDS slab (1776), and around the
+    # wide partition's span (2048) and slab (2288) that the FP32 product
+    # uses, below and above, then short rows after them
     lens = np.array([L, L, 3, L - 1, 0, 5] * 3, np.int64)
     rp = np.zeros(len(lens) + 1, np.int64)
     np.cumsum(lens, out=rp[1:])
@@ -304,6 +306,34 @@ def test_rows_at_the_lds_slab_size(L, dtype):
     for binning in ("off", "on"):
         y, M = run(A, x, dtype, binning)
         assert np.array_equal(y.astype(np.float64), oracle.spmv(A, x))
+
+
+def test_wide_partition_f32():
+    # an FP32 handle's own product runs over blocks of 2048 merge items (FP64
+    # handles and every solver kernel keep 1536).  For rows of fewer than 8
+    # entries each row's sum is taken in entry order whatever the partition,
+    # so the product equals the one over the 1536-item blocks bit for bit
+    # (taken here with run-compressed columns, which follow that partition);
+    # both lie within the FP32 bound of the oracle's sum of the same inputs
+    S = spcg()
+    A = I.poisson3d(64)
+    x = I.uniform_vector(A.n_rows, 4)
+    y, M = run(A, x, torch.float32)
+    info = M.info()
+    assert info["n_blocks"] == (A.nnz + A.n_rows + 1535) // 1536
+    assert info["n_wide_blocks"] == (A.nnz + A.n_rows + 2047) // 2048
+    _, M64 = run(A, x)
+    assert M64.info()["n_wide_blocks"] == 0
+    old = S.run_columns("on")
+    try:
+        Mr = S.CsrMatrix.from_host(A, dtype=torch.float32)
+        yr = S.spmv_csr(Mr, to_dev(x, torch.float32))
+        torch.cuda.synchronize()
+    finally:
+        S.run_columns(old)
+    assert Mr.run_info() is not None
+    assert np.array_equal(y, yr.cpu().numpy())
+    f32_check(A, x, y)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
