@@ -86,8 +86,8 @@ const char *spcg_last_error(void);
  * The structure is validated on the device (row_ptr[0] = 0, non-decreasing,
  * row_ptr[n] = nnz, 0 <= col < n_cols) -> SPCG_INVALID_CSR.  Then the row
  * analysis runs: a partition of the rows into blocks of bounded work (and the
- * value offset of each block); an F32 handle keeps a second partition into
- * blocks of a larger bound for spmv_csr (spcg_csr_wide_blocks).  Synchronous: returns after `stream` has
+ * value offset of each block), and a second one into blocks of a larger bound
+ * for the products in FP32 (spcg_csr_wide_blocks).  Synchronous: returns after `stream` has
  * finished the analysis.  The handle owns its analysis arrays (device memory).
  */
 int spcg_csr_create(spcg_csr_t *out, int32_t n_rows, int32_t n_cols, int64_t nnz,
@@ -115,13 +115,13 @@ int64_t spcg_keep_bytes(int64_t bytes);
 int spcg_csr_info(spcg_csr_t A, int64_t *n_blocks, int64_t *n_long_rows, int64_t *max_row_len);
 
 /*
- * Row blocks of the second partition that an F32 handle keeps for its own
- * product (Sec. 3.2's per-row sums over blocks of at most 2048 merge items,
- * rows plus entries, instead of 1536: each block carries more entries through
+ * Row blocks of the second partition that a handle keeps for its products in
+ * FP32 (Sec. 3.2's per-row sums over blocks of at most 2048 merge items, rows
+ * plus entries, instead of 1536: an FP32 block carries more entries through
  * the same chain of dependent loads, and its LDS still leaves room for 8
- * workgroups per CU).  spmv_csr on an F32 handle uses it unless runs are on;
- * every other kernel uses the partition of spcg_csr_info.  *n_wide_blocks = 0
- * for F64 handles and empty matrices.
+ * workgroups per CU).  spmv_csr on an F32 handle (unless runs are on) and the
+ * inner product of a mixed-precision cg_solve use it; every other kernel uses
+ * the partition of spcg_csr_info.  *n_wide_blocks = 0 for empty matrices.
  */
 int spcg_csr_wide_blocks(spcg_csr_t A, int64_t *n_wide_blocks);
 

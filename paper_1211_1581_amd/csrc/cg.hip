@@ -261,12 +261,13 @@ struct EpiPQ {
 };
 
 // K1: q = A p; partial p.q.  KEEP: load policy of A's streams (keep_bytes);
-// C16: compact columns (A.off16).
-template <typename TV, typename T, bool KEEP, bool C16 = false>
+// C16: compact columns (A.off16); CH: span of A's partition (kChunk, or
+// kChunkWide for the mixed form's FP32 inner product).
+template <typename TV, typename T, bool KEEP, bool C16 = false, int CH = kChunk>
 SPCG_ROWBLOCK_KERNEL
 k_cg_q(CsrDev A, const TV *__restrict__ vals, const T *__restrict__ p, T *__restrict__ q,
        const CgState *st, T *part, int expect) {
-    __shared__ SpmvSmem<T> sm;
+    __shared__ SpmvSmem<T, CH> sm;
     if (st->halt != RUN || st->k != expect) return;
     int bs, be;
     const int slot = block_range(A.n_blocks, bs, be);
@@ -1644,6 +1645,7 @@ struct Solver {
     unsigned gv() const { return grid_of(A->n_rows, kVecBlock); }
     unsigned gxr() const { return std::min<unsigned>(gv(), kXrGrid); }
     unsigned gA() const { return spmv_grid(A->n_blocks); }
+    unsigned gA32() const { return spmv_grid(A->n_wblocks); }  // wide partition (mixed inner product)
     // the G^T apply's workgroups (and r.z partials, which every workgroup of K3L sums)
     unsigned gG() const {
         return w.w_g ? ell_grid() : std::min<unsigned>(factor_grid(o->GT), kApplyGrid);
@@ -1861,23 +1863,25 @@ struct Solver {
         const int n = A->n_rows;
         const float *pf = w.partf;
         {
-            auto kern = keep ? (c16 ? k_cg_q<float, float, true, true> : k_cg_q<float, float, true, false>)
-                             : (c16 ? k_cg_q<float, float, false, true> : k_cg_q<float, float, false, false>);
-            CsrDev d = dev_view(A);
+            // over the wide partition (the compact columns are relative to its blocks)
+            constexpr int W = kChunkWide;
+            auto kern = keep ? (c16 ? k_cg_q<float, float, true, true, W> : k_cg_q<float, float, true, false, W>)
+                             : (c16 ? k_cg_q<float, float, false, true, W> : k_cg_q<float, float, false, false, W>);
+            CsrDev d = dev_view_wide(A);
             if (c16) d.off16 = w.off16;
             if (timed(e)) {
-                hipExtLaunchKernelGGL(kern, dim3(gA()), dim3(kBlock), 0, s, A->events[2 * n_timed],
+                hipExtLaunchKernelGGL(kern, dim3(gA32()), dim3(kBlock), 0, s, A->events[2 * n_timed],
                                       A->events[2 * n_timed + 1], 0, d, (const float *)w.vals32,
                                       (const float *)w.p32, w.q32, w.st, w.partf, e);
                 timed_k[n_timed++] = e;
             } else {
-                hipLaunchKernelGGL(kern, dim3(gA()), dim3(kBlock), 0, s, d, (const float *)w.vals32,
+                hipLaunchKernelGGL(kern, dim3(gA32()), dim3(kBlock), 0, s, d, (const float *)w.vals32,
                                    (const float *)w.p32, w.q32, w.st, w.partf, e);
             }
         }
         const unsigned gx = gxr();
         hipLaunchKernelGGL((k_fin_q<float, true>), dim3(1), dim3(kFinThreads), 0, s, w.st, pf,
-                           (int)gA(), e);
+                           (int)gA32(), e);
         hipLaunchKernelGGL((k_cg_xr<float, SPCG_PRECOND_JACOBI>), dim3(gx), dim3(kBlock), 0, s,
                            n, e, w.r32, (const float *)w.q32, (const float *)w.dinv32, w.st, w.partf);
         hipLaunchKernelGGL((k_cg_pf<float, SPCG_PRECOND_JACOBI, true>), dim3(gx), dim3(kBlock), 0,
@@ -2100,9 +2104,9 @@ int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o
                            A->nnz, (const double *)A->vals, w.vals32);
         hipLaunchKernelGGL(k_fill<float>, dim3(grid_of(n, kBlock * 8)), dim3(kBlock), 0, s,
                            (int64_t)n, w.x32, 0.0f);
-        if (A->n_blocks > 0)
-            hipLaunchKernelGGL(k_make_off16, dim3((unsigned)std::min<int64_t>(A->n_blocks, 4096)),
-                               dim3(kBlock), 0, s, dev_view(A), w.off16, w.st);
+        if (A->n_wblocks > 0)
+            hipLaunchKernelGGL(k_make_off16, dim3((unsigned)std::min<int64_t>(A->n_wblocks, 4096)),
+                               dim3(kBlock), 0, s, dev_view_wide(A), w.off16, w.st);
         SPCG_LAUNCH_CHECK("mixed set-up");
     }
     if (learned) {
@@ -2122,7 +2126,7 @@ int cg_solve(spcg_csr_t A, const double *d_b, double *d_x, const spcg_cg_opts *o
     if ((rc = S.resid(R_INIT, mixed ? w.r32 : nullptr))) return rc;
     if ((rc = S.read_state())) return rc;
     CgState *h = S.h;
-    if (mixed && A->n_blocks > 0 && !h->c16_bad) {
+    if (mixed && A->n_wblocks > 0 && !h->c16_bad) {
         S.c16 = true;
         S.set_keep();
     }

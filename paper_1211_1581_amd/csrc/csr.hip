@@ -310,7 +310,7 @@ int spcg_csr_create(spcg_csr_t *out, int32_t n_rows, int32_t n_cols, int64_t nnz
             CREATE_TRY(hipGetLastError());
         }
     }
-    if (dtype == SPCG_F32 && n_rows > 0) {
+    if (n_rows > 0) {
         h->n_wblocks = n_row_blocks(n_rows, nnz, kChunkWide);
         CREATE_TRY(hipMalloc(&h->wblock_row, sizeof(int32_t) * (h->n_wblocks + 1)));
         CREATE_TRY(hipMalloc(&h->wblock_k, sizeof(int32_t) * (h->n_wblocks + 1)));

@@ -42,7 +42,7 @@ struct spcg_csr {
     int32_t *block_row = nullptr;  // [n_blocks + 1], owned
     int32_t *block_k = nullptr;    // [n_blocks + 1], owned
     int64_t n_blocks = 0;
-    // FP32 values only: the wide partition (span kChunkWide) of the standalone product
+    // the wide partition (span kChunkWide) of the FP32 products; n_rows > 0 only
     int32_t *wblock_row = nullptr;  // [n_wblocks + 1], owned
     int32_t *wblock_k = nullptr;    // [n_wblocks + 1], owned
     int64_t n_wblocks = 0;
@@ -87,12 +87,14 @@ constexpr int kBlock = 256;              // threads per workgroup of the streami
 constexpr int kChunk = 1536;             // merge-coordinate span of one row block
 constexpr int kSlabExtra = 240;          // slab slots beyond the span (a moderately long last row stays in LDS)
 constexpr int kSlab = kChunk + kSlabExtra;  // LDS products per row block (longer last rows go strided)
-// Span of the second ("wide") partition that handles with FP32 values keep
-// for the standalone product: its LDS (slab of floats and row pointers, 17.4 KB)
-// still leaves room for 8 workgroups per CU, and a block carries a third
-// more entries through the same chain of dependent loads (128^3 FP32 product
-// 29.9 -> 28.9 us, a 2^20-row band of width 63 120.5 -> 106 us).  Every other
-// kernel, including those that read FP32 values with FP64 sums, uses kChunk.
+// Span of the second ("wide") partition that every handle keeps for the
+// products with FP32 values and sums (the standalone product of an FP32
+// handle, the mixed-precision solve's inner product): their LDS (slab of
+// floats and row pointers, 17.4 KB) still leaves room for 8 workgroups per
+// CU, and a block carries a third more entries through the same chain of
+// dependent loads (128^3 FP32 product 29.9 -> 28.9 us, a 2^20-row band of
+// width 63 120.5 -> 106 us).  Every other kernel, including those that read
+// FP32 values with FP64 sums, uses kChunk.
 constexpr int kChunkWide = 2048;
 constexpr int kMaxGrid = 32768;          // workgroups of a row-block kernel (each walks a range)
 
@@ -800,7 +802,8 @@ inline CsrDev dev_view(const spcg_csr *A) {
                   A->run_mask, A->run_base, A->run_col, A->run_chunk};
 }
 
-// The same matrix over the wide partition (no runs: those follow kChunk's blocks)
+// The same matrix over the wide partition (no runs: those follow kChunk's
+// blocks); only kernels instantiated with SpmvSmem<float, kChunkWide> may read it
 inline CsrDev dev_view_wide(const spcg_csr *A) {
     return CsrDev{A->row_ptr, A->col, A->wblock_row, A->wblock_k, (int)A->n_wblocks, nullptr,
                   nullptr, nullptr, nullptr, nullptr};

@@ -309,8 +309,10 @@ def test_rows_at_the_lds_slab_size(L, dtype):
 
 
 def test_wide_partition_f32():
-    # an FP32 handle's own product runs over blocks of 2048 merge items (FP64
-    # handles and every solver kernel keep 1536).  For rows of fewer than 8
+    # an FP32 handle's own product runs over the handle's wide partition,
+    # blocks of 2048 merge items (the FP64 products and the kernels with FP64
+    # sums keep 1536; the mixed form's FP32 inner product uses the wide one
+    # too, tested with the solver).  For rows of fewer than 8
     # entries each row's sum is taken in entry order whatever the partition,
     # so the product equals the one over the 1536-item blocks bit for bit
     # (taken here with run-compressed columns, which follow that partition);
@@ -323,7 +325,7 @@ def test_wide_partition_f32():
     assert info["n_blocks"] == (A.nnz + A.n_rows + 1535) // 1536
     assert info["n_wide_blocks"] == (A.nnz + A.n_rows + 2047) // 2048
     _, M64 = run(A, x)
-    assert M64.info()["n_wide_blocks"] == 0
+    assert M64.info()["n_wide_blocks"] == info["n_wide_blocks"]
     old = S.run_columns("on")
     try:
         Mr = S.CsrMatrix.from_host(A, dtype=torch.float32)
