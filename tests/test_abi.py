@@ -62,6 +62,8 @@ def test_invalid_args_rejected_on_host():
     assert L.spcg_csr_create(ctypes.byref(h), big, 3, 0, fake, fake, fake, 0, None) == spcg.INVALID_ARG
     assert L.spcg_csr_create(ctypes.byref(h), 3, big, 0, fake, fake, fake, 0, None) == spcg.INVALID_ARG
     assert L.spmv_csr(None, None, None, None) == spcg.INVALID_ARG
+    nb = ctypes.c_int64(-1)
+    assert L.spcg_csr_wide_blocks(None, ctypes.byref(nb)) == spcg.INVALID_ARG and nb.value == -1
     res = spcg.CgResult()
     assert L.cg_solve(None, None, None, None, None, 0, ctypes.byref(res), None, None) == spcg.INVALID_ARG
 
