@@ -423,3 +423,20 @@ def test_mixed_precision_column_layouts(case):
     assert abs(g["n_updates"] - ref["n_updates"]) <= 2
     assert g["iters"] <= 1.15 * j64["iters"] + 5
     assert np.allclose(g["hist"][:5], ref["hist"][:5], rtol=1e-4)
+
+
+@pytest.mark.parametrize("n,bw", [(30000, 31), (20000, 63)])
+def test_mixed_precision_banded(n, bw):
+    # rows of 63 and 127 entries: the FP32 inner product's wide row blocks
+    # reduce them with lane groups per row (not the per-row epilogue of
+    # short rows); passes, replacements and the first history entries
+    # against the oracle's mixed solve
+    A = I.banded_spd(n, bw)
+    b = I.rhs_from_solution(A, I.uniform_vector(n, 6))
+    ref = oracle.cg_mixed(A, b, tol=1e-10, maxit=5000, delta=0.1)
+    g = solve(A, b, tol=1e-10, maxit=5000, precond="jacobi", precision="mixed")
+    assert g["status"] == 0 and ref["status"] == 0
+    assert oracle.true_relres(A, b, g["x"]) <= 1e-10
+    assert within(g["iters"], ref["iters"], 0.05, 3), (g["iters"], ref["iters"])
+    assert abs(g["n_updates"] - ref["n_updates"]) <= 2
+    assert np.allclose(g["hist"][:5], ref["hist"][:5], rtol=1e-4)
