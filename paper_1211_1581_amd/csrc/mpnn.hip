@@ -531,7 +531,7 @@ struct EpiResidLoss {
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
 k_sp32(CsrDev A, const float *__restrict__ vals, const float *__restrict__ x, float *__restrict__ y) {
-    __shared__ SpmvSmem<float> sm;
+    __shared__ SpmvSmem<float, kChunkWide> sm;  // A over its handle's wide partition
     int bs, be;
     block_range(A.n_blocks, bs, be);
     EpiStore32 epi{y};
@@ -541,7 +541,7 @@ k_sp32(CsrDev A, const float *__restrict__ vals, const float *__restrict__ x, fl
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
 k_sp32_resid(CsrDev A, const float *__restrict__ vals, const float *__restrict__ x,
              const float *__restrict__ v, float *__restrict__ s, float scale, float *part) {
-    __shared__ SpmvSmem<float> sm;
+    __shared__ SpmvSmem<float, kChunkWide> sm;  // A over its handle's wide partition
     int bs, be;
     const int slot = block_range(A.n_blocks, bs, be);
     EpiResidLoss epi{v, s, scale, 0.0f};
@@ -1215,9 +1215,10 @@ int spcg_mpnn_loss_grad(spcg_mpnn_t g, const float *d_w, const float *d_probes, 
     rc = forward(g, ws, d_w, s);
     if (rc) return rc;
     const int n = g->n, E = g->E;
-    const CsrDev Gd = dev_view(g->G), GTd = dev_view(g->GT), Ad = dev_view(g->A32);
-    const unsigned gG = spmv_grid(g->G->n_blocks), gGT = spmv_grid(g->GT->n_blocks),
-                   gA = spmv_grid(g->A32->n_blocks);
+    // the FP32 products over the handles' wide row-block partitions
+    const CsrDev Gd = dev_view_wide(g->G), GTd = dev_view_wide(g->GT), Ad = dev_view_wide(g->A32);
+    const unsigned gG = spmv_grid(g->G->n_wblocks), gGT = spmv_grid(g->GT->n_wblocks),
+                   gA = spmv_grid(g->A32->n_wblocks);
     const float scale = 2.0f / ((float)n * (float)m);
     for (int k = 0; k < m; ++k) {
         const float *v = d_probes + (size_t)k * n;
