@@ -119,9 +119,10 @@ int spcg_csr_info(spcg_csr_t A, int64_t *n_blocks, int64_t *n_long_rows, int64_t
  * FP32 (Sec. 3.2's per-row sums over blocks of at most 2048 merge items, rows
  * plus entries, instead of 1536: an FP32 block carries more entries through
  * the same chain of dependent loads, and its LDS still leaves room for 8
- * workgroups per CU).  spmv_csr on an F32 handle (unless runs are on) and the
- * inner product of a mixed-precision cg_solve use it; every other kernel uses
- * the partition of spcg_csr_info.  *n_wide_blocks = 0 for empty matrices.
+ * workgroups per CU).  spmv_csr on an F32 handle (unless runs are on), the
+ * inner product of a mixed-precision cg_solve and the FP32 products of
+ * spcg_mpnn_loss_grad use it; every other kernel uses the partition of
+ * spcg_csr_info.  *n_wide_blocks = 0 for empty matrices.
  */
 int spcg_csr_wide_blocks(spcg_csr_t A, int64_t *n_wide_blocks);
 

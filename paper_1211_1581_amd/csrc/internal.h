@@ -89,7 +89,8 @@ constexpr int kSlabExtra = 240;          // slab slots beyond the span (a modera
 constexpr int kSlab = kChunk + kSlabExtra;  // LDS products per row block (longer last rows go strided)
 // Span of the second ("wide") partition that every handle keeps for the
 // products with FP32 values and sums (the standalone product of an FP32
-// handle, the mixed-precision solve's inner product): their LDS (slab of
+// handle, the mixed-precision solve's inner product, the network's loss
+// products): their LDS (slab of
 // floats and row pointers, 17.4 KB) still leaves room for 8 workgroups per
 // CU, and a block carries a third more entries through the same chain of
 // dependent loads (128^3 FP32 product 29.9 -> 28.9 us, a 2^20-row band of
