@@ -103,7 +103,11 @@ int spcg_csr_destroy(spcg_csr_t A);
  * matrices stream at most `bytes` per product or pass (col + vals + row_ptr;
  * in the learned form A, G and G^T together, else G and G^T alone) reads them
  * with cache-allocating loads, so repeated products find them in that cache;
- * larger ones are read with non-temporal loads, which leave it to the rest.
+ * larger ones are read with non-temporal loads, which leave it to the rest,
+ * except that the product of a plain, Jacobi or mixed-precision cg_solve
+ * still reads a share of such a matrix's row blocks with cache-allocating
+ * loads: (bytes - the bytes of p, r and D^-1) / matrix bytes, in sixteenths,
+ * spread over the whole matrix (at 160^3, 5/16 of the 358 MB FP64 matrix).
  * bytes >= 0 sets the limit (0: always non-temporal) and returns the previous
  * one; bytes < 0 only returns the current one.  Default 192 MiB.  The policy
  * changes speed only: results are bitwise identical either way.  Takes effect

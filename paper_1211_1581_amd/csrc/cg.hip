@@ -261,18 +261,26 @@ struct EpiPQ {
 };
 
 // K1: q = A p; partial p.q.  KEEP: load policy of A's streams (keep_bytes);
-// C16: compact columns (A.off16); CH: span of A's partition (kChunk, or
-// kChunkWide for the mixed form's FP32 inner product).
+// without it, the blocks k with (k & 15) < kq16 still use cache-allocating
+// loads (a matrix above the limit keeps that share of its blocks in the
+// memory-side cache, spread over every XCD's range of blocks).  C16: compact
+// columns (A.off16); CH: span of A's partition (kChunk, or kChunkWide for the
+// mixed form's FP32 inner product).
 template <typename TV, typename T, bool KEEP, bool C16 = false, int CH = kChunk>
 SPCG_ROWBLOCK_KERNEL
 k_cg_q(CsrDev A, const TV *__restrict__ vals, const T *__restrict__ p, T *__restrict__ q,
-       const CgState *st, T *part, int expect) {
+       const CgState *st, T *part, int expect, int kq16) {
     __shared__ SpmvSmem<T, CH> sm;
     if (st->halt != RUN || st->k != expect) return;
     int bs, be;
     const int slot = block_range(A.n_blocks, bs, be);
     EpiPQ<T> epi{q, p, T(0)};
-    for (int k = bs; k < be; ++k) spmv_block<TV, T, T, KEEP, C16>(A, vals, p, k, sm, epi, k + 1 < be);
+    for (int k = bs; k < be; ++k) {
+        if (KEEP || (k & 15) < kq16)
+            spmv_block<TV, T, T, true, C16>(A, vals, p, k, sm, epi, k + 1 < be);
+        else
+            spmv_block<TV, T, T, false, C16>(A, vals, p, k, sm, epi, k + 1 < be);
+    }
     const T v[1] = {epi.acc};
     store_block_partials(part, slot, v, sm.red);
 }
@@ -1560,6 +1568,9 @@ struct Solver {
     // together, else the two factors alone (measured at 128^3: keeping the
     // factors, 150 MB, beats keeping A).
     bool keep = false, keep_g = false, c16 = false;
+    // a matrix above the limit: sixteenths of its row blocks read with
+    // cache-allocating loads all the same (k_cg_q)
+    int kq16 = 0;
     // learned form: factors as DIA planes (dia) with their offsets and widths
     bool dia = false;
     DiaOff dia_g{}, dia_gt{};
@@ -1585,6 +1596,17 @@ struct Solver {
             // DIA applies stream their planes well: keep A instead of them
             keep = true;
             keep_g = false;
+        }
+        // Above the limit, the product of the standard and mixed loops keeps
+        // the share of A that fits beside the vectors the pass reads with
+        // cache-allocating loads (p, r and D^-1: 24 bytes per row in FP64,
+        // 12 in FP32): at 160^3 (358 MB of FP64 A) 5/16 of the blocks,
+        // Jacobi-PCG 107.5 -> 100.2 ms, where keeping all of A thrashes the
+        // cache (114.4 -> 118.8 ms when that was measured)
+        kq16 = 0;
+        if (!keep && o->precond != SPCG_PRECOND_LEARNED && !single_reduction() && a > 0) {
+            const int64_t vec = (int64_t)A->n_rows * (mixed ? 12 : 24);
+            if (lim > vec) kq16 = (int)std::min<int64_t>(15, 16 * (lim - vec) / a);
         }
     }
     int n_timed = 0;
@@ -1818,12 +1840,12 @@ struct Solver {
                 hipExtLaunchKernelGGL(kern, dim3(gA()), dim3(kBlock), 0, s, A->events[2 * n_timed],
                                       A->events[2 * n_timed + 1], 0, dev_view(A),
                                   (const double *)A->vals, (const double *)w.p, w.q, w.st,
-                                  w.partd, e);
+                                  w.partd, e, kq16);
                 timed_k[n_timed++] = e;
             } else {
                 hipLaunchKernelGGL(kern, dim3(gA()), dim3(kBlock), 0, s, dev_view(A),
                                   (const double *)A->vals, (const double *)w.p, w.q, w.st,
-                                  w.partd, e);
+                                  w.partd, e, kq16);
             }
         }
         if (pre != SPCG_PRECOND_LEARNED) {
@@ -1872,11 +1894,11 @@ struct Solver {
             if (timed(e)) {
                 hipExtLaunchKernelGGL(kern, dim3(gA32()), dim3(kBlock), 0, s, A->events[2 * n_timed],
                                       A->events[2 * n_timed + 1], 0, d, (const float *)w.vals32,
-                                      (const float *)w.p32, w.q32, w.st, w.partf, e);
+                                      (const float *)w.p32, w.q32, w.st, w.partf, e, kq16);
                 timed_k[n_timed++] = e;
             } else {
                 hipLaunchKernelGGL(kern, dim3(gA32()), dim3(kBlock), 0, s, d, (const float *)w.vals32,
-                                   (const float *)w.p32, w.q32, w.st, w.partf, e);
+                                   (const float *)w.p32, w.q32, w.st, w.partf, e, kq16);
             }
         }
         const unsigned gx = gxr();

@@ -1,7 +1,8 @@
 """The load policy of the matrix streams (cache-allocating or non-temporal
-loads, chosen from the matrix bytes against spcg_keep_bytes) changes only the
-memory instructions: every product and solve must be bitwise identical under
-both policies."""
+loads, chosen from the matrix bytes against spcg_keep_bytes, and for a solve
+whose matrix is above the limit a share of its row blocks kept all the same)
+changes only the memory instructions: every product and solve must be bitwise
+identical under every limit."""
 import numpy as np
 import pytest
 import torch
@@ -11,7 +12,10 @@ from gpu_util import lower_upper, spcg, to_dev
 
 pytestmark = pytest.mark.gpu
 
-BOTH = (0, 1 << 40)  # always non-temporal, always cache-allocating
+# always non-temporal; partial keeps for the 24^3 test system (400 kB: 6/16 of
+# the mixed form's compact FP32 copy, none of the FP64 matrix; 700 kB: 5/16 of
+# the FP64 matrix, all of the compact copy); always cache-allocating
+LIMITS = (0, 400_000, 700_000, 1 << 40)
 
 
 @pytest.fixture(autouse=True)
@@ -25,7 +29,7 @@ def restore_policy():
 def under_both(f):
     S = spcg()
     out = []
-    for lim in BOTH:
+    for lim in LIMITS:
         S.keep_bytes(lim)
         out.append(f())
         torch.cuda.synchronize()
@@ -41,7 +45,7 @@ def test_spmv_bitwise_under_both_policies(dtype):
         H = S.CsrMatrix.from_host(M, dtype=dtype)
         xt = to_dev(I.uniform_vector(M.n_cols, 5), dtype)
         ys = under_both(lambda: S.spmv_csr(H, xt).cpu().numpy())
-        assert np.array_equal(ys[0], ys[1])
+        assert all(np.array_equal(ys[0], y) for y in ys[1:])
 
 
 @pytest.mark.parametrize("form", ["jacobi", "none", "mixed", "single_reduction", "learned"])
@@ -66,6 +70,8 @@ def test_cg_bitwise_under_both_policies(form):
     else:
         kw.update(precond=form)
     rs = under_both(lambda: S.cg_solve(M, b, **kw))
-    assert rs[0]["status"] == 0 and rs[0]["iters"] == rs[1]["iters"]
-    assert np.array_equal(rs[0]["x"].cpu().numpy(), rs[1]["x"].cpu().numpy())
-    assert np.array_equal(rs[0]["hist"], rs[1]["hist"])
+    assert rs[0]["status"] == 0
+    for r in rs[1:]:
+        assert r["iters"] == rs[0]["iters"]
+        assert np.array_equal(r["x"].cpu().numpy(), rs[0]["x"].cpu().numpy())
+        assert np.array_equal(r["hist"], rs[0]["hist"])
