@@ -1030,16 +1030,19 @@ k_sr_vec(int n, int expect, double *__restrict__ x, double *__restrict__ r, doub
     if (st->halt != RUN || st->k != expect) return;
     const double alpha = st->alpha, beta = st->beta;
     const int base = blockIdx.x * kVecBlock + threadIdx.x;
+    // p, s and x are next read by this kernel in the following pass: their
+    // accesses are non-temporal so they do not displace A, u, r and w from
+    // the memory-side cache
 #pragma unroll
     for (int v = 0; v < kVecPer; ++v) {
         const int i = base + v * kBlock;
         if (i < n) {
-            const double pi = u[i] + beta * p[i];
-            const double si = w[i] + beta * s[i];
-            x[i] += alpha * pi;
+            const double pi = u[i] + beta * __builtin_nontemporal_load(p + i);
+            const double si = w[i] + beta * __builtin_nontemporal_load(s + i);
+            __builtin_nontemporal_store(__builtin_nontemporal_load(x + i) + alpha * pi, x + i);
             const double ri = r[i] - alpha * si;
-            p[i] = pi;
-            s[i] = si;
+            __builtin_nontemporal_store(pi, p + i);
+            __builtin_nontemporal_store(si, s + i);
             r[i] = ri;
             u[i] = PRE == SPCG_PRECOND_JACOBI ? dinv[i] * ri : ri;
         }
