@@ -90,12 +90,12 @@ constexpr int kSlab = kChunk + kSlabExtra;  // LDS products per row block (longe
 // Span of the second ("wide") partition that every handle keeps for the
 // products with FP32 values and sums (the standalone product of an FP32
 // handle, the mixed-precision solve's inner product, the network's loss
-// products): their LDS (slab of
-// floats and row pointers, 17.4 KB) still leaves room for 8 workgroups per
-// CU, and a block carries a third more entries through the same chain of
-// dependent loads (128^3 FP32 product 29.9 -> 28.9 us, a 2^20-row band of
-// width 63 120.5 -> 106 us).  Every other kernel, including those that read
-// FP32 values with FP64 sums, uses kChunk.
+// products): their LDS (slab of floats and row pointers, 17.4 KB) still
+// leaves room for 8 workgroups per CU, and a block carries a third more
+// entries through the same chain of dependent loads (128^3 FP32 product
+// 29.9 -> 28.9 us, a 2^20-row band of width 63 120.5 -> 106 us).  Every
+// other kernel, including those that read FP32 values with FP64 sums, uses
+// kChunk.
 constexpr int kChunkWide = 2048;
 constexpr int kMaxGrid = 32768;          // workgroups of a row-block kernel (each walks a range)
 
@@ -531,8 +531,9 @@ __device__ __forceinline__ void spmv_block(const CsrDev &A, const TV *__restrict
     // (kend < k0 never holds; testing it keeps the compiler from sinking the
     // entry descriptors' load below this exit into a second round trip)
     if (r0 >= r1 || kend < k0) return;  // uniform over the workgroup
-    // a block whose entries overflow the slab ends in a long row (every other
-    // row of a block has fewer than kChunk entries); that row is reduced below
+    // a block whose entries overflow the slab ends in a long row (the rows
+    // before a block's last one hold fewer than CH entries in all); that row
+    // is reduced below
     const bool long_last = (kend - k0) > kSl;
     const int cnt = min(kend - k0, kSl);
     const int nr = r1 - r0;
