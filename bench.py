@@ -210,7 +210,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
-              "(how it would shard is described in DESIGN.md)", file=sys.stderr)
+              "(it would shard by rows, with a halo exchange per product and one "
+              "small all-reduce per reduction)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
