@@ -1603,13 +1603,14 @@ struct Solver {
         // Above the limit, the product of the standard and mixed loops keeps
         // the share of A that fits beside the vectors the pass reads with
         // cache-allocating loads (p, r and D^-1: 24 bytes per row in FP64,
-        // 12 in FP32): at 160^3 (358 MB of FP64 A) 5/16 of the blocks,
+        // 12 in FP32), in sixteenths rounded to nearest: at 160^3 (358 MB of
+        // FP64 A, 4.6 sixteenths) 5/16 of the blocks,
         // Jacobi-PCG 107.5 -> 100.2 ms, where keeping all of A thrashes the
         // cache (114.4 -> 118.8 ms when that was measured)
         kq16 = 0;
         if (!keep && o->precond != SPCG_PRECOND_LEARNED && !single_reduction() && a > 0) {
             const int64_t vec = (int64_t)A->n_rows * (mixed ? 12 : 24);
-            if (lim > vec) kq16 = (int)std::min<int64_t>(15, 16 * (lim - vec) / a);
+            if (lim > vec) kq16 = (int)std::min<int64_t>(15, (32 * (lim - vec) / a + 1) / 2);  // nearest
         }
     }
     int n_timed = 0;
