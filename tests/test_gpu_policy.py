@@ -13,7 +13,7 @@ from gpu_util import lower_upper, spcg, to_dev
 pytestmark = pytest.mark.gpu
 
 # always non-temporal; partial keeps for the 24^3 test system (400 kB: 6/16 of
-# the mixed form's compact FP32 copy, none of the FP64 matrix; 700 kB: 5/16 of
+# the mixed form's compact FP32 copy, 1/16 of the FP64 matrix; 700 kB: 5/16 of
 # the FP64 matrix, all of the compact copy); always cache-allocating
 LIMITS = (0, 400_000, 700_000, 1 << 40)
 
