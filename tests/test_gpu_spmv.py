@@ -88,17 +88,21 @@ def _edge_shapes(S):
     # n = 1
     A = I.CSR(1, 1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([2.5]))
     assert run(A, np.array([4.0]))[0][0] == 10.0
-    # every row empty (nnz = 0)
+    # every row empty (nnz = 0), in both precisions (one wide block per 2048 rows)
     E = I.CSR(300, 7, np.zeros(301, np.int32), np.zeros(0, np.int32), np.zeros(0))
-    y, M = run(E, np.ones(7))
-    assert np.array_equal(y, np.zeros(300))
-    # empty matrix
-    Z = S.CsrMatrix(torch.zeros(1, dtype=torch.int32, device="cuda"),
-                    torch.zeros(0, dtype=torch.int32, device="cuda"),
-                    torch.zeros(0, dtype=torch.float64, device="cuda"))
-    y = S.spmv_csr(Z, torch.zeros(0, dtype=torch.float64, device="cuda"))
-    torch.cuda.synchronize()
-    assert y.numel() == 0
+    for dt in (torch.float64, torch.float32):
+        y, M = run(E, np.ones(7), dt)
+        assert np.array_equal(y, np.zeros(300))
+        assert M.info()["n_wide_blocks"] == 1
+    # empty matrix: no row blocks in either partition
+    for dt in (torch.float64, torch.float32):
+        Z = S.CsrMatrix(torch.zeros(1, dtype=torch.int32, device="cuda"),
+                        torch.zeros(0, dtype=torch.int32, device="cuda"),
+                        torch.zeros(0, dtype=dt, device="cuda"))
+        y = S.spmv_csr(Z, torch.zeros(0, dtype=dt, device="cuda"))
+        torch.cuda.synchronize()
+        assert y.numel() == 0
+        assert Z.info()["n_blocks"] == 0 and Z.info()["n_wide_blocks"] == 0
     # a single very long row and many tiny ones
     A, x = I.random_csr_small(50, 20000, 3, max_len=3, long_rows=[(49, 20000), (0, 12000)])
     y, M = run(A, x)
